@@ -1,0 +1,349 @@
+/*
+ * vr.h -- C ABI of libvr: bricked GPU ray casting of a scalar spectral cube
+ * with sort-last "over" compositing, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hassan, Fluke & Barnes, "Interactive Visualization of the Largest
+ * Radioastronomy Cubes" (arXiv:1008.0135).  The renderer casts one ray per
+ * pixel through a float32 cube (Sec. 2), tests each ray against the box of
+ * the data portion, samples it between entry and exit with a fixed step,
+ * maps every sample through a transfer function to colour and opacity,
+ * accumulates front to back and stops early once opacity reaches a threshold
+ * (Sec. 2.4).  The cube is split into sub-volumes ("bricks", Sec. 2.3), each
+ * rendered into its own rendering rectangle (Sec. 2.4), and the brick images
+ * are combined in depth order with the over operator (Sec. 2.5).
+ *
+ * Conventions (all entry points):
+ *  - Every function returns an int status: VR_OK (0) or a negative VR_E*
+ *    code.  vr_last_error() returns a thread-local description of the most
+ *    recent failure on the calling thread.  No C++ exception crosses the ABI.
+ *  - Output handles (vr_ctx**, vr_volume**, ...) are written only on success.
+ *    Every *_destroy(NULL) is a no-op returning VR_OK.
+ *  - `stream` is a hipStream_t passed as uintptr_t (0 = the null stream).
+ *    GPU work is enqueued asynchronously on it; functions that must read a
+ *    GPU result on the host (noted below) synchronise that stream.
+ *  - The library owns contexts, volumes (unless wrapped), brick storage,
+ *    saved forward state, batch caches and internal scratch.  The caller owns
+ *    every output buffer and every wrapped input; pointers documented as
+ *    "device" must be device (HBM) allocations on the context's device.
+ *  - Volumes are C-ordered [n3][n2][n1] float32 arrays (axis 1 fastest, axis 3
+ *    spectral; FITS axis order).  Images are [H][W][4] float32, RGBA with
+ *    premultiplied colour, row 0 = most negative image y, background (0,0,0,0).
+ *  - Coordinates are in voxel units with voxel centres at integers; the
+ *    volume's domain box is [0,n1-1] x [0,n2-1] x [0,n3-1].
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+enum {
+  VR_OK = 0,
+  VR_EINVAL = -1,       /* invalid argument (NULL where required, bad size, bad range) */
+  VR_ENOMEM = -2,       /* device or host allocation failed */
+  VR_EHIP = -3,         /* a HIP runtime call failed (message names it) */
+  VR_ENONFINITE = -4,   /* the cube holds NaN or Inf voxels */
+  VR_ESTATE = -5,       /* call out of order, or saved state does not match */
+  VR_EUNSUPPORTED = -6  /* valid request this build does not implement */
+};
+
+/* Description of the last failure on this thread ("" if none). */
+const char *vr_last_error(void);
+
+/* Library ABI version (increments when a struct or signature changes). */
+int vr_version(void);
+
+/* ------------------------------------------------------------------ types */
+typedef struct vr_ctx vr_ctx;
+typedef struct vr_volume vr_volume;
+typedef struct vr_state vr_state;
+typedef struct vr_batch vr_batch;
+
+/*
+ * Render request view (paper Sec. 2.2: a render request carries the
+ * transformation and projection; this build uses an orthographic projection).
+ * Rows of R are the view axes in volume coordinates: e1 = R[0..2] (image x),
+ * e2 = R[3..5] (image y), e3 = R[6..8] (ray direction).  Pixel (u,v) has
+ * x = ((u+1/2)/W - 1/2) S and y = ((v+1/2)/H - 1/2) S H/W; its ray starts at
+ * c + x e1 + y e2 - S e3 (c = box centre) and runs along e3.  R = identity
+ * looks along +axis 3 with image x = axis 1 and image y = axis 2.
+ */
+typedef struct {
+  double R[9];   /* row-major rotation (orthonormal rows expected, not enforced) */
+  int32_t W, H;  /* image size in pixels, each in [1, 16384] */
+  double extent; /* S: image width in voxels; <= 0 selects the box diagonal */
+} vr_view;
+
+enum { VR_ERT_LOCAL = 0 };   /* opacity threshold tested per brick (sort-last, Sec. 2.3/2.5) */
+enum { VR_MODE_DVR = 0 };    /* emission-absorption with the over operator */
+
+/* Per-render parameters (paper Sec. 2.4: sampling distance, early termination). */
+typedef struct {
+  double step;       /* sample spacing along the ray in voxels, > 0 (0.5 typical) */
+  double tau;        /* stop a ray after the sample where 1 - T >= tau; tau >= 1 disables */
+  int32_t ess;       /* 1: skip bricks whose transfer-function opacity is 0 over their range */
+  int32_t ert_scope; /* VR_ERT_LOCAL */
+  int32_t mode;      /* VR_MODE_DVR */
+  int32_t ckpt_K;    /* adjoint: transmittance checkpoint interval in samples (>= 1; 32 typical) */
+  int32_t tile;      /* pixel tile edge of one wavefront: 0 = autotuned/default (8) */
+  int32_t reserved;
+} vr_params;
+
+/* Fill *p with the defaults: step 0.5, tau 0.99, ess 1, LOCAL, DVR, K 32, tile 0. */
+void vr_params_default(vr_params *p);
+
+/* ------------------------------------------------------------------ context */
+/*
+ * Create a context on HIP device `device` (>= 0): a transfer-function slot,
+ * scratch arenas, a table-upload ring and the autotune cache.
+ * Errors: VR_EINVAL (out NULL), VR_EHIP (no such device / HIP failure).
+ */
+int vr_create(int device, vr_ctx **out);
+int vr_destroy(vr_ctx *ctx);
+
+/* 1: record per-stage GPU times of later calls (see vr_stage_times); 0: off. */
+int vr_set_profiling(vr_ctx *ctx, int on);
+
+enum { VR_STAGE_SETUP = 0, VR_STAGE_MARCH = 1, VR_STAGE_COMPOSITE = 2, VR_STAGE_BACKWARD = 3,
+       VR_STAGE_BATCH = 4, VR_NSTAGES = 5 };
+/*
+ * Per-stage GPU time (ms, summed over the stage's launches) of the most
+ * recent profiled call, plus its launch count.  Synchronises the stream of
+ * that call.  ms and launches are arrays of VR_NSTAGES (either may be NULL).
+ */
+int vr_stage_times(vr_ctx *ctx, double *ms, int32_t *launches);
+
+/* ------------------------------------------------------------------ volumes */
+/*
+ * Upload a cube or a sub-cube (paper Sec. 2.2: the user loads the entire cube
+ * or a selected sub-cube; min and max come from metadata or are recomputed
+ * by the GPUs).  `src` is a [n3][n2][n1] float32 array on the host
+ * (src_on_device = 0, pageable or pinned) or on the device (1).  If
+ * sub_origin/sub_extent are non-NULL the volume is the box
+ * [origin, origin+extent) of the source (each extent >= 2).  The data are
+ * copied into library storage, scanned for non-finite values and reduced to
+ * the global (min, max).  Synchronises `stream`.
+ * Errors: VR_EINVAL (NULL, a dimension < 2, a sub-cube outside the source),
+ * VR_ENOMEM, VR_ENONFINITE (NaN or Inf anywhere in the volume), VR_EHIP.
+ */
+int vr_volume_create(vr_ctx *ctx, const float *src, int src_on_device, int64_t n1, int64_t n2,
+                     int64_t n3, const int64_t *sub_origin, const int64_t *sub_extent,
+                     uintptr_t stream, vr_volume **out);
+
+/*
+ * Borrow a device array [n3][n2][n1] without copying (the differentiable
+ * path: the caller's tensor is read directly).  The caller keeps it alive
+ * and unchanged while the volume is used.  The range is computed on demand
+ * (vr_volume_minmax); no non-finite scan is made.
+ * Errors: VR_EINVAL, VR_EHIP.
+ */
+int vr_volume_wrap(vr_ctx *ctx, float *dev_ptr, int64_t n1, int64_t n2, int64_t n3, uintptr_t stream,
+                   vr_volume **out);
+int vr_volume_destroy(vr_volume *vol);
+
+/* Global (min, max) over all voxels (paper Sec. 2.2).  Synchronises. */
+int vr_volume_minmax(vr_volume *vol, float *vmin, float *vmax);
+
+/* Dimensions of the volume (n[0] = n1, n[1] = n2, n[2] = n3). */
+int vr_volume_dims(const vr_volume *vol, int64_t n[3]);
+
+/* Sub-volume partitioning (paper Sec. 2.3). */
+enum { VR_BRICK_GRID = 0, VR_BRICK_LONGEST_AXIS = 1 };
+typedef struct {
+  int32_t mode;        /* VR_BRICK_GRID or VR_BRICK_LONGEST_AXIS */
+  int32_t nparts;      /* LONGEST_AXIS: number of sub-volumes, in [1, 4096] */
+  int64_t size[3];     /* GRID: brick edge in cells per axis, each >= 1 */
+  int32_t ghost;       /* ghost layer width: must be 1 */
+  int32_t macrocell;   /* reserved, must be 0 */
+  int32_t materialize; /* 1: copy each brick and its ghost layer into its own storage */
+  int32_t reserved;
+} vr_brick_spec;
+
+/*
+ * Partition the volume into bricks.  GRID: brick j along an axis owns
+ * [j*size, (j+1)*size), the last is closed at n-1 (count = ceil((n-1)/size)).
+ * LONGEST_AXIS: recursive split of the longest extent (first axis on ties)
+ * into floor(p/2) and p - floor(p/2) parts at the integer plane nearest the
+ * proportional position (paper Sec. 2.3, equal weights).  Computes per-brick
+ * (min, max) over each brick's stored voxels (ownership box plus a 1-voxel
+ * ghost layer, clipped to the volume) and, with materialize = 1, copies the
+ * bricks.  Re-bricking replaces the previous partition.  Synchronises.
+ * Errors: VR_EINVAL (spec NULL, size < 1, nparts out of range, ghost != 1,
+ * macrocell != 0, more than 65536 bricks), VR_ENOMEM, VR_EHIP.
+ */
+int vr_volume_brick(vr_volume *vol, const vr_brick_spec *spec, uintptr_t stream);
+
+typedef struct {
+  int64_t lo[3], hi[3];   /* ownership box: [lo, hi) per axis, [lo, hi] where closed */
+  int32_t closed[3];
+  int32_t reserved;
+  int64_t slo[3], shi[3]; /* stored voxel range, inclusive (ghost included) */
+  float vmin, vmax;       /* range over the stored voxels */
+} vr_brick_desc;
+
+/*
+ * Number of bricks (*nb; 0 when not bricked) and, if out is non-NULL, their
+ * descriptions (out must hold *nb entries on input when non-NULL: pass the
+ * capacity in *nb).  Errors: VR_EINVAL (NULL nb, capacity too small).
+ */
+int vr_volume_brick_info(const vr_volume *vol, int32_t *nb, vr_brick_desc *out);
+
+/* ------------------------------------------------------------------ transfer function */
+/*
+ * Set the context's colour map (paper Sec. 2.2: generated once the global
+ * range is known, sent to the renderers, and changed interactively).  `rgba`
+ * is [m][4] float32 non-premultiplied, every value in [0,1], m in [2, 4096]; on the host
+ * (src_on_device = 0, copied before return) or the device (1, copied on
+ * `stream`; values are validated on the host and the copy synchronises).
+ * The normalisation window maps v to s = clamp((v - vmin)/(vmax - vmin), 0, 1)
+ * (s = 0 when vmax == vmin); vmin = vmax = 0 selects each volume's global range.
+ * Lookup: u = s (m-1), i = min(floor(u), m-2), linear between entries i, i+1.
+ * Errors: VR_EINVAL (m < 2 or > 4096, a value outside [0,1] or non-finite,
+ * vmax < vmin, non-finite window), VR_EHIP.
+ */
+int vr_tf_set(vr_ctx *ctx, const float *rgba, int32_t m, double vmin, double vmax, int src_on_device,
+              uintptr_t stream);
+
+/* ------------------------------------------------------------------ rendering */
+/*
+ * Render `nviews` views into out ([nviews][H][W][4] float32, device; all views
+ * must share W and H).  Unbricked volume: one accumulation chain per ray
+ * through the whole volume (at most 2^31 - 1 voxels).  Bricked volume: every
+ * non-culled brick is rendered into its rendering rectangle with its own
+ * accumulation and local early termination, then the brick images are
+ * over-composited in depth order (paper Sec. 2.4, 2.5).  Sample lattice per
+ * ray: t_k = t_in + (k + 1/2) step while t_k < t_out, anchored at the entry
+ * into the whole volume; a sample belongs to the brick whose ownership box
+ * holds it.  If save is non-NULL (unbricked volumes only), forward state for
+ * vr_render_backward is kept and returned (library-owned; free it with
+ * vr_state_destroy).
+ * Errors: VR_EINVAL (NULL, nviews < 1, W/H out of range or differing, bad
+ * params), VR_ESTATE (no transfer function set), VR_EUNSUPPORTED (save with a
+ * bricked volume; an unbricked volume of 2^31 voxels or more), VR_ENOMEM, VR_EHIP.
+ */
+int vr_render(vr_ctx *ctx, const vr_volume *vol, const vr_view *views, int32_t nviews,
+              const vr_params *p, float *out, uintptr_t stream, vr_state **save);
+
+/* One brick image: rectangle [x0, x0+w) x [y0, y0+h) of the frame, premultiplied RGBA. */
+typedef struct {
+  int32_t brick, x0, y0, w, h, reserved;
+  float *rgba; /* device, [h][w][4]; library arena memory (vr_render_bricks) or caller's */
+} vr_brick_image;
+
+/*
+ * Sort-last first half: render the bricks of a bricked volume for one view
+ * (paper Sec. 2.4: each renderer fills its rendering rectangle).  On input
+ * *nimg is the capacity of imgs and order; on output the number of images.
+ * order receives the front-to-back order as indices into imgs.  Image memory
+ * is library arena storage valid until the next render call on this context.
+ * Errors: VR_EINVAL, VR_ESTATE (not bricked, no transfer function), VR_ENOMEM, VR_EHIP.
+ */
+int vr_render_bricks(vr_ctx *ctx, const vr_volume *vol, const vr_view *view, const vr_params *p,
+                     vr_brick_image *imgs, int32_t *nimg, int32_t *order, uintptr_t stream);
+
+/*
+ * Sort-last second half: over-composite n brick images front to back into out
+ * ([H][W][4] float32, device, fully written) (paper Sec. 2.5).  order lists
+ * indices into imgs, front first (NULL: array order).
+ * Errors: VR_EINVAL (a rectangle outside W x H, an index out of range), VR_EHIP.
+ */
+int vr_composite(vr_ctx *ctx, const vr_brick_image *imgs, int32_t n, const int32_t *order, int32_t W,
+                 int32_t H, float *out, uintptr_t stream);
+
+/* ------------------------------------------------------------------ adjoint */
+/*
+ * Gradient of sum(grad_out * image) with respect to the transfer-function
+ * table and the voxel values, for the views of a vr_render call made with
+ * save.  grad_out: [nviews][H][W][4] float32 device.  grad_tf: [m][4] float32
+ * device.  grad_vol: [n3][n2][n1] float32 device or NULL.  accumulate = 0
+ * overwrites the outputs, 1 adds to them.  The normalisation window is a
+ * constant.  Each ray is walked back to front from its saved final colour and
+ * transmittance, recomputing each segment of ckpt_K samples forward from its
+ * saved transmittance checkpoint.
+ * Errors: VR_EINVAL, VR_ESTATE (state from another volume, or the transfer
+ * function changed since the forward), VR_EHIP.
+ */
+int vr_render_backward(vr_ctx *ctx, const vr_volume *vol, const vr_state *st, const float *grad_out,
+                       float *grad_tf, float *grad_vol, int accumulate, uintptr_t stream);
+int vr_state_destroy(vr_state *st);
+
+/* ------------------------------------------------------------------ batched */
+/* One request of a batch: its own volume (unbricked), view, table, window and output. */
+typedef struct {
+  const vr_volume *vol;
+  vr_view view;
+  const float *tf; /* device [m][4], values in [0,1] */
+  int32_t m;
+  int32_t reserved;
+  double vmin, vmax; /* window; vmin = vmax = 0 selects the volume's range */
+  float *out;        /* device [view.H][view.W][4] */
+} vr_request;
+
+/*
+ * Render n requests in one persistent launch: (request, pixel tile) work
+ * items, ordered by estimated cost, are pulled from an atomic counter by a
+ * grid sized to the device.  The launch sequence is captured once into a HIP
+ * graph held in *cache (created when *cache is NULL) and replayed while the
+ * request shapes (count, volumes, image sizes, table sizes) match; otherwise
+ * it is rebuilt.  Table values, views, windows and output pointers may change
+ * between calls.  Errors: VR_EINVAL, VR_ENOMEM, VR_EHIP.
+ */
+int vr_render_batch(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_params *p, vr_batch **cache,
+                    uintptr_t stream);
+int vr_batch_destroy(vr_batch *b);
+
+/* ------------------------------------------------------------------ autotuning */
+typedef struct {
+  int32_t tile;          /* chosen wavefront tile edge (pixels) */
+  int32_t waves_per_cu;  /* chosen persistent-grid occupancy (batched path) */
+  double ms;             /* best measured time */
+  double ms_default;     /* time with the defaults */
+} vr_tune_result;
+
+/*
+ * Time candidate tile shapes for rendering `view` of `vol` (and persistent
+ * grid sizes for the batched path) and store the fastest in the context's
+ * cache, keyed by volume size class and image size; later renders with
+ * p->tile = 0 use it.  The cache is also written to the file named by the
+ * environment variable VR_TUNE_CACHE when set.  Synchronises.
+ * Errors: VR_EINVAL, VR_ESTATE (no transfer function), VR_EHIP.
+ */
+int vr_autotune(vr_ctx *ctx, const vr_volume *vol, const vr_view *view, const vr_params *p,
+                vr_tune_result *out, uintptr_t stream);
+
+/* ------------------------------------------------------------------ host-only helpers */
+/*
+ * Rendering rectangles and depth order for a brick partition of a volume of
+ * size dims and one view (paper Sec. 2.4: the rectangle bounds the projection
+ * of the brick; it never changes the image).  No GPU use.  rects: [nb][4]
+ * (x0, y0, w, h; w = 0 for an empty rectangle), order: [nb] brick indices
+ * front to back.  *nb is the capacity on input, the brick count on output.
+ * Errors: VR_EINVAL.
+ */
+int vr_plan_view(const int64_t dims[3], const vr_brick_spec *spec, const vr_view *view, int32_t *nb,
+                 int32_t *rects, int32_t *order);
+
+/*
+ * The partition vr_volume_brick would make for a volume of size dims, without
+ * a GPU: ownership boxes and stored (ghost) ranges; vmin/vmax are left 0.
+ * *nb is the capacity of out on input (out may be NULL to query the count),
+ * the brick count on output.  Errors: VR_EINVAL.
+ */
+int vr_partition(const int64_t dims[3], const vr_brick_spec *spec, int32_t *nb, vr_brick_desc *out);
+
+/*
+ * Nominal sample count of a view: the sum over pixel rays of the lattice
+ * count inside the whole-volume box (no early termination, no skipping).
+ * No GPU use.  Errors: VR_EINVAL.
+ */
+int vr_count_samples(const int64_t dims[3], const vr_view *view, double step, int64_t *nominal);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

@@ -1,0 +1,358 @@
+"""Python binding of libvr: bricked ray casting + sort-last compositing on MI355X.
+
+Thin ctypes marshalling over the C ABI declared in ``include/vr.h`` (same
+function names).  Every step of the rendering path runs in the HIP kernels of
+``lib/libvr.so``; there is no CPU fallback: if the library is missing the
+import of the binding fails loudly.  PyTorch supplies device memory (tensors)
+and streams only.
+
+Method: Hassan, Fluke & Barnes, "Interactive Visualization of the Largest
+Radioastronomy Cubes" (arXiv:1008.0135), Sec. 2 (ray casting), Sec. 2.3
+(object-space partitioning), Sec. 2.4 (ray-casting process), Sec. 2.5 (image
+composition).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libvr.so")
+
+VR_OK = 0
+VR_EINVAL = -1
+VR_ENOMEM = -2
+VR_EHIP = -3
+VR_ENONFINITE = -4
+VR_ESTATE = -5
+VR_EUNSUPPORTED = -6
+_NAMES = {0: "VR_OK", -1: "VR_EINVAL", -2: "VR_ENOMEM", -3: "VR_EHIP", -4: "VR_ENONFINITE",
+          -5: "VR_ESTATE", -6: "VR_EUNSUPPORTED"}
+
+VR_BRICK_GRID = 0
+VR_BRICK_LONGEST_AXIS = 1
+VR_STAGE_SETUP, VR_STAGE_MARCH, VR_STAGE_COMPOSITE, VR_STAGE_BACKWARD, VR_STAGE_BATCH = range(5)
+VR_NSTAGES = 5
+
+
+class VRError(RuntimeError):
+    def __init__(self, code, func, msg):
+        super().__init__(f"{func}: {_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class vr_view(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("W", C.c_int32), ("H", C.c_int32), ("extent", C.c_double)]
+
+
+class vr_params(C.Structure):
+    _fields_ = [("step", C.c_double), ("tau", C.c_double), ("ess", C.c_int32), ("ert_scope", C.c_int32),
+                ("mode", C.c_int32), ("ckpt_K", C.c_int32), ("tile", C.c_int32), ("reserved", C.c_int32)]
+
+
+class vr_brick_spec(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("nparts", C.c_int32), ("size", C.c_int64 * 3), ("ghost", C.c_int32),
+                ("macrocell", C.c_int32), ("materialize", C.c_int32), ("reserved", C.c_int32)]
+
+
+class vr_brick_desc(C.Structure):
+    _fields_ = [("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3), ("closed", C.c_int32 * 3), ("reserved", C.c_int32),
+                ("slo", C.c_int64 * 3), ("shi", C.c_int64 * 3), ("vmin", C.c_float), ("vmax", C.c_float)]
+
+
+class vr_brick_image(C.Structure):
+    _fields_ = [("brick", C.c_int32), ("x0", C.c_int32), ("y0", C.c_int32), ("w", C.c_int32), ("h", C.c_int32),
+                ("reserved", C.c_int32), ("rgba", C.c_void_p)]
+
+
+class vr_request(C.Structure):
+    _fields_ = [("vol", C.c_void_p), ("view", vr_view), ("tf", C.c_void_p), ("m", C.c_int32),
+                ("reserved", C.c_int32), ("vmin", C.c_double), ("vmax", C.c_double), ("out", C.c_void_p)]
+
+
+class vr_tune_result(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("waves_per_cu", C.c_int32), ("ms", C.c_double), ("ms_default", C.c_double)]
+
+
+_P = C.c_void_p
+_I = C.c_int
+_I32 = C.c_int32
+_I64 = C.c_int64
+_D = C.c_double
+_U = C.c_uint64  # uintptr_t stream
+
+_SIGS = {
+    "vr_last_error": (C.c_char_p, []),
+    "vr_version": (_I, []),
+    "vr_params_default": (None, [_P]),
+    "vr_create": (_I, [_I, _P]),
+    "vr_destroy": (_I, [_P]),
+    "vr_set_profiling": (_I, [_P, _I]),
+    "vr_stage_times": (_I, [_P, _P, _P]),
+    "vr_volume_create": (_I, [_P, _P, _I, _I64, _I64, _I64, _P, _P, _U, _P]),
+    "vr_volume_wrap": (_I, [_P, _P, _I64, _I64, _I64, _U, _P]),
+    "vr_volume_destroy": (_I, [_P]),
+    "vr_volume_minmax": (_I, [_P, _P, _P]),
+    "vr_volume_dims": (_I, [_P, _P]),
+    "vr_volume_brick": (_I, [_P, _P, _U]),
+    "vr_volume_brick_info": (_I, [_P, _P, _P]),
+    "vr_tf_set": (_I, [_P, _P, _I32, _D, _D, _I, _U]),
+    "vr_render": (_I, [_P, _P, _P, _I32, _P, _P, _U, _P]),
+    "vr_render_bricks": (_I, [_P, _P, _P, _P, _P, _P, _P, _U]),
+    "vr_composite": (_I, [_P, _P, _I32, _P, _I32, _I32, _P, _U]),
+    "vr_render_backward": (_I, [_P, _P, _P, _P, _P, _P, _I, _U]),
+    "vr_state_destroy": (_I, [_P]),
+    "vr_render_batch": (_I, [_P, _P, _I32, _P, _P, _U]),
+    "vr_batch_destroy": (_I, [_P]),
+    "vr_autotune": (_I, [_P, _P, _P, _P, _P, _U]),
+    "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P]),
+    "vr_count_samples": (_I, [_P, _P, _D, _P]),
+    "vr_partition": (_I, [_P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load lib/libvr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libvr.so not found at {LIB_PATH}: build it with "
+                "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(rc, func):
+    if rc != VR_OK:
+        msg = lib().vr_last_error()
+        raise VRError(rc, func, msg.decode() if msg else "")
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return int(stream.cuda_stream)
+    return int(stream)
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor / numpy array / int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    if hasattr(t, "ctypes"):
+        return t.ctypes.data
+    raise TypeError(type(t))
+
+
+def make_view(R, W, H, extent=0.0) -> vr_view:
+    v = vr_view()
+    flat = [float(x) for row in R for x in row] if hasattr(R[0], "__len__") else [float(x) for x in R]
+    for i in range(9):
+        v.R[i] = flat[i]
+    v.W, v.H, v.extent = int(W), int(H), float(extent)
+    return v
+
+
+def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0) -> vr_params:
+    p = vr_params()
+    lib().vr_params_default(C.byref(p))
+    p.step, p.tau, p.ess, p.ckpt_K, p.tile = float(step), float(tau), int(ess), int(ckpt_K), int(tile)
+    return p
+
+
+def grid_spec(size, materialize=False) -> vr_brick_spec:
+    s = vr_brick_spec()
+    s.mode = VR_BRICK_GRID
+    for i in range(3):
+        s.size[i] = int(size[i])
+    s.ghost = 1
+    s.materialize = int(bool(materialize))
+    return s
+
+
+def kd_spec(nparts, materialize=False) -> vr_brick_spec:
+    s = vr_brick_spec()
+    s.mode = VR_BRICK_LONGEST_AXIS
+    s.nparts = int(nparts)
+    s.ghost = 1
+    s.materialize = int(bool(materialize))
+    return s
+
+
+# ------------------------------------------------------------------ C-ABI wrappers
+def vr_version():
+    return lib().vr_version()
+
+
+def vr_create(device=0):
+    h = C.c_void_p()
+    _check(lib().vr_create(int(device), C.byref(h)), "vr_create")
+    return h.value
+
+
+def vr_destroy(ctx):
+    _check(lib().vr_destroy(ctx), "vr_destroy")
+
+
+def vr_set_profiling(ctx, on=True):
+    _check(lib().vr_set_profiling(ctx, int(bool(on))), "vr_set_profiling")
+
+
+def vr_stage_times(ctx):
+    ms = (C.c_double * VR_NSTAGES)()
+    n = (C.c_int32 * VR_NSTAGES)()
+    _check(lib().vr_stage_times(ctx, ms, n), "vr_stage_times")
+    return list(ms), list(n)
+
+
+def vr_volume_create(ctx, src, dims, on_device=None, sub_origin=None, sub_extent=None, stream=None):
+    """Upload a [n3][n2][n1] float32 tensor/array (dims = (n1, n2, n3))."""
+    if on_device is None:
+        on_device = bool(getattr(src, "is_cuda", False))
+    h = C.c_void_p()
+    so = (C.c_int64 * 3)(*sub_origin) if sub_origin is not None else None
+    se = (C.c_int64 * 3)(*sub_extent) if sub_extent is not None else None
+    n1, n2, n3 = (int(d) for d in dims)
+    _check(lib().vr_volume_create(ctx, _ptr(src), int(on_device), n1, n2, n3, so, se, _stream(stream), C.byref(h)),
+           "vr_volume_create")
+    return h.value
+
+
+def vr_volume_wrap(ctx, dev_tensor, dims, stream=None):
+    h = C.c_void_p()
+    n1, n2, n3 = (int(d) for d in dims)
+    _check(lib().vr_volume_wrap(ctx, _ptr(dev_tensor), n1, n2, n3, _stream(stream), C.byref(h)), "vr_volume_wrap")
+    return h.value
+
+
+def vr_volume_destroy(vol):
+    _check(lib().vr_volume_destroy(vol), "vr_volume_destroy")
+
+
+def vr_volume_minmax(vol):
+    a, b = C.c_float(), C.c_float()
+    _check(lib().vr_volume_minmax(vol, C.byref(a), C.byref(b)), "vr_volume_minmax")
+    return a.value, b.value
+
+
+def vr_volume_dims(vol):
+    n = (C.c_int64 * 3)()
+    _check(lib().vr_volume_dims(vol, n), "vr_volume_dims")
+    return tuple(n)
+
+
+def vr_volume_brick(vol, spec, stream=None):
+    _check(lib().vr_volume_brick(vol, C.byref(spec), _stream(stream)), "vr_volume_brick")
+
+
+def vr_volume_brick_info(vol):
+    nb = C.c_int32(0)
+    _check(lib().vr_volume_brick_info(vol, C.byref(nb), None), "vr_volume_brick_info")
+    arr = (vr_brick_desc * max(1, nb.value))()
+    _check(lib().vr_volume_brick_info(vol, C.byref(nb), arr), "vr_volume_brick_info")
+    return [arr[i] for i in range(nb.value)]
+
+
+def vr_tf_set(ctx, tf, vmin=0.0, vmax=0.0, stream=None):
+    """tf: [m][4] float32 (numpy array on the host or a torch tensor on either side)."""
+    on_dev = bool(getattr(tf, "is_cuda", False))
+    m = int(tf.shape[0])
+    _check(lib().vr_tf_set(ctx, _ptr(tf), m, float(vmin), float(vmax), int(on_dev), _stream(stream)), "vr_tf_set")
+
+
+def vr_render(ctx, vol, views, params, out, stream=None, save=False):
+    """views: list of vr_view; out: device tensor [nv][H][W][4] float32.  Returns the state handle if save."""
+    arr = (vr_view * len(views))(*views)
+    st = C.c_void_p()
+    _check(lib().vr_render(ctx, vol, arr, len(views), C.byref(params), _ptr(out), _stream(stream),
+                           C.byref(st) if save else None), "vr_render")
+    return st.value if save else None
+
+
+def vr_render_bricks(ctx, vol, view, params, capacity=65536, stream=None):
+    """Returns (list of vr_brick_image, front-to-back order list)."""
+    imgs = (vr_brick_image * capacity)()
+    order = (C.c_int32 * capacity)()
+    n = C.c_int32(capacity)
+    _check(lib().vr_render_bricks(ctx, vol, C.byref(view), C.byref(params), imgs, C.byref(n), order,
+                                  _stream(stream)), "vr_render_bricks")
+    return [imgs[i] for i in range(n.value)], [order[i] for i in range(n.value)]
+
+
+def vr_composite(ctx, imgs, order, W, H, out, stream=None):
+    n = len(imgs)
+    arr = (vr_brick_image * max(1, n))(*imgs)
+    o = (C.c_int32 * max(1, n))(*order) if order is not None else None
+    _check(lib().vr_composite(ctx, arr, n, o, int(W), int(H), _ptr(out), _stream(stream)), "vr_composite")
+
+
+def vr_render_backward(ctx, vol, state, grad_out, grad_tf, grad_vol=None, accumulate=False, stream=None):
+    _check(lib().vr_render_backward(ctx, vol, state, _ptr(grad_out), _ptr(grad_tf), _ptr(grad_vol),
+                                    int(bool(accumulate)), _stream(stream)), "vr_render_backward")
+
+
+def vr_state_destroy(state):
+    _check(lib().vr_state_destroy(state), "vr_state_destroy")
+
+
+def vr_render_batch(ctx, reqs, params, cache=None, stream=None):
+    """reqs: list of vr_request.  Returns the (possibly new) cache handle."""
+    arr = (vr_request * len(reqs))(*reqs)
+    h = C.c_void_p(cache)
+    _check(lib().vr_render_batch(ctx, arr, len(reqs), C.byref(params), C.byref(h), _stream(stream)),
+           "vr_render_batch")
+    return h.value
+
+
+def vr_batch_destroy(b):
+    _check(lib().vr_batch_destroy(b), "vr_batch_destroy")
+
+
+def vr_autotune(ctx, vol, view, params, stream=None):
+    r = vr_tune_result()
+    _check(lib().vr_autotune(ctx, vol, C.byref(view), C.byref(params), C.byref(r), _stream(stream)), "vr_autotune")
+    return r
+
+
+def vr_plan_view(dims, spec, view, capacity=65536):
+    d = (C.c_int64 * 3)(*[int(x) for x in dims])
+    rects = (C.c_int32 * (4 * capacity))()
+    order = (C.c_int32 * capacity)()
+    nb = C.c_int32(capacity)
+    _check(lib().vr_plan_view(d, C.byref(spec), C.byref(view), C.byref(nb), rects, order), "vr_plan_view")
+    n = nb.value
+    return [tuple(rects[4 * i:4 * i + 4]) for i in range(n)], [order[i] for i in range(n)]
+
+
+def vr_partition(dims, spec):
+    d = (C.c_int64 * 3)(*[int(x) for x in dims])
+    nb = C.c_int32(0)
+    _check(lib().vr_partition(d, C.byref(spec), C.byref(nb), None), "vr_partition")
+    arr = (vr_brick_desc * max(1, nb.value))()
+    _check(lib().vr_partition(d, C.byref(spec), C.byref(nb), arr), "vr_partition")
+    return [arr[i] for i in range(nb.value)]
+
+
+def vr_count_samples(dims, view, step=0.5):
+    d = (C.c_int64 * 3)(*[int(x) for x in dims])
+    out = C.c_int64()
+    _check(lib().vr_count_samples(d, C.byref(view), float(step), C.byref(out)), "vr_count_samples")
+    return out.value

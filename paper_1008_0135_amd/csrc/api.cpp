@@ -1,0 +1,743 @@
+// api.cpp -- the extern "C" entry points of libvr (declared in include/vr.h):
+// argument validation, device memory ownership, per-view planning and the
+// launch sequence of the forward path.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+#include "runtime.h"
+#include "vr_internal.h"
+
+using namespace vr;
+
+namespace vr {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+void clear_error() { g_err.clear(); }
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  if (prev != dev) (void)hipSetDevice(dev);
+  target = dev;
+}
+DeviceGuard::~DeviceGuard() {
+  if (prev >= 0 && prev != target) (void)hipSetDevice(prev);
+}
+
+// ---------------------------------------------------------------- ctx helpers
+int ctx_begin(vr_ctx* ctx, hipStream_t s) {
+  if (ctx->done_valid) VR_HIP(hipStreamWaitEvent(s, ctx->done, 0));
+  if (ctx->prof) {
+    for (auto& t : ctx->timed) {
+      ctx->event_pool.push_back(t.a);
+      ctx->event_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    ctx->prof_stream = s;
+  }
+  return VR_OK;
+}
+
+int ctx_end(vr_ctx* ctx, hipStream_t s) {
+  VR_HIP(hipEventRecord(ctx->done, s));
+  ctx->done_valid = true;
+  return VR_OK;
+}
+
+static hipEvent_t pool_event(vr_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int stage_begin(vr_ctx* ctx, int stage, hipStream_t s) {
+  if (!ctx->prof) return VR_OK;
+  vr_ctx::Timed t{stage, pool_event(ctx), pool_event(ctx)};
+  if (!t.a || !t.b) return fail(VR_EHIP, "hipEventCreate failed");
+  VR_HIP(hipEventRecord(t.a, s));
+  ctx->timed.push_back(t);
+  return VR_OK;
+}
+
+int stage_end(vr_ctx* ctx, hipStream_t s) {
+  if (!ctx->prof) return VR_OK;
+  VR_HIP(hipEventRecord(ctx->timed.back().b, s));
+  return VR_OK;
+}
+
+int ensure_device(void** p, size_t* cap, size_t need) {
+  if (need <= *cap && *p) return VR_OK;
+  if (*p) {
+    hipError_t e = hipFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    if (e != hipSuccess) return fail(VR_EHIP, "hipFree: %s", hipGetErrorString(e));
+  }
+  size_t bytes = std::max<size_t>(need, 256);
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(VR_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  *cap = bytes;
+  return VR_OK;
+}
+
+int upload_tables(vr_ctx* ctx, hipStream_t s, const void* data, size_t bytes, void** dev) {
+  vr_ctx::Slot& sl = ctx->ring[ctx->ring_next];
+  ctx->ring_next = (ctx->ring_next + 1) % vr_ctx::kRing;
+  if (sl.used) VR_HIP(hipEventSynchronize(sl.copied));
+  if (bytes > sl.bytes || !sl.h || !sl.d) {
+    if (sl.h) VR_HIP(hipHostFree(sl.h));
+    if (sl.d) VR_HIP(hipFree(sl.d));
+    sl.h = sl.d = nullptr;
+    sl.bytes = 0;
+    size_t cap = std::max<size_t>(bytes, 4096);
+    cap = (cap + 4095) & ~(size_t)4095;
+    if (hipHostMalloc(&sl.h, cap, hipHostMallocDefault) != hipSuccess) {
+      sl.h = nullptr;
+      return fail(VR_ENOMEM, "hipHostMalloc(%zu) failed", cap);
+    }
+    if (hipMalloc(&sl.d, cap) != hipSuccess) {
+      sl.d = nullptr;
+      return fail(VR_ENOMEM, "hipMalloc(%zu) failed", cap);
+    }
+    sl.bytes = cap;
+  }
+  std::memcpy(sl.h, data, bytes);
+  VR_HIP(hipMemcpyAsync(sl.d, sl.h, bytes, hipMemcpyHostToDevice, s));
+  VR_HIP(hipEventRecord(sl.copied, s));
+  sl.used = true;
+  *dev = sl.d;
+  return VR_OK;
+}
+
+// Global (min, max, non-finite count) of n floats at x, read back to the host.
+int reduce_minmax(vr_ctx* ctx, const float* x, int64_t n, hipStream_t s, float out3[3]) {
+  int32_t nb = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(1, n / (256 * 16)));
+  VR_TRY(ensure_device(&ctx->d_small, &ctx->small_bytes, (size_t)nb * 16 + 64));
+  float* part = reinterpret_cast<float*>(ctx->d_small);
+  float* res = reinterpret_cast<float*>(reinterpret_cast<char*>(ctx->d_small) + (size_t)nb * 16);
+  VR_HIP(launch_minmax(x, n, part, nb, s));
+  VR_HIP(launch_minmax_final(part, nb, res, s));
+  VR_HIP(hipMemcpyAsync(out3, res, 3 * sizeof(float), hipMemcpyDeviceToHost, s));
+  VR_HIP(hipStreamSynchronize(s));
+  return VR_OK;
+}
+
+static bool finite_view(const vr_view& v) {
+  for (int i = 0; i < 9; i++)
+    if (!std::isfinite(v.R[i])) return false;
+  return std::isfinite(v.extent);
+}
+
+int check_view(const vr_view* v) {
+  if (!v) return fail(VR_EINVAL, "view is NULL");
+  if (v->W < 1 || v->H < 1 || v->W > 16384 || v->H > 16384)
+    return fail(VR_EINVAL, "image size %dx%d outside [1, 16384]", v->W, v->H);
+  if (!finite_view(*v)) return fail(VR_EINVAL, "view has non-finite entries");
+  double e3 = v->R[6] * v->R[6] + v->R[7] * v->R[7] + v->R[8] * v->R[8];
+  if (!(e3 > 0.0)) return fail(VR_EINVAL, "view direction (third row of R) is zero");
+  return VR_OK;
+}
+
+int check_params(const vr_params* p) {
+  if (!p) return fail(VR_EINVAL, "params is NULL");
+  if (!(p->step > 0.0) || !std::isfinite(p->step)) return fail(VR_EINVAL, "step must be > 0");
+  if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(VR_EINVAL, "tau must be > 0 (>= 1 disables)");
+  if (p->ert_scope != VR_ERT_LOCAL) return fail(VR_EUNSUPPORTED, "only VR_ERT_LOCAL is implemented");
+  if (p->mode != VR_MODE_DVR) return fail(VR_EUNSUPPORTED, "only VR_MODE_DVR is implemented");
+  if (p->ckpt_K < 1) return fail(VR_EINVAL, "ckpt_K must be >= 1");
+  if (p->tile != 0 && p->tile != 4 && p->tile != 8 && p->tile != 16)
+    return fail(VR_EINVAL, "tile must be 0, 4, 8 or 16");
+  return VR_OK;
+}
+
+// Normalisation window of a render: the table's, or the volume's range.
+int resolve_window(vr_ctx* ctx, vr_volume* vol, hipStream_t s, double& vmin, double& vmax) {
+  if (ctx->tf_vmin == 0.0 && ctx->tf_vmax == 0.0) {
+    VR_TRY(volume_range(vol, s));
+    vmin = vol->vmin;
+    vmax = vol->vmax;
+  } else {
+    vmin = ctx->tf_vmin;
+    vmax = ctx->tf_vmax;
+  }
+  return VR_OK;
+}
+
+int volume_range(vr_volume* vol, hipStream_t s) {
+  if (vol->have_range) return VR_OK;
+  float r[3];
+  VR_TRY(reduce_minmax(vol->ctx, vol->data, vol->n[0] * vol->n[1] * vol->n[2], s, r));
+  vol->vmin = r[0];
+  vol->vmax = r[1];
+  vol->nonfinite = (int64_t)r[2];
+  vol->have_range = true;
+  return VR_OK;
+}
+
+void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, double vmin, double vmax,
+                       const float4* tf, int32_t M) {
+  for (int i = 0; i < 3; i++) a.hi[i] = (double)(vol->n[i] - 1);
+  a.step = p->step;
+  a.tau = p->tau >= 1.0 ? 2.0f : (float)p->tau;
+  a.ert = p->tau < 1.0;
+  a.vmin = (float)vmin;
+  a.inv_range = vmax > vmin ? (float)(1.0 / (vmax - vmin)) : 0.0f;
+  a.M = M;
+  a.tf = tf;
+  a.tile_w = p->tile ? p->tile : 8;
+  a.tile_h = 64 / a.tile_w;
+}
+
+}  // namespace vr
+
+// ====================================================================== ABI
+extern "C" {
+
+const char* vr_last_error(void) { return g_err.c_str(); }
+
+int vr_version(void) { return 1; }
+
+void vr_params_default(vr_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->step = 0.5;
+  p->tau = 0.99;
+  p->ess = 1;
+  p->ert_scope = VR_ERT_LOCAL;
+  p->mode = VR_MODE_DVR;
+  p->ckpt_K = 32;
+  p->tile = 0;
+}
+
+int vr_create(int device, vr_ctx** out) {
+  clear_error();
+  if (!out) return fail(VR_EINVAL, "out is NULL");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return fail(VR_EHIP, "no HIP device available (%s)", hipGetErrorString(e));
+  }
+  if (device < 0 || device >= ndev) return fail(VR_EHIP, "device %d out of range (have %d)", device, ndev);
+  DeviceGuard g(device);
+  vr_ctx* ctx = new (std::nothrow) vr_ctx();
+  if (!ctx) return fail(VR_ENOMEM, "out of host memory");
+  ctx->device = device;
+  if (hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
+    delete ctx;
+    return fail(VR_EHIP, "hipEventCreate failed");
+  }
+  for (auto& sl : ctx->ring)
+    if (hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming) != hipSuccess) {
+      vr_destroy(ctx);
+      return fail(VR_EHIP, "hipEventCreate failed");
+    }
+  *out = ctx;
+  return VR_OK;
+}
+
+int vr_destroy(vr_ctx* ctx) {
+  if (!ctx) return VR_OK;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& sl : ctx->ring) {
+    if (sl.h) (void)hipHostFree(sl.h);
+    if (sl.d) (void)hipFree(sl.d);
+    if (sl.copied) (void)hipEventDestroy(sl.copied);
+  }
+  if (ctx->d_tf) (void)hipFree(ctx->d_tf);
+  if (ctx->d_arena) (void)hipFree(ctx->d_arena);
+  if (ctx->d_small) (void)hipFree(ctx->d_small);
+  if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+  for (auto& t : ctx->timed) {
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
+  }
+  for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+  if (ctx->done) (void)hipEventDestroy(ctx->done);
+  delete ctx;
+  return VR_OK;
+}
+
+int vr_set_profiling(vr_ctx* ctx, int on) {
+  clear_error();
+  if (!ctx) return fail(VR_EINVAL, "ctx is NULL");
+  ctx->prof = on != 0;
+  return VR_OK;
+}
+
+int vr_stage_times(vr_ctx* ctx, double* ms, int32_t* launches) {
+  clear_error();
+  if (!ctx) return fail(VR_EINVAL, "ctx is NULL");
+  DeviceGuard g(ctx->device);
+  double acc[VR_NSTAGES] = {0};
+  int32_t cnt[VR_NSTAGES] = {0};
+  for (auto& t : ctx->timed) {
+    VR_HIP(hipEventSynchronize(t.b));
+    float f = 0.f;
+    VR_HIP(hipEventElapsedTime(&f, t.a, t.b));
+    if (t.stage >= 0 && t.stage < VR_NSTAGES) {
+      acc[t.stage] += f;
+      cnt[t.stage]++;
+    }
+  }
+  for (int i = 0; i < VR_NSTAGES; i++) {
+    if (ms) ms[i] = acc[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return VR_OK;
+}
+
+// ---------------------------------------------------------------- volumes
+static int make_whole_brick(vr_volume* vol) {
+  DevBrick b;
+  std::memset(&b, 0, sizeof b);
+  b.base = vol->data;
+  b.sy = (int32_t)vol->n[0];
+  b.sz = (int32_t)(vol->n[0] * vol->n[1]);
+  for (int i = 0; i < 3; i++) {
+    b.lo[i] = 0;
+    b.hi[i] = (int32_t)(vol->n[i] - 1);
+    b.clo[i] = 0;
+    b.chi[i] = (int32_t)(vol->n[i] - 2);
+  }
+  b.closed = 7;
+  b.vmin = vol->vmin;
+  b.vmax = vol->vmax;
+  vol->whole = b;
+  return VR_OK;
+}
+
+static int check_dims(int64_t n1, int64_t n2, int64_t n3) {
+  if (n1 < 2 || n2 < 2 || n3 < 2) return fail(VR_EINVAL, "every dimension must be >= 2 (got %lld x %lld x %lld)",
+                                               (long long)n1, (long long)n2, (long long)n3);
+  if (n1 > (1 << 24) || n2 > (1 << 24) || n3 > (1 << 24)) return fail(VR_EINVAL, "dimension above 2^24");
+  if (n1 * n2 > ((int64_t)1 << 31) - 1) return fail(VR_EINVAL, "n1*n2 must be below 2^31");
+  return VR_OK;
+}
+
+int vr_volume_create(vr_ctx* ctx, const float* src, int src_on_device, int64_t n1, int64_t n2, int64_t n3,
+                     const int64_t* sub_origin, const int64_t* sub_extent, uintptr_t stream, vr_volume** out) {
+  clear_error();
+  if (!ctx || !src || !out) return fail(VR_EINVAL, "ctx, src and out must be non-NULL");
+  VR_TRY(check_dims(n1, n2, n3));
+  int64_t so[3] = {0, 0, 0}, dn[3] = {n1, n2, n3};
+  const int64_t sn[3] = {n1, n2, n3};
+  if ((sub_origin == nullptr) != (sub_extent == nullptr))
+    return fail(VR_EINVAL, "sub_origin and sub_extent must both be given or both NULL");
+  if (sub_origin) {
+    for (int i = 0; i < 3; i++) {
+      so[i] = sub_origin[i];
+      dn[i] = sub_extent[i];
+      if (so[i] < 0 || dn[i] < 2 || so[i] + dn[i] > sn[i])
+        return fail(VR_EINVAL, "sub-cube axis %d [%lld, %lld) outside [0, %lld) or extent < 2", i + 1,
+                    (long long)so[i], (long long)(so[i] + dn[i]), (long long)sn[i]);
+    }
+    VR_TRY(check_dims(dn[0], dn[1], dn[2]));
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  VR_TRY(ctx_begin(ctx, s));
+  vr_volume* vol = new (std::nothrow) vr_volume();
+  if (!vol) return fail(VR_ENOMEM, "out of host memory");
+  vol->ctx = ctx;
+  for (int i = 0; i < 3; i++) vol->n[i] = dn[i];
+  const int64_t count = dn[0] * dn[1] * dn[2];
+  const size_t bytes = (size_t)count * sizeof(float);
+  if (hipMalloc(&vol->data, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete vol;
+    return fail(VR_ENOMEM, "hipMalloc(%zu bytes) for the volume failed", bytes);
+  }
+  vol->owned = true;
+  int rc = VR_OK;
+  hipError_t e = hipSuccess;
+  const bool whole = !sub_origin || (so[0] == 0 && so[1] == 0 && so[2] == 0 && dn[0] == n1 && dn[1] == n2 && dn[2] == n3);
+  if (whole) {
+    e = hipMemcpyAsync(vol->data, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+  } else if (src_on_device) {
+    e = launch_copy_box(src, sn, so, vol->data, dn, s);
+  } else {
+    for (int64_t z = 0; z < dn[2] && e == hipSuccess; z++) {
+      const float* sp = src + ((so[2] + z) * n2 + so[1]) * n1 + so[0];
+      e = hipMemcpy2DAsync(vol->data + z * dn[0] * dn[1], (size_t)dn[0] * 4, sp, (size_t)n1 * 4, (size_t)dn[0] * 4,
+                           (size_t)dn[1], hipMemcpyHostToDevice, s);
+    }
+  }
+  if (e != hipSuccess) rc = fail(VR_EHIP, "volume upload: %s", hipGetErrorString(e));
+  if (rc == VR_OK) rc = volume_range(vol, s);
+  if (rc == VR_OK && vol->nonfinite > 0)
+    rc = fail(VR_ENONFINITE, "volume holds %lld non-finite voxels", (long long)vol->nonfinite);
+  if (rc == VR_OK) rc = make_whole_brick(vol);
+  if (rc == VR_OK) rc = ctx_end(ctx, s);
+  if (rc != VR_OK) {
+    vr_volume_destroy(vol);
+    return rc;
+  }
+  *out = vol;
+  return VR_OK;
+}
+
+int vr_volume_wrap(vr_ctx* ctx, float* dev_ptr, int64_t n1, int64_t n2, int64_t n3, uintptr_t stream,
+                   vr_volume** out) {
+  clear_error();
+  (void)stream;
+  if (!ctx || !dev_ptr || !out) return fail(VR_EINVAL, "ctx, dev_ptr and out must be non-NULL");
+  VR_TRY(check_dims(n1, n2, n3));
+  hipPointerAttribute_t attr;
+  {
+    DeviceGuard g(ctx->device);
+    if (hipPointerGetAttributes(&attr, dev_ptr) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(VR_EINVAL, "dev_ptr is not a HIP allocation");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+      return fail(VR_EINVAL, "dev_ptr is not device memory");
+  }
+  vr_volume* vol = new (std::nothrow) vr_volume();
+  if (!vol) return fail(VR_ENOMEM, "out of host memory");
+  vol->ctx = ctx;
+  vol->n[0] = n1;
+  vol->n[1] = n2;
+  vol->n[2] = n3;
+  vol->data = dev_ptr;
+  vol->owned = false;
+  make_whole_brick(vol);
+  *out = vol;
+  return VR_OK;
+}
+
+int vr_volume_destroy(vr_volume* vol) {
+  if (!vol) return VR_OK;
+  DeviceGuard g(vol->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (vol->owned && vol->data) (void)hipFree(vol->data);
+  if (vol->d_bricks) (void)hipFree(vol->d_bricks);
+  if (vol->d_store) (void)hipFree(vol->d_store);
+  delete vol;
+  return VR_OK;
+}
+
+int vr_volume_minmax(vr_volume* vol, float* vmin, float* vmax) {
+  clear_error();
+  if (!vol || !vmin || !vmax) return fail(VR_EINVAL, "vol, vmin and vmax must be non-NULL");
+  DeviceGuard g(vol->ctx->device);
+  if (!vol->owned) vol->have_range = false;  // borrowed data may have changed
+  VR_TRY(volume_range(vol, nullptr));
+  if (vol->nonfinite > 0) return fail(VR_ENONFINITE, "volume holds non-finite voxels");
+  *vmin = vol->vmin;
+  *vmax = vol->vmax;
+  vol->whole.vmin = vol->vmin;
+  vol->whole.vmax = vol->vmax;
+  return VR_OK;
+}
+
+int vr_volume_dims(const vr_volume* vol, int64_t n[3]) {
+  clear_error();
+  if (!vol || !n) return fail(VR_EINVAL, "vol and n must be non-NULL");
+  for (int i = 0; i < 3; i++) n[i] = vol->n[i];
+  return VR_OK;
+}
+
+int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream) {
+  clear_error();
+  if (!vol || !spec) return fail(VR_EINVAL, "vol and spec must be non-NULL");
+  if (spec->ghost != 1) return fail(VR_EINVAL, "ghost must be 1");
+  if (spec->macrocell != 0) return fail(VR_EINVAL, "macrocell must be 0");
+  Partition P;
+  std::string err;
+  if (spec->mode == VR_BRICK_GRID) {
+    if (!make_grid(vol->n, spec->size, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else if (spec->mode == VR_BRICK_LONGEST_AXIS) {
+    if (!make_kd(vol->n, spec->nparts, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else {
+    return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
+  }
+  vr_ctx* ctx = vol->ctx;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  VR_TRY(ctx_begin(ctx, s));
+  const int32_t nb = (int32_t)P.boxes.size();
+  const int64_t* n = vol->n;
+  // storage: virtual (strided view of the volume) unless asked, or unless a
+  // brick's local offsets would not fit 32-bit indices
+  bool mat = spec->materialize != 0;
+  std::vector<int64_t> sboxes(6 * (size_t)nb);
+  for (int32_t b = 0; b < nb; b++) {
+    int64_t slo[3], shi[3];
+    stored_box(P.boxes[b], n, slo, shi);
+    for (int i = 0; i < 3; i++) {
+      sboxes[6 * b + i] = slo[i];
+      sboxes[6 * b + 3 + i] = shi[i];
+    }
+    const int64_t span = (shi[2] - slo[2] + 1) * n[0] * n[1];
+    if (span >= ((int64_t)1 << 31)) mat = true;
+  }
+  // free previous partition storage
+  if (vol->d_store) {
+    VR_HIP(hipStreamSynchronize(s));
+    VR_HIP(hipFree(vol->d_store));
+    vol->d_store = nullptr;
+  }
+  std::vector<int64_t> store_off((size_t)nb, 0);
+  if (mat) {
+    int64_t total = 0;
+    for (int32_t b = 0; b < nb; b++) {
+      store_off[b] = total;
+      int64_t c = 1;
+      for (int i = 0; i < 3; i++) c *= sboxes[6 * b + 3 + i] - sboxes[6 * b + i] + 1;
+      total += (c + 63) & ~(int64_t)63;
+    }
+    if (hipMalloc(&vol->d_store, (size_t)total * sizeof(float)) != hipSuccess) {
+      (void)hipGetLastError();
+      vol->d_store = nullptr;
+      return fail(VR_ENOMEM, "hipMalloc(%lld floats) for materialised bricks failed", (long long)total);
+    }
+    for (int32_t b = 0; b < nb; b++) {
+      const int64_t so[3] = {sboxes[6 * b], sboxes[6 * b + 1], sboxes[6 * b + 2]};
+      const int64_t dn[3] = {sboxes[6 * b + 3] - so[0] + 1, sboxes[6 * b + 4] - so[1] + 1, sboxes[6 * b + 5] - so[2] + 1};
+      VR_HIP(launch_copy_box(vol->data, n, so, vol->d_store + store_off[b], dn, s));
+    }
+  }
+  // per-brick (min, max) over stored voxels
+  int zper = 4, zmax = 1;
+  for (int32_t b = 0; b < nb; b++) zmax = std::max<int>(zmax, (int)(sboxes[6 * b + 5] - sboxes[6 * b + 2] + 1));
+  const int zgroups = (zmax + zper - 1) / zper;
+  const size_t need = (size_t)nb * 48 + (size_t)nb * zgroups * 8 + (size_t)nb * 8 + 1024;
+  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes, need));
+  char* sc = reinterpret_cast<char*>(ctx->d_scratch);
+  int64_t* d_boxes = reinterpret_cast<int64_t*>(sc);
+  float* d_part = reinterpret_cast<float*>(sc + (size_t)nb * 48);
+  float* d_mm = reinterpret_cast<float*>(sc + (size_t)nb * 48 + (size_t)nb * zgroups * 8);
+  VR_HIP(hipMemcpyAsync(d_boxes, sboxes.data(), (size_t)nb * 48, hipMemcpyHostToDevice, s));
+  VR_HIP(launch_brick_minmax_parts(vol->data, n, d_boxes, nb, zgroups, zper, d_part, d_mm, s));
+  std::vector<float> mm(2 * (size_t)nb);
+  VR_HIP(hipMemcpyAsync(mm.data(), d_mm, (size_t)nb * 8, hipMemcpyDeviceToHost, s));
+  VR_HIP(hipStreamSynchronize(s));
+  // brick records
+  std::vector<DevBrick> recs((size_t)nb);
+  vol->bdesc.assign((size_t)nb, vr_brick_desc());
+  for (int32_t b = 0; b < nb; b++) {
+    const Box& bx = P.boxes[b];
+    DevBrick& r = recs[b];
+    std::memset(&r, 0, sizeof r);
+    const int64_t* slo = &sboxes[6 * b];
+    const int64_t* shi = &sboxes[6 * b + 3];
+    if (mat) {
+      const int64_t d1 = shi[0] - slo[0] + 1, d2 = shi[1] - slo[1] + 1;
+      r.sy = (int32_t)d1;
+      r.sz = (int32_t)(d1 * d2);
+      r.base = vol->d_store + store_off[b] + ((bx.lo[2] - slo[2]) * d2 + (bx.lo[1] - slo[1])) * d1 + (bx.lo[0] - slo[0]);
+    } else {
+      r.sy = (int32_t)n[0];
+      r.sz = (int32_t)(n[0] * n[1]);
+      r.base = vol->data + (bx.lo[2] * n[1] + bx.lo[1]) * n[0] + bx.lo[0];
+    }
+    r.closed = 0;
+    for (int i = 0; i < 3; i++) {
+      r.lo[i] = (int32_t)bx.lo[i];
+      r.hi[i] = (int32_t)bx.hi[i];
+      if (bx.closed[i]) r.closed |= 1 << i;
+      r.clo[i] = (int32_t)(slo[i] - bx.lo[i]);
+      r.chi[i] = (int32_t)(shi[i] - 1 - bx.lo[i]);
+    }
+    r.vmin = mm[2 * b];
+    r.vmax = mm[2 * b + 1];
+    vr_brick_desc& d = vol->bdesc[b];
+    for (int i = 0; i < 3; i++) {
+      d.lo[i] = bx.lo[i];
+      d.hi[i] = bx.hi[i];
+      d.closed[i] = bx.closed[i];
+      d.slo[i] = slo[i];
+      d.shi[i] = shi[i];
+    }
+    d.vmin = r.vmin;
+    d.vmax = r.vmax;
+  }
+  if (vol->d_bricks) {
+    VR_HIP(hipFree(vol->d_bricks));
+    vol->d_bricks = nullptr;
+  }
+  if (hipMalloc(&vol->d_bricks, sizeof(DevBrick) * (size_t)nb) != hipSuccess) {
+    (void)hipGetLastError();
+    vol->d_bricks = nullptr;
+    return fail(VR_ENOMEM, "hipMalloc for the brick table failed");
+  }
+  VR_HIP(hipMemcpy(vol->d_bricks, recs.data(), sizeof(DevBrick) * (size_t)nb, hipMemcpyHostToDevice));
+  vol->bricks = std::move(recs);
+  vol->part = std::move(P);
+  vol->bricked = true;
+  vol->materialized = mat;
+  vol->version++;
+  VR_TRY(ctx_end(ctx, s));
+  return VR_OK;
+}
+
+int vr_volume_brick_info(const vr_volume* vol, int32_t* nb, vr_brick_desc* out) {
+  clear_error();
+  if (!vol || !nb) return fail(VR_EINVAL, "vol and nb must be non-NULL");
+  const int32_t have = vol->bricked ? (int32_t)vol->bdesc.size() : 0;
+  if (out) {
+    if (*nb < have) return fail(VR_EINVAL, "capacity %d below brick count %d", *nb, have);
+    for (int32_t i = 0; i < have; i++) out[i] = vol->bdesc[i];
+  }
+  *nb = have;
+  return VR_OK;
+}
+
+// ---------------------------------------------------------------- transfer function
+int vr_tf_set(vr_ctx* ctx, const float* rgba, int32_t m, double vmin, double vmax, int src_on_device,
+              uintptr_t stream) {
+  clear_error();
+  if (!ctx || !rgba) return fail(VR_EINVAL, "ctx and rgba must be non-NULL");
+  if (m < 2 || m > 4096) return fail(VR_EINVAL, "table size %d outside [2, 4096]", m);
+  if (!std::isfinite(vmin) || !std::isfinite(vmax) || vmax < vmin)
+    return fail(VR_EINVAL, "window must be finite with vmax >= vmin");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float> h((size_t)m * 4);
+  if (src_on_device) {
+    VR_HIP(hipMemcpyAsync(h.data(), rgba, h.size() * 4, hipMemcpyDeviceToHost, s));
+    VR_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(h.data(), rgba, h.size() * 4);
+  }
+  for (size_t i = 0; i < h.size(); i++)
+    if (!(h[i] >= 0.0f && h[i] <= 1.0f)) return fail(VR_EINVAL, "table entry %zu = %g outside [0, 1]", i, (double)h[i]);
+  VR_TRY(ctx_begin(ctx, s));
+  if (m > ctx->tf_cap) {
+    if (ctx->d_tf) VR_HIP(hipFree(ctx->d_tf));
+    ctx->d_tf = nullptr;
+    if (hipMalloc(&ctx->d_tf, sizeof(float4) * (size_t)m) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->d_tf = nullptr;
+      ctx->tf_cap = 0;
+      return fail(VR_ENOMEM, "hipMalloc for the table failed");
+    }
+    ctx->tf_cap = m;
+  }
+  // synchronous copy: the host vector dies with this call
+  VR_HIP(hipMemcpyAsync(ctx->d_tf, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+  VR_HIP(hipStreamSynchronize(s));
+  ctx->h_tf = std::move(h);
+  ctx->tf_m = m;
+  ctx->tf_vmin = vmin;
+  ctx->tf_vmax = vmax;
+  ctx->tf_set = true;
+  ctx->tf_version++;
+  VR_TRY(ctx_end(ctx, s));
+  return VR_OK;
+}
+
+// ---------------------------------------------------------------- host-only helpers
+int vr_plan_view(const int64_t dims[3], const vr_brick_spec* spec, const vr_view* view, int32_t* nb, int32_t* rects,
+                 int32_t* order) {
+  clear_error();
+  if (!dims || !spec || !view || !nb) return fail(VR_EINVAL, "dims, spec, view and nb must be non-NULL");
+  VR_TRY(check_dims(dims[0], dims[1], dims[2]));
+  VR_TRY(check_view(view));
+  Partition P;
+  std::string err;
+  if (spec->mode == VR_BRICK_GRID) {
+    if (!make_grid(dims, spec->size, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else if (spec->mode == VR_BRICK_LONGEST_AXIS) {
+    if (!make_kd(dims, spec->nparts, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else {
+    return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
+  }
+  const int32_t have = (int32_t)P.boxes.size();
+  if ((rects || order) && *nb < have) return fail(VR_EINVAL, "capacity %d below brick count %d", *nb, have);
+  Camera cam;
+  make_camera(*view, dims, cam);
+  if (rects)
+    for (int32_t b = 0; b < have; b++) {
+      Rect r = brick_rect(cam, P.boxes[b]);
+      rects[4 * b] = r.x0;
+      rects[4 * b + 1] = r.y0;
+      rects[4 * b + 2] = r.w;
+      rects[4 * b + 3] = r.h;
+    }
+  if (order) {
+    std::vector<int32_t> o;
+    depth_order(P, cam.e3, o);
+    std::copy(o.begin(), o.end(), order);
+  }
+  *nb = have;
+  return VR_OK;
+}
+
+int vr_partition(const int64_t dims[3], const vr_brick_spec* spec, int32_t* nb, vr_brick_desc* out) {
+  clear_error();
+  if (!dims || !spec || !nb) return fail(VR_EINVAL, "dims, spec and nb must be non-NULL");
+  VR_TRY(check_dims(dims[0], dims[1], dims[2]));
+  Partition P;
+  std::string err;
+  if (spec->mode == VR_BRICK_GRID) {
+    if (!make_grid(dims, spec->size, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else if (spec->mode == VR_BRICK_LONGEST_AXIS) {
+    if (!make_kd(dims, spec->nparts, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else {
+    return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
+  }
+  const int32_t have = (int32_t)P.boxes.size();
+  if (out) {
+    if (*nb < have) return fail(VR_EINVAL, "capacity %d below brick count %d", *nb, have);
+    for (int32_t b = 0; b < have; b++) {
+      vr_brick_desc d;
+      std::memset(&d, 0, sizeof d);
+      int64_t slo[3], shi[3];
+      stored_box(P.boxes[b], dims, slo, shi);
+      for (int i = 0; i < 3; i++) {
+        d.lo[i] = P.boxes[b].lo[i];
+        d.hi[i] = P.boxes[b].hi[i];
+        d.closed[i] = P.boxes[b].closed[i];
+        d.slo[i] = slo[i];
+        d.shi[i] = shi[i];
+      }
+      out[b] = d;
+    }
+  }
+  *nb = have;
+  return VR_OK;
+}
+
+int vr_count_samples(const int64_t dims[3], const vr_view* view, double step, int64_t* nominal) {
+  clear_error();
+  if (!dims || !view || !nominal) return fail(VR_EINVAL, "dims, view and nominal must be non-NULL");
+  VR_TRY(check_dims(dims[0], dims[1], dims[2]));
+  VR_TRY(check_view(view));
+  if (!(step > 0.0)) return fail(VR_EINVAL, "step must be > 0");
+  Camera cam;
+  make_camera(*view, dims, cam);
+  *nominal = count_samples(cam, dims, step);
+  return VR_OK;
+}
+
+}  // extern "C"

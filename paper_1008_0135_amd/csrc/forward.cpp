@@ -1,0 +1,281 @@
+// forward.cpp -- forward rendering entry points: vr_render (whole volume or
+// bricks + composite), vr_render_bricks and vr_composite (the two halves of
+// sort-last compositing, paper Sec. 2.4 and 2.5).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "forward.h"
+#include "plan.h"
+#include "runtime.h"
+#include "vr_internal.h"
+
+namespace vr {
+
+namespace {
+
+size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+}  // namespace
+
+// Plan one view of a bricked volume: rectangles, culling (empty rectangle or
+// transparent brick), launch order (brick index order, which keeps
+// neighbouring bricks together), arena offsets and the front-to-back layers.
+void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params* p, int32_t tile_w,
+                       const float* tf, int32_t M, double vmin, double vmax, ViewPlan& vp) {
+  const Partition& P = vol->part;
+  const int32_t nb = (int32_t)P.boxes.size();
+  const int32_t tile_h = 64 / tile_w;
+  std::vector<Rect> rects((size_t)nb);
+  std::vector<int32_t> slot((size_t)nb, -1);
+  vp.bv.clear();
+  vp.layers_order.clear();
+  int32_t tiles = 0;
+  int64_t pix = 0;
+  for (int32_t b = 0; b < nb; b++) {
+    rects[b] = brick_rect(cam, P.boxes[b]);
+    if (rects[b].w == 0 || rects[b].h == 0) continue;
+    if (p->ess && brick_transparent(vol->bricks[b].vmin, vol->bricks[b].vmax, tf, M, vmin, vmax)) continue;
+    DevBrickView v;
+    std::memset(&v, 0, sizeof v);
+    v.brick = b;
+    v.x0 = rects[b].x0;
+    v.y0 = rects[b].y0;
+    v.w = rects[b].w;
+    v.h = rects[b].h;
+    v.tiles_x = (v.w + tile_w - 1) / tile_w;
+    v.tile_begin = tiles;
+    v.img_off = pix;
+    tiles += v.tiles_x * ((v.h + tile_h - 1) / tile_h);
+    pix += (int64_t)v.w * v.h;
+    slot[b] = (int32_t)vp.bv.size();
+    vp.bv.push_back(v);
+  }
+  std::vector<int32_t> order;
+  depth_order(P, cam.e3, order);
+  for (int32_t b : order)
+    if (slot[b] >= 0) vp.layers_order.push_back(slot[b]);
+  vp.ntiles = tiles;
+  vp.pixels = pix;
+}
+
+int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p,
+                   float* out, hipStream_t s, ForwardExtras* extras) {
+  const bool bricked = vol->bricked;
+  const int32_t W = views[0].W, H = views[0].H;
+  double vmin, vmax;
+  VR_TRY(resolve_window(ctx, vol, s, vmin, vmax));
+  MarchArgs base;
+  std::memset(&base, 0, sizeof base);
+  fill_march_common(base, vol, p, vmin, vmax, ctx->d_tf, ctx->tf_m);
+  const int32_t tw = base.tile_w, th = base.tile_h;
+
+  std::vector<ViewPlan> plans((size_t)nviews);
+  std::vector<Camera> cams((size_t)nviews);
+  int64_t arena_pix = 0;
+  for (int32_t v = 0; v < nviews; v++) {
+    make_camera(views[v], vol->n, cams[v]);
+    ViewPlan& vp = plans[v];
+    if (bricked) {
+      plan_bricked_view(vol, cams[v], p, tw, ctx->h_tf.data(), ctx->tf_m, vmin, vmax, vp);
+      arena_pix = std::max(arena_pix, vp.pixels);
+    } else {
+      DevBrickView b;
+      std::memset(&b, 0, sizeof b);
+      b.brick = 0;
+      b.w = W;
+      b.h = H;
+      b.tiles_x = (W + tw - 1) / tw;
+      b.tile_begin = 0;
+      b.img_off = (int64_t)v * W * H;
+      vp.bv.assign(1, b);
+      vp.ntiles = b.tiles_x * ((H + th - 1) / th);
+      vp.pixels = (int64_t)W * H;
+    }
+  }
+  if (bricked && arena_pix > 0) VR_TRY(ensure_device(&ctx->d_arena, &ctx->arena_bytes, (size_t)arena_pix * 16));
+  float4* arena = reinterpret_cast<float4*>(ctx->d_arena);
+
+  // pack: [whole-volume brick] then per view [DevBrickView...][CompLayer...]
+  std::vector<size_t> off_bv((size_t)nviews), off_cl((size_t)nviews);
+  size_t bytes = align16(sizeof(DevBrick));
+  for (int32_t v = 0; v < nviews; v++) {
+    off_bv[v] = bytes;
+    bytes = align16(bytes + sizeof(DevBrickView) * plans[v].bv.size());
+    off_cl[v] = bytes;
+    bytes = align16(bytes + sizeof(CompLayer) * plans[v].layers_order.size());
+  }
+  std::vector<unsigned char> host(bytes, 0);
+  std::memcpy(host.data(), &vol->whole, sizeof(DevBrick));
+  for (int32_t v = 0; v < nviews; v++) {
+    const ViewPlan& vp = plans[v];
+    std::memcpy(host.data() + off_bv[v], vp.bv.data(), sizeof(DevBrickView) * vp.bv.size());
+    CompLayer* cl = reinterpret_cast<CompLayer*>(host.data() + off_cl[v]);
+    for (size_t i = 0; i < vp.layers_order.size(); i++) {
+      const DevBrickView& b = vp.bv[vp.layers_order[i]];
+      cl[i].x0 = b.x0;
+      cl[i].y0 = b.y0;
+      cl[i].w = b.w;
+      cl[i].h = b.h;
+      cl[i].rgba = arena + b.img_off;
+    }
+  }
+  void* dtab = nullptr;
+  VR_TRY(stage_begin(ctx, VR_STAGE_SETUP, s));
+  VR_TRY(upload_tables(ctx, s, host.data(), bytes, &dtab));
+  VR_TRY(stage_end(ctx, s));
+  unsigned char* dt = reinterpret_cast<unsigned char*>(dtab);
+
+  for (int32_t v = 0; v < nviews; v++) {
+    const ViewPlan& vp = plans[v];
+    MarchArgs a = base;
+    a.cam = cams[v];
+    a.nbv = (int32_t)vp.bv.size();
+    a.ntiles = vp.ntiles;
+    a.bv = reinterpret_cast<const DevBrickView*>(dt + off_bv[v]);
+    if (bricked) {
+      a.bricks = vol->d_bricks;
+      a.img = arena;
+    } else {
+      a.bricks = reinterpret_cast<const DevBrick*>(dt);
+      a.img = reinterpret_cast<float4*>(out);
+    }
+    if (extras) extras->prepare(a, v);
+    VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
+    VR_HIP(extras ? extras->launch(a, s) : launch_march(a, s));
+    VR_TRY(stage_end(ctx, s));
+    if (bricked && out) {
+      CompArgs c;
+      std::memset(&c, 0, sizeof c);
+      c.layers = reinterpret_cast<const CompLayer*>(dt + off_cl[v]);
+      c.n = (int32_t)vp.layers_order.size();
+      c.W = W;
+      c.H = H;
+      c.out = reinterpret_cast<float4*>(out) + (int64_t)v * W * H;
+      VR_TRY(stage_begin(ctx, VR_STAGE_COMPOSITE, s));
+      VR_HIP(launch_composite(c, s));
+      VR_TRY(stage_end(ctx, s));
+    }
+  }
+  if (extras) {
+    extras->vmin = vmin;
+    extras->vmax = vmax;
+  }
+  return VR_OK;
+}
+
+int validate_render(vr_ctx* ctx, const vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p) {
+  if (!ctx || !vol || !views) return fail(VR_EINVAL, "ctx, vol and views must be non-NULL");
+  if (vol->ctx != ctx) return fail(VR_EINVAL, "volume belongs to another context");
+  if (nviews < 1) return fail(VR_EINVAL, "nviews must be >= 1");
+  VR_TRY(check_params(p));
+  for (int32_t v = 0; v < nviews; v++) {
+    VR_TRY(check_view(&views[v]));
+    if (views[v].W != views[0].W || views[v].H != views[0].H)
+      return fail(VR_EINVAL, "all views of one call must share W and H");
+  }
+  if (!ctx->tf_set) return fail(VR_ESTATE, "no transfer function set (vr_tf_set)");
+  if (!vol->bricked && vol->n[0] * vol->n[1] * vol->n[2] >= ((int64_t)1 << 31))
+    return fail(VR_EUNSUPPORTED, "unbricked rendering needs fewer than 2^31 voxels; brick the volume");
+  return VR_OK;
+}
+
+}  // namespace vr
+
+using namespace vr;
+
+extern "C" {
+
+int vr_render(vr_ctx* ctx, const vr_volume* cvol, const vr_view* views, int32_t nviews, const vr_params* p,
+              float* out, uintptr_t stream, vr_state** save) {
+  clear_error();
+  VR_TRY(validate_render(ctx, cvol, views, nviews, p));
+  if (!out) return fail(VR_EINVAL, "out is NULL");
+  vr_volume* vol = const_cast<vr_volume*>(cvol);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  if (save) return render_with_state(ctx, vol, views, nviews, p, out, s, save);
+  VR_TRY(ctx_begin(ctx, s));
+  VR_TRY(render_forward(ctx, vol, views, nviews, p, out, s, nullptr));
+  return ctx_end(ctx, s);
+}
+
+int vr_render_bricks(vr_ctx* ctx, const vr_volume* cvol, const vr_view* view, const vr_params* p,
+                     vr_brick_image* imgs, int32_t* nimg, int32_t* order, uintptr_t stream) {
+  clear_error();
+  VR_TRY(validate_render(ctx, cvol, view, 1, p));
+  if (!imgs || !nimg || !order) return fail(VR_EINVAL, "imgs, nimg and order must be non-NULL");
+  if (!cvol->bricked) return fail(VR_ESTATE, "volume is not bricked (vr_volume_brick)");
+  vr_volume* vol = const_cast<vr_volume*>(cvol);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  VR_TRY(ctx_begin(ctx, s));
+  // plan first to check capacity
+  double vmin, vmax;
+  VR_TRY(resolve_window(ctx, vol, s, vmin, vmax));
+  Camera cam;
+  make_camera(*view, vol->n, cam);
+  ViewPlan vp;
+  const int32_t tw = p->tile ? p->tile : 8;
+  plan_bricked_view(vol, cam, p, tw, ctx->h_tf.data(), ctx->tf_m, vmin, vmax, vp);
+  if ((int32_t)vp.bv.size() > *nimg)
+    return fail(VR_EINVAL, "capacity %d below the %d rendered bricks", *nimg, (int)vp.bv.size());
+  VR_TRY(render_forward(ctx, vol, view, 1, p, nullptr, s, nullptr));
+  float4* arena = reinterpret_cast<float4*>(ctx->d_arena);
+  for (size_t i = 0; i < vp.bv.size(); i++) {
+    const DevBrickView& b = vp.bv[i];
+    imgs[i].brick = b.brick;
+    imgs[i].x0 = b.x0;
+    imgs[i].y0 = b.y0;
+    imgs[i].w = b.w;
+    imgs[i].h = b.h;
+    imgs[i].reserved = 0;
+    imgs[i].rgba = reinterpret_cast<float*>(arena + b.img_off);
+  }
+  for (size_t i = 0; i < vp.layers_order.size(); i++) order[i] = vp.layers_order[i];
+  *nimg = (int32_t)vp.bv.size();
+  return ctx_end(ctx, s);
+}
+
+int vr_composite(vr_ctx* ctx, const vr_brick_image* imgs, int32_t n, const int32_t* order, int32_t W, int32_t H,
+                 float* out, uintptr_t stream) {
+  clear_error();
+  if (!ctx || !out || (n > 0 && !imgs)) return fail(VR_EINVAL, "ctx, out (and imgs when n > 0) must be non-NULL");
+  if (n < 0) return fail(VR_EINVAL, "n must be >= 0");
+  if (W < 1 || H < 1 || W > 16384 || H > 16384) return fail(VR_EINVAL, "image size outside [1, 16384]");
+  std::vector<CompLayer> layers((size_t)n);
+  std::vector<char> seen((size_t)n, 0);
+  for (int32_t i = 0; i < n; i++) {
+    const int32_t j = order ? order[i] : i;
+    if (j < 0 || j >= n) return fail(VR_EINVAL, "order[%d] = %d out of range", i, j);
+    if (seen[j]) return fail(VR_EINVAL, "order lists image %d twice", j);
+    seen[j] = 1;
+    const vr_brick_image& im = imgs[j];
+    if (im.w < 0 || im.h < 0 || im.x0 < 0 || im.y0 < 0 || (int64_t)im.x0 + im.w > W || (int64_t)im.y0 + im.h > H)
+      return fail(VR_EINVAL, "image %d rectangle (%d,%d,%d,%d) outside %dx%d", j, im.x0, im.y0, im.w, im.h, W, H);
+    if (im.w > 0 && im.h > 0 && !im.rgba) return fail(VR_EINVAL, "image %d has no pixels pointer", j);
+    layers[i] = CompLayer{im.x0, im.y0, im.w, im.h, reinterpret_cast<const float4*>(im.rgba)};
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  VR_TRY(ctx_begin(ctx, s));
+  void* d = nullptr;
+  CompLayer dummy{0, 0, 0, 0, nullptr};
+  VR_TRY(upload_tables(ctx, s, n > 0 ? (const void*)layers.data() : (const void*)&dummy,
+                       sizeof(CompLayer) * (size_t)std::max(n, 1), &d));
+  CompArgs c;
+  std::memset(&c, 0, sizeof c);
+  c.layers = reinterpret_cast<const CompLayer*>(d);
+  c.n = n;
+  c.W = W;
+  c.H = H;
+  c.out = reinterpret_cast<float4*>(out);
+  VR_TRY(stage_begin(ctx, VR_STAGE_COMPOSITE, s));
+  VR_HIP(launch_composite(c, s));
+  VR_TRY(stage_end(ctx, s));
+  return ctx_end(ctx, s);
+}
+
+}  // extern "C"

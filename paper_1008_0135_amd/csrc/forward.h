@@ -1,0 +1,35 @@
+// forward.h -- forward-path planning and launch sequence shared by the
+// forward, differentiable and autotuning entry points.
+#pragma once
+
+#include <vector>
+
+#include "runtime.h"
+
+namespace vr {
+
+struct ViewPlan {
+  std::vector<DevBrickView> bv;       // rendered bricks, launch order
+  std::vector<int32_t> layers_order;  // indices into bv, front to back
+  int32_t ntiles = 0;
+  int64_t pixels = 0;                 // brick-image pixels of this view
+};
+
+// Hook that replaces the march launch (the differentiable forward saves
+// per-ray state from its own kernel variant).
+struct ForwardExtras {
+  virtual ~ForwardExtras() {}
+  virtual void prepare(MarchArgs& a, int32_t view) = 0;
+  virtual hipError_t launch(const MarchArgs& a, hipStream_t s) = 0;
+  double vmin = 0.0, vmax = 0.0;
+};
+
+void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params* p, int32_t tile_w, const float* tf,
+                       int32_t M, double vmin, double vmax, ViewPlan& vp);
+int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p, float* out,
+                   hipStream_t s, ForwardExtras* extras);
+int validate_render(vr_ctx* ctx, const vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p);
+int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p,
+                      float* out, hipStream_t s, vr_state** save);
+
+}  // namespace vr

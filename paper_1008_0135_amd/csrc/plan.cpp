@@ -1,0 +1,203 @@
+// plan.cpp -- host-side planning of libvr (see plan.h).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace vr {
+
+bool make_grid(const int64_t n[3], const int64_t size[3], Partition& out, std::string& err) {
+  out = Partition();
+  out.mode = VR_BRICK_GRID;
+  int64_t total = 1;
+  for (int i = 0; i < 3; i++) {
+    if (size[i] < 1) {
+      err = "brick size must be >= 1 along every axis";
+      return false;
+    }
+    out.gsize[i] = size[i];
+    int64_t c = (n[i] - 1 + size[i] - 1) / size[i];
+    if (c < 1) c = 1;
+    out.gcount[i] = (int32_t)std::min<int64_t>(c, 1 << 20);
+    total *= c;
+  }
+  if (total > 65536) {
+    err = "more than 65536 bricks";
+    return false;
+  }
+  out.boxes.reserve((size_t)total);
+  for (int32_t k3 = 0; k3 < out.gcount[2]; k3++)
+    for (int32_t k2 = 0; k2 < out.gcount[1]; k2++)
+      for (int32_t k1 = 0; k1 < out.gcount[0]; k1++) {
+        Box b;
+        const int32_t k[3] = {k1, k2, k3};
+        for (int i = 0; i < 3; i++) {
+          b.lo[i] = (int64_t)k[i] * size[i];
+          const bool last = k[i] == out.gcount[i] - 1;
+          b.hi[i] = last ? n[i] - 1 : (int64_t)(k[i] + 1) * size[i];
+          b.closed[i] = last ? 1 : 0;
+        }
+        out.boxes.push_back(b);
+      }
+  return true;
+}
+
+static void kd_rec(Partition& P, const int64_t lo[3], const int64_t hi[3], const int32_t cl[3], int32_t p,
+                   int32_t node) {
+  if (p == 1) {
+    Box b;
+    for (int i = 0; i < 3; i++) {
+      b.lo[i] = lo[i];
+      b.hi[i] = hi[i];
+      b.closed[i] = cl[i];
+    }
+    P.nodes[node].leaf = (int32_t)P.boxes.size();
+    P.boxes.push_back(b);
+    return;
+  }
+  int ax = 0;
+  for (int i = 1; i < 3; i++)
+    if (hi[i] - lo[i] > hi[ax] - lo[ax]) ax = i;
+  const int32_t pl = p / 2;
+  const int64_t ext = hi[ax] - lo[ax];
+  int64_t cut = lo[ax] + (int64_t)std::nearbyint((double)(ext * pl) / (double)p);
+  cut = std::min(std::max(cut, lo[ax] + 1), hi[ax] - 1);
+  P.nodes[node].axis = ax;
+  P.nodes[node].plane = cut;
+  P.nodes[node].leaf = -1;
+  const int32_t left = (int32_t)P.nodes.size();
+  P.nodes.push_back(KdNode{0, 0, -1, -1, -1});
+  const int32_t right = (int32_t)P.nodes.size();
+  P.nodes.push_back(KdNode{0, 0, -1, -1, -1});
+  P.nodes[node].left = left;
+  P.nodes[node].right = right;
+  int64_t hl[3] = {hi[0], hi[1], hi[2]}, lr[3] = {lo[0], lo[1], lo[2]};
+  int32_t cll[3] = {cl[0], cl[1], cl[2]};
+  hl[ax] = cut;
+  cll[ax] = 0;
+  lr[ax] = cut;
+  kd_rec(P, lo, hl, cll, pl, left);
+  kd_rec(P, lr, hi, cl, p - pl, right);
+}
+
+bool make_kd(const int64_t n[3], int32_t nparts, Partition& out, std::string& err) {
+  out = Partition();
+  out.mode = VR_BRICK_LONGEST_AXIS;
+  if (nparts < 1 || nparts > 4096) {
+    err = "nparts must be in [1, 4096]";
+    return false;
+  }
+  // every split needs an extent of at least 2 cells on the chosen axis
+  int64_t cells = (n[0] - 1) * (n[1] - 1) * (n[2] - 1);
+  if (cells < nparts) {
+    err = "volume too small for that many sub-volumes";
+    return false;
+  }
+  const int64_t lo[3] = {0, 0, 0}, hi[3] = {n[0] - 1, n[1] - 1, n[2] - 1};
+  const int32_t cl[3] = {1, 1, 1};
+  out.nodes.push_back(KdNode{0, 0, -1, -1, -1});
+  kd_rec(out, lo, hi, cl, nparts, 0);
+  for (const Box& b : out.boxes)
+    for (int i = 0; i < 3; i++)
+      if (b.hi[i] <= b.lo[i]) {
+        err = "longest-axis split produced an empty sub-volume";
+        return false;
+      }
+  return true;
+}
+
+void stored_box(const Box& b, const int64_t n[3], int64_t slo[3], int64_t shi[3]) {
+  for (int i = 0; i < 3; i++) {
+    slo[i] = std::max<int64_t>(0, b.lo[i] - 1);
+    shi[i] = std::min<int64_t>(n[i] - 1, b.hi[i] + 1);
+  }
+}
+
+Rect brick_rect(const Camera& cam, const Box& b) {
+  double umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+  const double k = (double)cam.W / cam.S;  // pixels per voxel
+  for (int c = 0; c < 8; c++) {
+    double p[3];
+    for (int i = 0; i < 3; i++) p[i] = (double)(((c >> i) & 1) ? b.hi[i] : b.lo[i]) - cam.c[i];
+    const double x = p[0] * cam.e1[0] + p[1] * cam.e1[1] + p[2] * cam.e1[2];
+    const double y = p[0] * cam.e2[0] + p[1] * cam.e2[1] + p[2] * cam.e2[2];
+    const double u = x * k + 0.5 * cam.W - 0.5, v = y * k + 0.5 * cam.H - 0.5;
+    umin = std::min(umin, u);
+    umax = std::max(umax, u);
+    vmin = std::min(vmin, v);
+    vmax = std::max(vmax, v);
+  }
+  Rect r{0, 0, 0, 0};
+  const double x0 = std::max(0.0, std::floor(umin) - 1.0), x1 = std::min((double)cam.W - 1, std::ceil(umax) + 1.0);
+  const double y0 = std::max(0.0, std::floor(vmin) - 1.0), y1 = std::min((double)cam.H - 1, std::ceil(vmax) + 1.0);
+  if (x1 < x0 || y1 < y0) return r;
+  r.x0 = (int32_t)x0;
+  r.y0 = (int32_t)y0;
+  r.w = (int32_t)(x1 - x0) + 1;
+  r.h = (int32_t)(y1 - y0) + 1;
+  return r;
+}
+
+static void kd_order(const Partition& P, int32_t node, const double d[3], std::vector<int32_t>& order) {
+  const KdNode& nd = P.nodes[node];
+  if (nd.leaf >= 0) {
+    order.push_back(nd.leaf);
+    return;
+  }
+  const bool low_first = d[nd.axis] >= 0.0;
+  kd_order(P, low_first ? nd.left : nd.right, d, order);
+  kd_order(P, low_first ? nd.right : nd.left, d, order);
+}
+
+void depth_order(const Partition& p, const double d[3], std::vector<int32_t>& order) {
+  order.clear();
+  if (p.mode == VR_BRICK_LONGEST_AXIS) {
+    kd_order(p, 0, d, order);
+    return;
+  }
+  // grid: visit slabs along axis 3, then 2, then 1, each in the ray's direction;
+  // a ray crosses the grid monotonically along every axis, so this lexicographic
+  // order puts every brick a ray meets after the ones it met before.
+  const int32_t* c = p.gcount;
+  order.reserve(p.boxes.size());
+  for (int32_t a3 = 0; a3 < c[2]; a3++) {
+    const int32_t k3 = d[2] >= 0.0 ? a3 : c[2] - 1 - a3;
+    for (int32_t a2 = 0; a2 < c[1]; a2++) {
+      const int32_t k2 = d[1] >= 0.0 ? a2 : c[1] - 1 - a2;
+      for (int32_t a1 = 0; a1 < c[0]; a1++) {
+        const int32_t k1 = d[0] >= 0.0 ? a1 : c[0] - 1 - a1;
+        order.push_back((k3 * c[1] + k2) * c[0] + k1);
+      }
+    }
+  }
+}
+
+bool brick_transparent(float bmin, float bmax, const float* tf, int32_t M, double vmin, double vmax) {
+  if (!std::isfinite(bmin) || !std::isfinite(bmax)) return false;
+  auto ucoord = [&](double v) {
+    double s = vmax > vmin ? (v - vmin) / (vmax - vmin) : 0.0;
+    s = std::min(1.0, std::max(0.0, s));
+    return s * (double)(M - 1);
+  };
+  int64_t i0 = (int64_t)std::floor(ucoord(bmin)) - 1, i1 = (int64_t)std::ceil(ucoord(bmax)) + 1;
+  i0 = std::max<int64_t>(0, i0);
+  i1 = std::min<int64_t>(M - 1, i1);
+  for (int64_t i = i0; i <= i1; i++)
+    if (tf[4 * i + 3] != 0.0f) return false;
+  return true;
+}
+
+int64_t count_samples(const Camera& cam, const int64_t n[3], double step) {
+  const double hi[3] = {(double)(n[0] - 1), (double)(n[1] - 1), (double)(n[2] - 1)};
+  int64_t total = 0;
+  for (int v = 0; v < cam.H; v++)
+    for (int u = 0; u < cam.W; u++) {
+      double o[3], tin;
+      int64_t k;
+      pixel_origin(cam, u, v, o);
+      if (ray_lattice(o, cam.e3, hi, step, tin, k)) total += k;
+    }
+  return total;
+}
+
+}  // namespace vr

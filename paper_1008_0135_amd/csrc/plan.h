@@ -1,0 +1,66 @@
+// plan.h -- host-side planning of libvr (no GPU calls): sub-volume
+// partitions (regular grid and longest-axis split, paper Sec. 2.3), rendering
+// rectangles and depth order per view (paper Sec. 2.4, 2.5), empty-space
+// classification of bricks and nominal sample counts.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "vr_internal.h"
+
+namespace vr {
+
+struct Box {
+  int64_t lo[3], hi[3];  // ownership [lo, hi) per axis, [lo, hi] where closed
+  int32_t closed[3];
+};
+
+struct KdNode {
+  int32_t axis;   // split axis (internal nodes)
+  int64_t plane;  // split plane (low child owns < plane)
+  int32_t left, right;
+  int32_t leaf;   // brick index for leaves, -1 for internal nodes
+};
+
+struct Partition {
+  int32_t mode = VR_BRICK_GRID;
+  int64_t gsize[3] = {0, 0, 0};
+  int32_t gcount[3] = {0, 0, 0};
+  std::vector<Box> boxes;
+  std::vector<KdNode> nodes;  // longest-axis split tree (root = 0)
+};
+
+struct Rect {
+  int32_t x0, y0, w, h;  // w == 0 or h == 0: empty
+};
+
+// Regular grid: brick j along an axis owns [j*size, (j+1)*size); the last one
+// is closed at n-1; count = ceil((n-1)/size).  Box order: axis 1 fastest.
+bool make_grid(const int64_t n[3], const int64_t size[3], Partition& out, std::string& err);
+
+// Longest-axis recursive split into nparts boxes (leaves in depth-first, low
+// side first order).
+bool make_kd(const int64_t n[3], int32_t nparts, Partition& out, std::string& err);
+
+// Stored voxel range of a box: ownership box plus a 1-voxel ghost layer,
+// clipped to the volume.
+void stored_box(const Box& b, const int64_t n[3], int64_t slo[3], int64_t shi[3]);
+
+// Conservative pixel rectangle of the box's projection (corner bounding box
+// padded by one pixel, clipped to the image).
+Rect brick_rect(const Camera& cam, const Box& b);
+
+// Front-to-back order of all boxes for ray direction d.
+void depth_order(const Partition& p, const double d[3], std::vector<int32_t>& order);
+
+// True when every sample a brick with stored range [bmin, bmax] can produce
+// has zero opacity: all table alphas in [floor(u(bmin)) - 1, ceil(u(bmax)) + 1]
+// (clipped to [0, M-1]) are zero.  Skipping such a brick is bit-exact.
+bool brick_transparent(float bmin, float bmax, const float* tf_rgba, int32_t M, double vmin, double vmax);
+
+// Sum over pixels of the whole-volume lattice count (no ERT, no skipping).
+int64_t count_samples(const Camera& cam, const int64_t n[3], double step);
+
+}  // namespace vr

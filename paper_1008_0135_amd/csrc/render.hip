@@ -1,0 +1,155 @@
+// render.hip -- forward ray-casting and over-composite kernels for gfx950.
+//
+// March (paper Sec. 2 and 2.4): one lane per pixel ray of a brick's
+// rendering rectangle, wavefronts own TW x TH pixel tiles.  Each lane does
+// the ray setup in double precision (whole-volume box test, lattice count,
+// the brick's share [k0, k1) of the lattice), then marches its share in
+// single precision with brick-local coordinates: trilinear reconstruction from
+// four dword-pair loads, normalisation, a transfer-function lookup from LDS,
+// front-to-back emission-absorption and the early-termination test.  The
+// wavefront keeps issuing while any of its lanes is still marching.
+//
+// Composite (paper Sec. 2.5): one lane per output pixel walks the brick
+// images front to back and applies the over operator where its pixel lies
+// inside a brick's rectangle.
+#include "vr_internal.h"
+
+namespace vr {
+
+namespace {
+
+typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+
+__device__ __forceinline__ f2u ld_pair(const float* p) { return *reinterpret_cast<const f2u*>(p); }
+
+// Blocks of 256 lanes (4 wavefronts, 4 consecutive tiles).  Consecutive
+// hardware block ids go round-robin over the 8 XCDs; remap them so each XCD
+// receives one contiguous range of tiles (neighbouring tiles of the same brick
+// then share that XCD's L2).
+__device__ __forceinline__ int xcd_block(int nblk) {
+  const int per = (nblk + 7) >> 3;
+  return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+}
+
+template <int TW>
+__global__ __launch_bounds__(256) void k_march(MarchArgs a) {
+  extern __shared__ float4 s_tf[];
+  for (int i = threadIdx.x; i < a.M; i += 256) s_tf[i] = a.tf[i];
+  __syncthreads();
+
+  constexpr int TH = 64 / TW;
+  const int nblk = (a.ntiles + 3) >> 2;
+  const int lb = xcd_block(nblk);
+  if (lb >= nblk) return;
+  int tile = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+  if (tile >= a.ntiles) return;
+
+  // brick owning this tile: last entry with tile_begin <= tile
+  int lo = 0, hi = a.nbv - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a.bv[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const DevBrickView bvw = a.bv[lo];
+  const DevBrick br = a.bricks[bvw.brick];
+  const int t = tile - bvw.tile_begin;
+  const int tx = t % bvw.tiles_x, ty = t / bvw.tiles_x;
+  const int lane = threadIdx.x & 63;
+  const int lx = tx * TW + (lane % TW), ly = ty * TH + (lane / TW);
+  if (lx >= bvw.w || ly >= bvw.h) return;
+  const int u = bvw.x0 + lx, v = bvw.y0 + ly;
+
+  double o[3];
+  pixel_origin(a.cam, u, v, o);
+  const double* d = a.cam.e3;
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
+  double tin;
+  int64_t n;
+  if (ray_lattice(o, d, a.hi, a.step, tin, n)) {
+    int64_t k0, k1;
+    brick_krange(o, d, tin, a.step, n, br.lo, br.hi, br.closed, k0, k1);
+    if (k1 > k0) {
+      const double t0 = tin + ((double)k0 + 0.5) * a.step;
+      const float px = (float)(o[0] + t0 * d[0] - (double)br.lo[0]);
+      const float py = (float)(o[1] + t0 * d[1] - (double)br.lo[1]);
+      const float pz = (float)(o[2] + t0 * d[2] - (double)br.lo[2]);
+      const float sx = (float)(a.step * d[0]), sy = (float)(a.step * d[1]), sz = (float)(a.step * d[2]);
+      const int cnt = (int)(k1 - k0);
+      const float fM = (float)(a.M - 1);
+      const float* __restrict__ base = br.base;
+      const int ys = br.sy, zs = br.sz;
+      for (int j = 0; j < cnt; ++j) {
+        const float fj = (float)j;
+        const float qx = fmaf(fj, sx, px), qy = fmaf(fj, sy, py), qz = fmaf(fj, sz, pz);
+        const int ix = min(max((int)floorf(qx), br.clo[0]), br.chi[0]);
+        const int iy = min(max((int)floorf(qy), br.clo[1]), br.chi[1]);
+        const int iz = min(max((int)floorf(qz), br.clo[2]), br.chi[2]);
+        const float wx = qx - (float)ix, wy = qy - (float)iy, wz = qz - (float)iz;
+        const float* p = base + (iz * zs + iy * ys + ix);
+        const f2u a00 = ld_pair(p), a01 = ld_pair(p + ys), a10 = ld_pair(p + zs), a11 = ld_pair(p + zs + ys);
+        const float c00 = fmaf(wx, a00.y - a00.x, a00.x), c01 = fmaf(wx, a01.y - a01.x, a01.x);
+        const float c10 = fmaf(wx, a10.y - a10.x, a10.x), c11 = fmaf(wx, a11.y - a11.x, a11.x);
+        const float c0 = fmaf(wy, c01 - c00, c00), c1 = fmaf(wy, c11 - c10, c10);
+        const float val = fmaf(wz, c1 - c0, c0);
+        const float s = fminf(fmaxf((val - a.vmin) * a.inv_range, 0.f), 1.f);
+        const float uu = s * fM;
+        const int i = min((int)uu, a.M - 2);
+        const float w = uu - (float)i;
+        const float4 e0 = s_tf[i], e1 = s_tf[i + 1];
+        const float al = fmaf(w, e1.w - e0.w, e0.w);
+        const float Ta = T * al;
+        Cr = fmaf(Ta, fmaf(w, e1.x - e0.x, e0.x), Cr);
+        Cg = fmaf(Ta, fmaf(w, e1.y - e0.y, e0.y), Cg);
+        Cb = fmaf(Ta, fmaf(w, e1.z - e0.z, e0.z), Cb);
+        T = fmaf(-T, al, T);
+        if (1.f - T >= a.tau) break;
+      }
+    }
+  }
+  a.img[bvw.img_off + (int64_t)ly * bvw.w + lx] = make_float4(Cr, Cg, Cb, 1.f - T);
+}
+
+__global__ __launch_bounds__(256) void k_composite(CompArgs a) {
+  const int x = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int y = blockIdx.y * 16 + (threadIdx.x >> 4);
+  if (x >= a.W || y >= a.H) return;
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, A = 0.f;
+  for (int i = 0; i < a.n; ++i) {
+    const CompLayer L = a.layers[i];
+    const unsigned lx = (unsigned)(x - L.x0), ly = (unsigned)(y - L.y0);
+    if (lx < (unsigned)L.w && ly < (unsigned)L.h) {
+      const float4 c = L.rgba[(int64_t)ly * L.w + lx];
+      const float t = 1.f - A;
+      Cr = fmaf(t, c.x, Cr);
+      Cg = fmaf(t, c.y, Cg);
+      Cb = fmaf(t, c.z, Cb);
+      A = fmaf(t, c.w, A);
+    }
+  }
+  a.out[(int64_t)y * a.W + x] = make_float4(Cr, Cg, Cb, A);
+}
+
+}  // namespace
+
+hipError_t launch_march(const MarchArgs& a, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  const int nblk = (a.ntiles + 3) / 4;
+  const int grid = ((nblk + 7) / 8) * 8;
+  const size_t lds = sizeof(float4) * (size_t)a.M;
+  switch (a.tile_w) {
+    case 8: hipLaunchKernelGGL(k_march<8>, dim3(grid), dim3(256), lds, s, a); break;
+    case 16: hipLaunchKernelGGL(k_march<16>, dim3(grid), dim3(256), lds, s, a); break;
+    case 4: hipLaunchKernelGGL(k_march<4>, dim3(grid), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_composite(const CompArgs& a, hipStream_t s) {
+  dim3 grid((a.W + 15) / 16, (a.H + 15) / 16);
+  hipLaunchKernelGGL(k_composite, grid, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vr

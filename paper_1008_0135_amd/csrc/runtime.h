@@ -1,0 +1,121 @@
+// runtime.h -- host-side objects behind the opaque handles of vr.h and the
+// helpers the entry points share (errors, device guard, stream ordering,
+// table uploads, stage timers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "plan.h"
+#include "vr_internal.h"
+
+namespace vr {
+
+int fail(int code, const char* fmt, ...);
+void clear_error();
+
+#define VR_TRY(expr)                 \
+  do {                               \
+    int rc_ = (expr);                \
+    if (rc_ != VR_OK) return rc_;    \
+  } while (0)
+
+#define VR_HIP(call)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      (void)hipGetLastError();                                                          \
+      return ::vr::fail(VR_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));        \
+    }                                                                                   \
+  } while (0)
+
+// Makes `dev` current for the scope and restores the caller's device.
+struct DeviceGuard {
+  int prev = -1, target = -1;
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+};
+
+}  // namespace vr
+
+struct vr_ctx {
+  int device = 0;
+  // transfer function slot
+  float4* d_tf = nullptr;
+  int32_t tf_cap = 0, tf_m = 0;
+  std::vector<float> h_tf;
+  double tf_vmin = 0.0, tf_vmax = 0.0;
+  bool tf_set = false;
+  uint64_t tf_version = 0;
+  // brick-image arena and general scratch
+  void* d_arena = nullptr;
+  size_t arena_bytes = 0;
+  void* d_small = nullptr;
+  size_t small_bytes = 0;
+  void* d_scratch = nullptr;
+  size_t scratch_bytes = 0;
+  // per-call table uploads: pinned staging + device copy, reused round-robin
+  static constexpr int kRing = 4;
+  struct Slot {
+    void* h = nullptr;
+    void* d = nullptr;
+    size_t bytes = 0;
+    hipEvent_t copied = nullptr;
+    bool used = false;
+  } ring[kRing];
+  int ring_next = 0;
+  // calls on this context are ordered, whatever stream they use
+  hipEvent_t done = nullptr;
+  bool done_valid = false;
+  // stage timers
+  bool prof = false;
+  struct Timed {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> timed;
+  std::vector<hipEvent_t> event_pool;
+  hipStream_t prof_stream = nullptr;
+  // autotune cache: key -> tile edge
+  std::vector<std::pair<std::string, int32_t>> tune;
+  int32_t tune_waves_per_cu = 0;
+};
+
+struct vr_volume {
+  vr_ctx* ctx = nullptr;
+  int64_t n[3] = {0, 0, 0};
+  float* data = nullptr;
+  bool owned = false;
+  bool have_range = false;
+  float vmin = 0.f, vmax = 0.f;
+  int64_t nonfinite = 0;
+  vr::DevBrick whole;  // the whole volume as one brick (unbricked rendering)
+  bool bricked = false, materialized = false;
+  vr::Partition part;
+  std::vector<vr::DevBrick> bricks;
+  std::vector<vr_brick_desc> bdesc;
+  vr::DevBrick* d_bricks = nullptr;
+  float* d_store = nullptr;  // materialised brick storage
+  uint64_t version = 0;
+};
+
+namespace vr {
+
+int ctx_begin(vr_ctx* ctx, hipStream_t s);
+int ctx_end(vr_ctx* ctx, hipStream_t s);
+int stage_begin(vr_ctx* ctx, int stage, hipStream_t s);
+int stage_end(vr_ctx* ctx, hipStream_t s);
+int ensure_device(void** p, size_t* cap, size_t need);
+int upload_tables(vr_ctx* ctx, hipStream_t s, const void* data, size_t bytes, void** dev);
+int reduce_minmax(vr_ctx* ctx, const float* x, int64_t n, hipStream_t s, float out3[3]);
+int volume_range(vr_volume* vol, hipStream_t s);
+int check_view(const vr_view* v);
+int check_params(const vr_params* p);
+int resolve_window(vr_ctx* ctx, vr_volume* vol, hipStream_t s, double& vmin, double& vmax);
+void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, double vmin, double vmax,
+                       const float4* tf, int32_t M);
+
+}  // namespace vr

@@ -1,0 +1,172 @@
+// volume.hip -- once-per-cube kernels: global (min, max) with a non-finite
+// count (paper Sec. 2.2: each GPU reduces its portion, the results are
+// combined into the global range), per-brick (min, max) over each brick's
+// stored voxels, and box copies (sub-cube upload, brick materialisation).
+#include "vr_internal.h"
+
+namespace vr {
+
+namespace {
+
+struct MinMaxPart {
+  float mn, mx;
+  uint32_t bad, pad;
+};
+
+__device__ __forceinline__ void acc(float v, float& mn, float& mx, uint32_t& bad) {
+  if (!isfinite(v)) {
+    bad++;
+    return;
+  }
+  mn = fminf(mn, v);
+  mx = fmaxf(mx, v);
+}
+
+__device__ __forceinline__ void block_reduce(float& mn, float& mx, uint32_t& bad) {
+  for (int off = 32; off > 0; off >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, off));
+    mx = fmaxf(mx, __shfl_xor(mx, off));
+    bad += __shfl_xor(bad, off);
+  }
+  __shared__ float smn[4], smx[4];
+  __shared__ uint32_t sbad[4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    smn[w] = mn;
+    smx[w] = mx;
+    sbad[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x >> 6); i++) {
+      mn = fminf(mn, smn[i]);
+      mx = fmaxf(mx, smx[i]);
+      bad += sbad[i];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const float* __restrict__ x, int64_t n, MinMaxPart* part) {
+  float mn = INFINITY, mx = -INFINITY;
+  uint32_t bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  const bool al = ((uintptr_t)x & 15) == 0;
+  if (al) {
+    const int64_t n4 = n >> 2;
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+      const float4 v = x4[i];
+      acc(v.x, mn, mx, bad);
+      acc(v.y, mn, mx, bad);
+      acc(v.z, mn, mx, bad);
+      acc(v.w, mn, mx, bad);
+    }
+    for (int64_t i = (n4 << 2) + (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) acc(x[i], mn, mx, bad);
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) acc(x[i], mn, mx, bad);
+  }
+  block_reduce(mn, mx, bad);
+  if (threadIdx.x == 0) part[blockIdx.x] = MinMaxPart{mn, mx, bad, 0};
+}
+
+__global__ __launch_bounds__(256) void k_minmax_final(const MinMaxPart* part, int nb, float* out3) {
+  float mn = INFINITY, mx = -INFINITY;
+  uint32_t bad = 0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    mn = fminf(mn, part[i].mn);
+    mx = fmaxf(mx, part[i].mx);
+    bad += part[i].bad;
+  }
+  block_reduce(mn, mx, bad);
+  if (threadIdx.x == 0) {
+    out3[0] = mn;
+    out3[1] = mx;
+    out3[2] = (float)bad;
+  }
+}
+
+// One block per (brick, group of z-planes); partial (min, max) per block.
+__global__ __launch_bounds__(256) void k_brick_minmax(const float* __restrict__ vol, int64_t n1, int64_t n2,
+                                                      const int64_t* __restrict__ boxes, int zgroups,
+                                                      int zper, float2* part) {
+  const int b = blockIdx.x / zgroups, g = blockIdx.x % zgroups;
+  const int64_t* bx = boxes + 6 * b;
+  const int64_t x0 = bx[0], y0 = bx[1], z0 = bx[2], x1 = bx[3], y1 = bx[4], z1 = bx[5];
+  const int64_t za = z0 + (int64_t)g * zper;
+  const int64_t zb = min(z1, za + zper - 1);
+  float mn = INFINITY, mx = -INFINITY;
+  uint32_t bad = 0;
+  const int64_t w = x1 - x0 + 1, h = y1 - y0 + 1;
+  for (int64_t z = za; z <= zb; z++) {
+    for (int64_t r = threadIdx.x / 64; r < h; r += 4) {
+      const float* row = vol + (z * n2 + (y0 + r)) * n1 + x0;
+      for (int64_t i = threadIdx.x & 63; i < w; i += 64) acc(row[i], mn, mx, bad);
+    }
+  }
+  block_reduce(mn, mx, bad);
+  if (threadIdx.x == 0) part[blockIdx.x] = make_float2(mn, mx);
+}
+
+__global__ void k_brick_minmax_final(const float2* part, int nb, int zgroups, float* out2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  float mn = INFINITY, mx = -INFINITY;
+  for (int g = 0; g < zgroups; g++) {
+    const float2 p = part[b * zgroups + g];
+    mn = fminf(mn, p.x);
+    mx = fmaxf(mx, p.y);
+  }
+  out2[2 * b] = mn;
+  out2[2 * b + 1] = mx;
+}
+
+// dst[z][y][x] = src[so3 + z][so2 + y][so1 + x] for the dst box dn.
+__global__ __launch_bounds__(256) void k_copy_box(const float* __restrict__ src, int64_t s1, int64_t s2,
+                                                  int64_t o1, int64_t o2, int64_t o3, float* __restrict__ dst,
+                                                  int64_t d1, int64_t d2, int64_t d3) {
+  const int64_t rows = d2 * d3;
+  for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int64_t z = r / d2, y = r % d2;
+    const float* srow = src + ((o3 + z) * s2 + (o2 + y)) * s1 + o1;
+    float* drow = dst + r * d1;
+    for (int64_t i = threadIdx.x; i < d1; i += 256) drow[i] = srow[i];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax, dim3(nblocks), dim3(256), 0, s, x, n, reinterpret_cast<MinMaxPart*>(partial));
+  return hipGetLastError();
+}
+
+hipError_t launch_minmax_final(const float* partial, int32_t nblocks, float* out3, hipStream_t s) {
+  hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, reinterpret_cast<const MinMaxPart*>(partial),
+                     nblocks, out3);
+  return hipGetLastError();
+}
+
+// `boxes` is a device array of nb x (slo1, slo2, slo3, shi1, shi2, shi3);
+// `out2` receives nb (min, max) pairs.  Uses out2-adjacent scratch: the
+// partial buffer is allocated by the caller as `scratch` of nb*zgroups float2.
+hipError_t launch_brick_minmax_parts(const float* vol, const int64_t n[3], const int64_t* boxes, int32_t nb,
+                                     int zgroups, int zper, float* scratch, float* out2, hipStream_t s) {
+  hipLaunchKernelGGL(k_brick_minmax, dim3(nb * zgroups), dim3(256), 0, s, vol, n[0], n[1], boxes, zgroups, zper,
+                     reinterpret_cast<float2*>(scratch));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_brick_minmax_final, dim3((nb + 127) / 128), dim3(128), 0, s,
+                     reinterpret_cast<const float2*>(scratch), nb, zgroups, out2);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
+                           const int64_t dn[3], hipStream_t s) {
+  const int64_t rows = dn[1] * dn[2];
+  const int grid = (int)(rows < 65536 ? rows : 65536);
+  hipLaunchKernelGGL(k_copy_box, dim3(grid), dim3(256), 0, s, src, sn[0], sn[1], so[0], so[1], so[2], dst, dn[0],
+                     dn[1], dn[2]);
+  return hipGetLastError();
+}
+
+}  // namespace vr

@@ -1,0 +1,196 @@
+// vr_internal.h -- internal types of libvr shared by the host runtime and the
+// gfx950 kernels: camera and ray setup (double precision, used on both sides
+// so the host plan and the device launch agree bit for bit), brick tables and
+// POD kernel argument blocks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "vr.h"
+
+namespace vr {
+
+// ---------------------------------------------------------------- camera
+// Orthographic camera of one view (paper Sec. 2.2: a render request carries
+// the transformation and projection).  Pixel pitch is S/W voxels on both axes.
+struct Camera {
+  double c[3];          // box centre
+  double e1[3], e2[3];  // image axes
+  double e3[3];         // ray direction
+  double S;             // image width in voxels
+  double Sy;            // image height in voxels = S*H/W
+  int32_t W, H;
+  int32_t pad[2];
+};
+
+__host__ __device__ inline void make_camera(const vr_view& v, const int64_t n[3], Camera& cam) {
+  double diag = 0.0;
+  for (int i = 0; i < 3; i++) {
+    cam.c[i] = 0.5 * (double)(n[i] - 1);
+    diag += (double)(n[i] - 1) * (double)(n[i] - 1);
+    cam.e1[i] = v.R[i];
+    cam.e2[i] = v.R[3 + i];
+    cam.e3[i] = v.R[6 + i];
+  }
+  cam.S = v.extent > 0.0 ? v.extent : sqrt(diag);
+  cam.Sy = cam.S * (double)v.H / (double)v.W;
+  cam.W = v.W;
+  cam.H = v.H;
+  cam.pad[0] = cam.pad[1] = 0;
+}
+
+// Ray origin of pixel (u, v); the direction is cam.e3.
+__host__ __device__ inline void pixel_origin(const Camera& cam, int u, int v, double o[3]) {
+#pragma clang fp contract(off)
+  double x = (((double)u + 0.5) / (double)cam.W - 0.5) * cam.S;
+  double y = (((double)v + 0.5) / (double)cam.H - 0.5) * cam.S * (double)cam.H / (double)cam.W;
+  for (int i = 0; i < 3; i++) o[i] = cam.c[i] + x * cam.e1[i] + y * cam.e2[i] - cam.S * cam.e3[i];
+}
+
+// Whole-volume ray/box test (slab method against the closed box [0, hi]) and
+// lattice count n = max(0, ceil((t_out - t_in)/step - 1/2)): samples sit at
+// t_k = t_in + (k + 1/2) step for k in [0, n) (paper Sec. 2.4: entry and exit
+// points of the ray in the data's bounding box).  Returns false on a miss.
+__host__ __device__ inline bool ray_lattice(const double o[3], const double d[3], const double hi[3],
+                                            double step, double& tin, int64_t& n) {
+#pragma clang fp contract(off)
+  double a = -INFINITY, b = INFINITY;
+  for (int i = 0; i < 3; i++) {
+    if (d[i] == 0.0) {
+      if (o[i] < 0.0 || o[i] > hi[i]) return false;
+      continue;
+    }
+    double t1 = (0.0 - o[i]) / d[i], t2 = (hi[i] - o[i]) / d[i];
+    double tn = t1 < t2 ? t1 : t2, tf = t1 < t2 ? t2 : t1;
+    if (tn > a) a = tn;
+    if (tf < b) b = tf;
+  }
+  if (!(a < b)) return false;
+  tin = a;
+  double X = (b - a) / step - 0.5;
+  double c = ceil(X);
+  n = c > 0.0 ? (int64_t)c : 0;
+  return n > 0;
+}
+
+// Lattice index at which the ray crosses the plane x_i = P, as a real number:
+// sample k lies at or beyond the plane (in the direction of d_i > 0) iff
+// k >= X.  Every brick that shares the plane evaluates this same expression,
+// so the partition of the lattice between neighbours is exact.
+__host__ __device__ inline double plane_index(double P, double o, double d, double tin, double step) {
+#pragma clang fp contract(off)
+  return ((P - o) / d - tin) / step - 0.5;
+}
+
+__host__ __device__ inline int64_t clamp_idx(double x, int64_t lo, int64_t hi) {
+  // x is a real-valued index already rounded by ceil/floor; clamp before converting
+  if (!(x > (double)lo)) return lo;
+  if (!(x < (double)hi)) return hi;
+  return (int64_t)x;
+}
+
+// Samples [k0, k1) of the whole-volume lattice owned by the box
+// lo <= p < hi (p <= hi along closed axes).  n is the lattice count.
+__host__ __device__ inline void brick_krange(const double o[3], const double d[3], double tin, double step,
+                                             int64_t n, const int32_t lo[3], const int32_t hi[3], int closed,
+                                             int64_t& k0, int64_t& k1) {
+  int64_t a = 0, b = n;
+  for (int i = 0; i < 3; i++) {
+    bool cl = (closed >> i) & 1;
+    if (d[i] == 0.0) {
+      bool in = o[i] >= (double)lo[i] && (cl ? o[i] <= (double)hi[i] : o[i] < (double)hi[i]);
+      if (!in) {
+        k0 = k1 = 0;
+        return;
+      }
+      continue;
+    }
+    double Xl = plane_index((double)lo[i], o[i], d[i], tin, step);
+    double Xh = plane_index((double)hi[i], o[i], d[i], tin, step);
+    int64_t s, e;  // this axis admits k in [s, e)
+    if (d[i] > 0.0) {
+      s = clamp_idx(ceil(Xl), -1, n + 1);
+      e = cl ? clamp_idx(floor(Xh) + 1.0, -1, n + 1) : clamp_idx(ceil(Xh), -1, n + 1);
+    } else {
+      s = cl ? clamp_idx(ceil(Xh), -1, n + 1) : clamp_idx(floor(Xh) + 1.0, -1, n + 1);
+      e = clamp_idx(floor(Xl) + 1.0, -1, n + 1);
+    }
+    if (s > a) a = s;
+    if (e < b) b = e;
+  }
+  k0 = a;
+  k1 = b > a ? b : a;
+}
+
+// ---------------------------------------------------------------- brick tables
+// Static per-brick record (one per brick of the partition).
+struct DevBrick {
+  const float* base;      // storage address of voxel (lo1, lo2, lo3)
+  int32_t sy, sz;         // storage strides (elements) along axes 2 and 3
+  int32_t lo[3], hi[3];   // ownership box
+  int32_t closed;         // bit i: closed along axis i
+  int32_t clo[3], chi[3]; // clamps of the local cell index (global [0, n-2] shifted by -lo)
+  float vmin, vmax;       // range of the stored voxels
+  int32_t pad;
+};
+
+// Per (view, rendered brick) record, in launch order.
+struct DevBrickView {
+  int32_t brick;       // index into the DevBrick table
+  int32_t x0, y0, w, h;
+  int32_t tiles_x;     // tiles along x of the rectangle
+  int32_t tile_begin;  // first work-item (tile) index of this brick
+  int32_t pad;
+  int64_t img_off;     // offset (in pixels) of the brick image in the image arena
+};
+
+// One layer of the over-composite, front to back.
+struct CompLayer {
+  int32_t x0, y0, w, h;
+  const float4* rgba;
+};
+
+// ---------------------------------------------------------------- kernel arguments
+struct MarchArgs {
+  Camera cam;
+  double hi[3];          // n - 1 per axis (whole-volume box)
+  double step;
+  float tau;             // ERT threshold (ert == 0: off)
+  int32_t ert;
+  float vmin, inv_range; // normalisation window (inv_range = 0 when vmax == vmin)
+  int32_t M;             // table entries
+  int32_t nbv;           // rendered bricks in this launch
+  int32_t ntiles;        // total work items (tiles)
+  int32_t tile_w, tile_h;
+  int32_t pad;
+  const float4* tf;      // [M] RGBA
+  const DevBrick* bricks;
+  const DevBrickView* bv;
+  float4* img;           // image arena (or the output frame)
+};
+
+struct CompArgs {
+  const CompLayer* layers;
+  int32_t n;
+  int32_t W, H;
+  int32_t pad;
+  float4* out;
+};
+
+// Launchers (defined in the .hip files); all asynchronous on `s`.
+hipError_t launch_march(const MarchArgs& a, hipStream_t s);
+hipError_t launch_composite(const CompArgs& a, hipStream_t s);
+hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s);
+hipError_t launch_minmax_final(const float* partial, int32_t nblocks, float* out3, hipStream_t s);
+// Per-brick (min, max) over stored voxel boxes: boxes is a device array of
+// nb x (slo1, slo2, slo3, shi1, shi2, shi3); each brick's z range is split into
+// zgroups groups of zper planes; scratch holds nb*zgroups float2 partials.
+hipError_t launch_brick_minmax_parts(const float* vol, const int64_t n[3], const int64_t* boxes, int32_t nb,
+                                     int zgroups, int zper, float* scratch, float* out2, hipStream_t s);
+hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
+                           const int64_t dn[3], hipStream_t s);
+
+}  // namespace vr

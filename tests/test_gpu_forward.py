@@ -1,0 +1,241 @@
+"""GPU parity of the forward path (through the C ABI) against the FP64 oracle.
+
+Covers: global min/max and per-brick ranges, the whole-volume render (the
+64^3 two-view case), bricked renders with local early termination (grid and
+longest-axis partitions, ragged edges), bricked == whole without ERT,
+bit-identity of the sort-last halves, of empty-space skipping and of
+materialised bricks, the 1 GiB / 1024^2 / 16-view bricked case on strided
+rays, and error paths.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1008_0135_amd as vr
+import synth
+from gpu_util import parity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = vr.vr_create(0)
+    yield c
+    vr.vr_destroy(c)
+
+
+def _upload(ctx, vol):
+    n3, n2, n1 = vol.shape
+    d = torch.from_numpy(np.ascontiguousarray(vol)).cuda()
+    h = vr.vr_volume_create(ctx, d, (n1, n2, n3))
+    return h
+
+
+def _render(ctx, h, views, W, H, params, extent=0.0):
+    out = torch.empty((len(views), H, W, 4), device="cuda")
+    out.fill_(-7.0)
+    vr.vr_render(ctx, h, [vr.make_view(R, W, H, extent) for R in views], params, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+# ------------------------------------------------------------------ ranges
+def test_minmax_and_brick_ranges(ctx):
+    _say("minmax: 96x80x70 cube, grid bricks 32^3")
+    vol = synth.cube(96, 80, 70, seed=7, n_sources=5, sigma_range=(1.5, 3.0))
+    h = _upload(ctx, vol)
+    mn, mx = vr.vr_volume_minmax(h)
+    assert mn == float(vol.min()) and mx == float(vol.max())
+    vr.vr_volume_brick(h, vr.grid_spec((32, 32, 32)))
+    for d in vr.vr_volume_brick_info(h):
+        a, b = oracle.box_minmax(vol, d.slo, d.shi)
+        assert d.vmin == a and d.vmax == b
+    vr.vr_volume_destroy(h)
+
+
+def test_nonfinite_rejected(ctx):
+    _say("non-finite voxel rejected at upload")
+    vol = np.zeros((8, 8, 8), np.float32)
+    vol[3, 4, 5] = np.nan
+    with pytest.raises(vr.VRError) as e:
+        _upload(ctx, vol)
+    assert e.value.code == vr.VR_ENONFINITE
+
+
+def test_subcube_upload(ctx):
+    _say("sub-cube upload from host and device")
+    vol = synth.cube(40, 30, 20, seed=8, n_sources=2, sigma_range=(1.5, 2.0))
+    so, se = (5, 3, 2), (17, 20, 11)
+    want = vol[2:13, 3:23, 5:22]
+    for src in (vol, torch.from_numpy(vol).cuda()):
+        h = vr.vr_volume_create(ctx, src, (40, 30, 20), sub_origin=so, sub_extent=se)
+        assert vr.vr_volume_dims(h) == se
+        mn, mx = vr.vr_volume_minmax(h)
+        assert mn == float(want.min()) and mx == float(want.max())
+        vr.vr_volume_destroy(h)
+
+
+# ------------------------------------------------------------------ whole volume
+@pytest.mark.parametrize("tile", [8, 4, 16])
+def test_c1_two_views_whole_volume(ctx, tile):
+    _say(f"C1 64^3, 2 views, 128^2, tile {tile}")
+    vol = synth.config_cube("C1")
+    tf = synth.tf_ramp(256)
+    h = _upload(ctx, vol)
+    mn, mx = vr.vr_volume_minmax(h)
+    vr.vr_tf_set(ctx, tf)
+    views = synth.c1_views()
+    got = _render(ctx, h, views, 128, 128, vr.make_params(tile=tile))
+    ref = oracle.render(vol, tf, views, 128, 128, mn, mx, tau=0.99)
+    s = parity(got, ref, label="C1")
+    _say(f"C1 parity {s}")
+    vr.vr_volume_destroy(h)
+
+
+@pytest.mark.parametrize("seed,tau,M", [(11, 0.9, 64), (12, 2.0, 256), (13, 0.5, 7)])
+def test_whole_volume_random(ctx, seed, tau, M):
+    _say(f"whole volume, seed {seed}, tau {tau}, M {M}")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dims = (37, 29, 45)
+    vol = synth.cube(*dims, seed=seed, n_sources=4, sigma_range=(1.5, 3.0))
+    tf = synth.tf_random(rng, m=M, amax=0.3)
+    h = _upload(ctx, vol)
+    mn, mx = vr.vr_volume_minmax(h)
+    wmin, wmax = mn + 0.3 * (mx - mn) * 0.1, mx - 0.2 * (mx - mn)
+    vr.vr_tf_set(ctx, tf, wmin, wmax)
+    views = synth.random_views(3, seed)
+    got = _render(ctx, h, views, 77, 61, vr.make_params(tau=tau))
+    ref = oracle.render(vol, tf, views, 77, 61, wmin, wmax, tau=tau)
+    parity(got, ref, label=f"random {seed}")
+    vr.vr_volume_destroy(h)
+
+
+def test_degenerate_window_and_extent(ctx):
+    _say("vmax == vmin window, explicit extent, 1x1 and 3x200 images")
+    vol = synth.cube(16, 18, 20, seed=14, n_sources=1, sigma_range=(1.5, 2.0))
+    tf = synth.tf_colour(16)
+    h = _upload(ctx, vol)
+    vr.vr_tf_set(ctx, tf, 0.5, 0.5)
+    for W, H in ((1, 1), (3, 200), (200, 3)):
+        views = synth.random_views(1, W * 1000 + H)
+        got = _render(ctx, h, views, W, H, vr.make_params(tau=0.95), extent=12.5)
+        ref = oracle.render(vol, tf, views, W, H, 0.5, 0.5, tau=0.95, extent=12.5)
+        parity(got, ref, label=f"{W}x{H}")
+    vr.vr_volume_destroy(h)
+
+
+# ------------------------------------------------------------------ bricked
+@pytest.mark.parametrize("kind,arg", [("grid", (32, 32, 48)), ("grid", (17, 23, 29)), ("kd", 5), ("kd", 8)])
+def test_bricked_local_ert_parity(ctx, kind, arg):
+    _say(f"bricked {kind} {arg}: 100x90x120 cube, 3 views, 160x144")
+    dims = (100, 90, 120)
+    vol = synth.cube(*dims, seed=21, n_sources=12, sigma_range=(2.0, 4.0))
+    tf = synth.tf_ramp(256)
+    tf[:, 3] = np.minimum(1.0, tf[:, 3] * 8)
+    h = _upload(ctx, vol)
+    mn, mx = vr.vr_volume_minmax(h)
+    spec = vr.grid_spec(arg) if kind == "grid" else vr.kd_spec(arg)
+    vr.vr_volume_brick(h, spec)
+    vr.vr_tf_set(ctx, tf)
+    views = synth.random_views(3, 22)
+    got = _render(ctx, h, views, 160, 144, vr.make_params(tau=0.99))
+    bricks = {"grid": arg} if kind == "grid" else oracle.kd_boxes(dims, arg)
+    ref = oracle.render(vol, tf, views, 160, 144, mn, mx, tau=0.99, bricks=bricks)
+    s = parity(got, ref, label=f"bricked {kind}")
+    _say(f"parity {s}")
+    vr.vr_volume_destroy(h)
+
+
+def test_bricked_equals_whole_without_ert(ctx):
+    _say("bricked (2x2x2) vs whole oracle, ERT off")
+    dims = (128, 128, 256)
+    vol = synth.cube(*dims, seed=23, n_sources=20, sigma_range=(2.0, 5.0))
+    tf = synth.tf_colour(256)
+    h = _upload(ctx, vol)
+    mn, mx = vr.vr_volume_minmax(h)
+    vr.vr_volume_brick(h, vr.grid_spec((64, 64, 128)))
+    vr.vr_tf_set(ctx, tf)
+    views = synth.random_views(2, 24)
+    got = _render(ctx, h, views, 256, 256, vr.make_params(tau=2.0))
+    ref = oracle.render(vol, tf, views, 256, 256, mn, mx, tau=2.0)
+    parity(got, ref, label="bricked vs whole")
+    vr.vr_volume_destroy(h)
+
+
+def test_sort_last_halves_and_invariances(ctx):
+    _say("render_bricks + composite == render; ESS and materialise bit-identical")
+    dims = (120, 100, 90)
+    vol = synth.cube(*dims, seed=25, n_sources=10, sigma_range=(2.0, 4.0))
+    mnv, mxv = float(vol.min()), float(vol.max())
+    tf = synth.tf_noise_suppress(mnv, mxv, thresh=4.0)
+    h = _upload(ctx, vol)
+    vr.vr_volume_brick(h, vr.grid_spec((32, 32, 32)))
+    vr.vr_tf_set(ctx, tf)
+    R = synth.random_views(1, 26)[0]
+    W, H = 150, 130
+    view = vr.make_view(R, W, H)
+    p_ess = vr.make_params(ess=1)
+    p_all = vr.make_params(ess=0)
+    a = _render(ctx, h, [R], W, H, p_ess)
+    b = _render(ctx, h, [R], W, H, p_all)
+    assert np.array_equal(a, b)
+    imgs, order = vr.vr_render_bricks(ctx, h, view, p_all)
+    out = torch.empty((H, W, 4), device="cuda")
+    vr.vr_composite(ctx, imgs, order, W, H, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), b[0])
+    nb = len(vr.vr_volume_brick_info(h))
+    imgs_e, _ = vr.vr_render_bricks(ctx, h, view, p_ess)
+    assert len(imgs_e) < len(imgs) <= nb  # some bricks skipped as transparent
+    vr.vr_volume_brick(h, vr.grid_spec((32, 32, 32), materialize=True))
+    c = _render(ctx, h, [R], W, H, p_ess)
+    assert np.array_equal(a, c)
+    ref = oracle.render(vol, tf, [R], W, H, mnv, mxv, tau=0.99, bricks={"grid": (32, 32, 32)})
+    parity(a, ref, label="ESS case")
+    vr.vr_volume_destroy(h)
+
+
+def test_composite_validation(ctx):
+    _say("composite argument checks")
+    out = torch.empty((8, 8, 4), device="cuda")
+    img = torch.zeros((4, 4, 4), device="cuda")
+    bi = vr.vr_brick_image(0, 6, 6, 4, 4, 0, img.data_ptr())
+    with pytest.raises(vr.VRError) as e:
+        vr.vr_composite(ctx, [bi], None, 8, 8, out)
+    assert e.value.code == vr.VR_EINVAL
+    vr.vr_composite(ctx, [], None, 8, 8, out)
+    torch.cuda.synchronize()
+    assert float(out.abs().max()) == 0.0
+
+
+# ------------------------------------------------------------------ the 1 GiB bricked case
+def test_c2_full_size_strided_rays(ctx):
+    """512x512x1024, 2x2x2 bricks, 1024^2, 16 views: every 16th row and column vs the oracle."""
+    _say("C2: generating 1 GiB cube")
+    c = synth.CONFIGS["C2"]
+    vol = synth.config_cube("C2")
+    tf = synth.tf_ramp(256)
+    h = _upload(ctx, vol)
+    mn, mx = vr.vr_volume_minmax(h)
+    vr.vr_volume_brick(h, vr.grid_spec(c["bricks"]))
+    vr.vr_tf_set(ctx, tf)
+    views = synth.random_views(c["nviews"], c["view_seed"])
+    W, H = c["image"]
+    _say("C2: rendering 16 views on the GPU")
+    got = _render(ctx, h, views, W, H, vr.make_params())
+    vv, yy, xx = np.meshgrid(np.arange(len(views)), np.arange(3, H, 16), np.arange(5, W, 16), indexing="ij")
+    _say(f"C2: oracle on {vv.size} rays")
+    ref = oracle.render_rays(vol, tf, views, W, H, vv.ravel(), xx.ravel(), yy.ravel(), mn, mx, tau=0.99,
+                             bricks={"grid": c["bricks"]})
+    s = parity(got[vv.ravel(), yy.ravel(), xx.ravel()], ref, label="C2 strided")
+    _say(f"C2 parity {s}")
+    assert np.isfinite(got).all() and (got >= 0).all() and (got <= 1.0 + 1e-6).all()
+    vr.vr_volume_destroy(h)
