@@ -302,18 +302,31 @@ typedef struct {
   int32_t waves_per_cu;  /* chosen persistent-grid occupancy (batched path) */
   double ms;             /* best measured time */
   double ms_default;     /* time with the defaults */
+  int32_t lds_budget;    /* chosen LDS floats per slab box (LDS-staged march) */
+  int32_t march_mode;    /* 0: LDS-staged slabs where they fit, 1: gathers */
 } vr_tune_result;
 
 /*
- * Time candidate tile shapes for rendering `view` of `vol` (and persistent
- * grid sizes for the batched path) and store the fastest in the context's
- * cache, keyed by volume size class and image size; later renders with
- * p->tile = 0 use it.  The cache is also written to the file named by the
- * environment variable VR_TUNE_CACHE when set.  Synchronises.
- * Errors: VR_EINVAL, VR_ESTATE (no transfer function), VR_EHIP.
+ * Time candidate launch shapes for rendering `view` of `vol` -- wavefront
+ * tile (4x16, 8x8, 16x4 pixels), LDS budget of the slab-staged march, or the
+ * gather march -- and store the fastest in the context's cache, keyed by the
+ * volume's size class (floor(log2) per axis), bricked or not, and the image
+ * size; later renders with p->tile = 0 on that key use it.  The cache is read
+ * from and written to the file named by the environment variable
+ * VR_TUNE_CACHE when set.  Synchronises.
+ * Errors: VR_EINVAL, VR_ESTATE (no transfer function), VR_ENOMEM, VR_EHIP.
  */
 int vr_autotune(vr_ctx *ctx, const vr_volume *vol, const vr_view *view, const vr_params *p,
                 vr_tune_result *out, uintptr_t stream);
+
+/*
+ * Time the batched launch of these requests with persistent grids of 2, 4, 8,
+ * 16 and 32 wavefronts per compute unit, keep the fastest for later batched
+ * calls on this context (and in VR_TUNE_CACHE), and leave *cache holding the
+ * graph of the chosen grid.  Synchronises.  Errors: as vr_render_batch.
+ */
+int vr_autotune_batch(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_params *p, vr_batch **cache,
+                      vr_tune_result *out, uintptr_t stream);
 
 /* ------------------------------------------------------------------ host-only helpers */
 /*

@@ -71,7 +71,8 @@ class vr_request(C.Structure):
 
 
 class vr_tune_result(C.Structure):
-    _fields_ = [("tile", C.c_int32), ("waves_per_cu", C.c_int32), ("ms", C.c_double), ("ms_default", C.c_double)]
+    _fields_ = [("tile", C.c_int32), ("waves_per_cu", C.c_int32), ("ms", C.c_double), ("ms_default", C.c_double),
+                ("lds_budget", C.c_int32), ("march_mode", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -105,6 +106,7 @@ _SIGS = {
     "vr_render_batch": (_I, [_P, _P, _I32, _P, _P, _U]),
     "vr_batch_destroy": (_I, [_P]),
     "vr_autotune": (_I, [_P, _P, _P, _P, _P, _U]),
+    "vr_autotune_batch": (_I, [_P, _P, _I32, _P, _P, _P, _U]),
     "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P]),
     "vr_count_samples": (_I, [_P, _P, _D, _P]),
     "vr_partition": (_I, [_P, _P, _P, _P]),
@@ -330,6 +332,27 @@ def vr_autotune(ctx, vol, view, params, stream=None):
     r = vr_tune_result()
     _check(lib().vr_autotune(ctx, vol, C.byref(view), C.byref(params), C.byref(r), _stream(stream)), "vr_autotune")
     return r
+
+
+def vr_autotune_batch(ctx, reqs, params, cache=None, stream=None):
+    """Returns (tune result, cache handle)."""
+    arr = (vr_request * len(reqs))(*reqs)
+    h = C.c_void_p(cache)
+    r = vr_tune_result()
+    _check(lib().vr_autotune_batch(ctx, arr, len(reqs), C.byref(params), C.byref(h), C.byref(r), _stream(stream)),
+           "vr_autotune_batch")
+    return r, h.value
+
+
+def make_request(vol, R, W, H, tf, vmin, vmax, out, extent=0.0):
+    q = vr_request()
+    q.vol = vol
+    q.view = make_view(R, W, H, extent)
+    q.tf = _ptr(tf)
+    q.m = int(tf.shape[0])
+    q.vmin, q.vmax = float(vmin), float(vmax)
+    q.out = _ptr(out)
+    return q
 
 
 def vr_plan_view(dims, spec, view, capacity=65536):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -250,6 +251,12 @@ int vr_create(int device, vr_ctx** out) {
   vr_ctx* ctx = new (std::nothrow) vr_ctx();
   if (!ctx) return fail(VR_ENOMEM, "out of host memory");
   ctx->device = device;
+  if (const char* m = std::getenv("VR_MARCH")) ctx->march_mode = std::strcmp(m, "gather") == 0 ? 1 : 0;
+  if (const char* b = std::getenv("VR_LDS_BUDGET")) {
+    const long v = std::strtol(b, nullptr, 10);
+    if (v >= 256 && v <= 32768) ctx->lds_budget = (int32_t)v;
+  }
+  tune_load(ctx);
   if (hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess) {
     delete ctx;
     return fail(VR_EHIP, "hipEventCreate failed");

@@ -69,7 +69,11 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   VR_TRY(resolve_window(ctx, vol, s, vmin, vmax));
   MarchArgs base;
   std::memset(&base, 0, sizeof base);
-  fill_march_common(base, vol, p, vmin, vmax, ctx->d_tf, ctx->tf_m);
+  int32_t tuned_tile, budget, mode;
+  tuned_shape(ctx, vol, W, H, p, tuned_tile, budget, mode);
+  vr_params pt = *p;
+  pt.tile = tuned_tile;
+  fill_march_common(base, vol, &pt, vmin, vmax, ctx->d_tf, ctx->tf_m);
   const int32_t tw = base.tile_w, th = base.tile_h;
 
   std::vector<ViewPlan> plans((size_t)nviews);
@@ -143,8 +147,11 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       a.img = reinterpret_cast<float4*>(out);
     }
     if (extras) extras->prepare(a, v);
+    bool lds = false;
+    if (!extras && mode == 0) lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
+    a.lds_budget = budget;
     VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
-    VR_HIP(extras ? extras->launch(a, s) : launch_march(a, s));
+    VR_HIP(extras ? extras->launch(a, s) : (lds ? launch_march_lds(a, s) : launch_march(a, s)));
     VR_TRY(stage_end(ctx, s));
     if (bricked && out) {
       CompArgs c;
@@ -218,7 +225,8 @@ int vr_render_bricks(vr_ctx* ctx, const vr_volume* cvol, const vr_view* view, co
   Camera cam;
   make_camera(*view, vol->n, cam);
   ViewPlan vp;
-  const int32_t tw = p->tile ? p->tile : 8;
+  int32_t tw, budget, mode;
+  tuned_shape(ctx, vol, view->W, view->H, p, tw, budget, mode);
   plan_bricked_view(vol, cam, p, tw, ctx->h_tf.data(), ctx->tf_m, vmin, vmax, vp);
   if ((int32_t)vp.bv.size() > *nimg)
     return fail(VR_EINVAL, "capacity %d below the %d rendered bricks", *nimg, (int)vp.bv.size());

@@ -187,6 +187,39 @@ bool brick_transparent(float bmin, float bmax, const float* tf, int32_t M, doubl
   return true;
 }
 
+bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int32_t& axis, int32_t& T) {
+  const double p = cam.S / (double)cam.W;  // pixel pitch in voxels
+  double best = INFINITY;
+  bool found = false;
+  for (int b = 1; b <= 2; b++) {
+    const int g = 3 - b;
+    const double db = cam.e3[b];
+    if (std::fabs(db) < 1e-3) continue;
+    const double rf = cam.e3[0] / db, rg = cam.e3[g] / db;
+    // footprint of the tile's corner rays on one plane of constant axis b
+    const double Wf = p * ((tw - 1) * std::fabs(cam.e1[0] - cam.e1[b] * rf) + (th - 1) * std::fabs(cam.e2[0] - cam.e2[b] * rf));
+    const double Wg = p * ((tw - 1) * std::fabs(cam.e1[g] - cam.e1[b] * rg) + (th - 1) * std::fabs(cam.e2[g] - cam.e2[b] * rg));
+    for (int t = 64; t >= 1; t--) {
+      // box: cells floor(q) .. floor(q)+1 over the footprint widened by 0.05 each side
+      const double nf = std::floor(Wf + t * std::fabs(rf) + 0.11) + 2.0;
+      const double ng = std::floor(Wg + t * std::fabs(rg) + 0.11) + 2.0;
+      const double pitch = 4.0 * std::ceil(nf / 4.0);
+      const double size = pitch * ng * (double)(t + 1);
+      if (size > (double)budget) continue;
+      // voxels loaded per sample: box / (rays x samples per ray in t layers)
+      const double cost = size / ((double)(tw * th) * (double)t / (0.5 * std::fabs(db)));
+      if (cost < best) {
+        best = cost;
+        axis = b;
+        T = t;
+        found = true;
+      }
+      break;
+    }
+  }
+  return found;
+}
+
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step) {
   const double hi[3] = {(double)(n[0] - 1), (double)(n[1] - 1), (double)(n[2] - 1)};
   int64_t total = 0;

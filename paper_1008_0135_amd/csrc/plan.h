@@ -60,6 +60,16 @@ void depth_order(const Partition& p, const double d[3], std::vector<int32_t>& or
 // (clipped to [0, M-1]) are zero.  Skipping such a brick is bit-exact.
 bool brick_transparent(float bmin, float bmax, const float* tf_rgba, int32_t M, double vmin, double vmax);
 
+// Slab parameters of the LDS-staged march for one view: the slab axis
+// (1 = axis 2, 2 = axis 3; axis 1 is the contiguous storage axis and is never
+// the slab axis) and the number of cell layers per slab, the largest for
+// which a conservative bound of the voxel box that one tw x th tile of rays
+// touches in a slab fits `budget` floats.  Among the two axes, the one that
+// loads the fewest voxels per sample wins.  Returns false when no slab of one
+// layer fits (rays nearly parallel to axis 1, or pixels much larger than
+// voxels): the gather march is used then.
+bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int32_t& axis, int32_t& T);
+
 // Sum over pixels of the whole-volume lattice count (no ERT, no skipping).
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step);
 

@@ -12,6 +12,7 @@
 // Composite (paper Sec. 2.5): one lane per output pixel walks the brick
 // images front to back and applies the over operator where its pixel lies
 // inside a brick's rectangle.
+#include "sample.h"
 #include "vr_internal.h"
 
 namespace vr {
@@ -19,8 +20,12 @@ namespace vr {
 namespace {
 
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef const float __attribute__((address_space(1))) gfloat;
 
-__device__ __forceinline__ f2u ld_pair(const float* p) { return *reinterpret_cast<const f2u*>(p); }
+// two adjacent voxels with one 8-byte global load (dword alignment suffices)
+__device__ __forceinline__ f2u ld_pair(gfloat* p) {
+  return *reinterpret_cast<const f2u __attribute__((address_space(1)))*>(p);
+}
 
 // Blocks of 256 lanes (4 wavefronts, 4 consecutive tiles).  Consecutive
 // hardware block ids go round-robin over the 8 XCDs; remap them so each XCD
@@ -76,33 +81,14 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       const float pz = (float)(o[2] + t0 * d[2] - (double)br.lo[2]);
       const float sx = (float)(a.step * d[0]), sy = (float)(a.step * d[1]), sz = (float)(a.step * d[2]);
       const int cnt = (int)(k1 - k0);
-      const float fM = (float)(a.M - 1);
-      const float* __restrict__ base = br.base;
+      gfloat* base = (gfloat*)br.base;
       const int ys = br.sy, zs = br.sz;
       for (int j = 0; j < cnt; ++j) {
-        const float fj = (float)j;
-        const float qx = fmaf(fj, sx, px), qy = fmaf(fj, sy, py), qz = fmaf(fj, sz, pz);
-        const int ix = min(max((int)floorf(qx), br.clo[0]), br.chi[0]);
-        const int iy = min(max((int)floorf(qy), br.clo[1]), br.chi[1]);
-        const int iz = min(max((int)floorf(qz), br.clo[2]), br.chi[2]);
-        const float wx = qx - (float)ix, wy = qy - (float)iy, wz = qz - (float)iz;
-        const float* p = base + (iz * zs + iy * ys + ix);
+        const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
+        gfloat* p = base + (c.iz * zs + c.iy * ys + c.ix);
         const f2u a00 = ld_pair(p), a01 = ld_pair(p + ys), a10 = ld_pair(p + zs), a11 = ld_pair(p + zs + ys);
-        const float c00 = fmaf(wx, a00.y - a00.x, a00.x), c01 = fmaf(wx, a01.y - a01.x, a01.x);
-        const float c10 = fmaf(wx, a10.y - a10.x, a10.x), c11 = fmaf(wx, a11.y - a11.x, a11.x);
-        const float c0 = fmaf(wy, c01 - c00, c00), c1 = fmaf(wy, c11 - c10, c10);
-        const float val = fmaf(wz, c1 - c0, c0);
-        const float s = fminf(fmaxf((val - a.vmin) * a.inv_range, 0.f), 1.f);
-        const float uu = s * fM;
-        const int i = min((int)uu, a.M - 2);
-        const float w = uu - (float)i;
-        const float4 e0 = s_tf[i], e1 = s_tf[i + 1];
-        const float al = fmaf(w, e1.w - e0.w, e0.w);
-        const float Ta = T * al;
-        Cr = fmaf(Ta, fmaf(w, e1.x - e0.x, e0.x), Cr);
-        Cg = fmaf(Ta, fmaf(w, e1.y - e0.y, e0.y), Cg);
-        Cb = fmaf(Ta, fmaf(w, e1.z - e0.z, e0.z), Cb);
-        T = fmaf(-T, al, T);
+        const float val = trilerp(a00.x, a00.y, a01.x, a01.y, a10.x, a10.y, a11.x, a11.y, c);
+        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
         if (1.f - T >= a.tau) break;
       }
     }

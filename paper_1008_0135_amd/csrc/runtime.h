@@ -79,9 +79,17 @@ struct vr_ctx {
   std::vector<Timed> timed;
   std::vector<hipEvent_t> event_pool;
   hipStream_t prof_stream = nullptr;
-  // autotune cache: key -> tile edge
-  std::vector<std::pair<std::string, int32_t>> tune;
-  int32_t tune_waves_per_cu = 0;
+  // march selection: 0 = LDS-staged slabs when a slab fits, else gather; 1 = gather only
+  int32_t march_mode = 0;
+  int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
+  // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
+  struct TuneEntry {
+    std::string key;
+    int32_t tile, lds_budget, march_mode;
+    double ms;
+  };
+  std::vector<TuneEntry> tune;
+  int32_t tune_waves_per_cu = 0;  // persistent-grid occupancy of the batched path (0 = default 8)
 };
 
 struct vr_volume {
@@ -117,5 +125,12 @@ int check_params(const vr_params* p);
 int resolve_window(vr_ctx* ctx, vr_volume* vol, hipStream_t s, double& vmin, double& vmax);
 void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, double vmin, double vmax,
                        const float4* tf, int32_t M);
+// Tuned launch shape for a render (tile edge, LDS budget, march mode); defaults when untuned.
+void tuned_shape(const vr_ctx* ctx, const vr_volume* vol, int32_t W, int32_t H, const vr_params* p, int32_t& tile,
+                 int32_t& budget, int32_t& mode);
+std::string tune_key(const vr_volume* vol, int32_t W, int32_t H);
+void tune_load(vr_ctx* ctx);
+int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, vr_batch** cache, hipStream_t s,
+                 int32_t force_blocks);
 
 }  // namespace vr

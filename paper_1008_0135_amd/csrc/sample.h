@@ -1,0 +1,81 @@
+// sample.h -- per-sample arithmetic shared by every march kernel (forward
+// gather, forward LDS-staged, checkpointing forward and adjoint), so all of
+// them evaluate a sample with the same single-precision operations in the
+// same order (paper Sec. 2: trilinear value -> transfer function -> colour
+// and opacity; Sec. 2.4: front-to-back accumulation).
+#pragma once
+
+#include "vr_internal.h"
+
+namespace vr {
+
+// Position of sample j of a lane: start + j * step (one rounding per axis).
+struct SamplePos {
+  float x, y, z;
+};
+
+__device__ __forceinline__ SamplePos sample_pos(int j, float px, float py, float pz, float sx, float sy, float sz) {
+  const float fj = (float)j;
+  return SamplePos{fmaf(fj, sx, px), fmaf(fj, sy, py), fmaf(fj, sz, pz)};
+}
+
+// Base cell (clamped to the brick's stored range) and fractions.
+struct Cell {
+  int ix, iy, iz;
+  float wx, wy, wz;
+};
+
+__device__ __forceinline__ Cell cell_of(const SamplePos& q, const DevBrick& br) {
+  Cell c;
+  c.ix = min(max((int)floorf(q.x), br.clo[0]), br.chi[0]);
+  c.iy = min(max((int)floorf(q.y), br.clo[1]), br.chi[1]);
+  c.iz = min(max((int)floorf(q.z), br.clo[2]), br.chi[2]);
+  c.wx = q.x - (float)c.ix;
+  c.wy = q.y - (float)c.iy;
+  c.wz = q.z - (float)c.iz;
+  return c;
+}
+
+// Trilinear value from the eight corners v[dz][dy][dx] (lerp along 1, then 2, then 3).
+__device__ __forceinline__ float trilerp(float v000, float v001, float v010, float v011, float v100, float v101,
+                                         float v110, float v111, const Cell& c) {
+  const float c00 = fmaf(c.wx, v001 - v000, v000), c01 = fmaf(c.wx, v011 - v010, v010);
+  const float c10 = fmaf(c.wx, v101 - v100, v100), c11 = fmaf(c.wx, v111 - v110, v110);
+  const float c0 = fmaf(c.wy, c01 - c00, c00), c1 = fmaf(c.wy, c11 - c10, c10);
+  return fmaf(c.wz, c1 - c0, c0);
+}
+
+// Transfer-function lookup: value -> (r, g, b, a), plus the table interval i,
+// the weight w and the unclamped normalised value (for the adjoint).
+struct Classified {
+  float r, g, b, a;
+  int i;
+  float w;
+  float sraw;
+};
+
+__device__ __forceinline__ Classified classify(float val, float vmin, float inv_range, int M, const float4* s_tf) {
+  Classified k;
+  k.sraw = (val - vmin) * inv_range;
+  const float s = fminf(fmaxf(k.sraw, 0.f), 1.f);
+  const float uu = s * (float)(M - 1);
+  k.i = min((int)uu, M - 2);
+  k.w = uu - (float)k.i;
+  const float4 e0 = s_tf[k.i], e1 = s_tf[k.i + 1];
+  k.a = fmaf(k.w, e1.w - e0.w, e0.w);
+  k.r = fmaf(k.w, e1.x - e0.x, e0.x);
+  k.g = fmaf(k.w, e1.y - e0.y, e0.y);
+  k.b = fmaf(k.w, e1.z - e0.z, e0.z);
+  return k;
+}
+
+// One front-to-back emission-absorption step: C += T a rgb, T *= (1 - a).
+__device__ __forceinline__ void accumulate(const Classified& k, float& Cr, float& Cg, float& Cb, float& T) {
+  const float Ta = T * k.a;
+  Cr = fmaf(Ta, k.r, Cr);
+  Cg = fmaf(Ta, k.g, Cg);
+  Cb = fmaf(Ta, k.b, Cb);
+  T = fmaf(-T, k.a, T);
+}
+
+}  // namespace vr

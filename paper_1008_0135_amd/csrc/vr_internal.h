@@ -165,6 +165,9 @@ struct MarchArgs {
   int32_t nbv;           // rendered bricks in this launch
   int32_t ntiles;        // total work items (tiles)
   int32_t tile_w, tile_h;
+  int32_t slab_axis;     // LDS-staged march: slab axis (1 = axis 2, 2 = axis 3); 0 = gather march
+  int32_t slab_T;        // cell layers per slab
+  int32_t lds_budget;    // floats of LDS for one slab's voxel box
   int32_t pad;
   const float4* tf;      // [M] RGBA
   const DevBrick* bricks;
@@ -180,8 +183,49 @@ struct CompArgs {
   float4* out;
 };
 
+// Differentiable path (whole volume).  Checkpoints are stored [segment][pixel].
+struct SaveArgs {
+  float* ckpt;        // T before samples 0, K, 2K, ... of each ray
+  int32_t* nused;     // samples applied per ray (early termination included)
+  int32_t K;
+  int32_t npix;       // W * H
+};
+
+struct BwdArgs {
+  const float* ckpt;
+  const int32_t* nused;
+  const float4* gout; // dL/d(image) of this view, [H][W]
+  float* gvol;        // dL/d(voxels), [n3][n2][n1], or null
+  double* tf_part;    // per-workgroup table gradients, [blocks][M][4]
+  double vmin, inv_range;  // normalisation window in double precision
+  int32_t K;
+  int32_t npix;
+};
+
+// Batched rendering: one descriptor per request (whole volume, own view,
+// table, window and output), work items numbered request by request.
+struct BatchReq {
+  Camera cam;
+  DevBrick br;           // the request's volume as one brick
+  double hi[3];          // n - 1 per axis
+  float vmin, inv_range;
+  const float4* tf;
+  float4* out;
+  int32_t M, tiles_x, ntiles, item_begin;
+};
+
+struct BatchArgs {
+  const BatchReq* reqs;
+  unsigned int* counter;  // next work item
+  int32_t nreq, total_items, max_M, pad;
+  double step;
+  float tau;
+  int32_t pad2;
+};
+
 // Launchers (defined in the .hip files); all asynchronous on `s`.
 hipError_t launch_march(const MarchArgs& a, hipStream_t s);
+hipError_t launch_march_lds(const MarchArgs& a, hipStream_t s);
 hipError_t launch_composite(const CompArgs& a, hipStream_t s);
 hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s);
 hipError_t launch_minmax_final(const float* partial, int32_t nblocks, float* out3, hipStream_t s);
@@ -190,6 +234,12 @@ hipError_t launch_minmax_final(const float* partial, int32_t nblocks, float* out
 // zgroups groups of zper planes; scratch holds nb*zgroups float2 partials.
 hipError_t launch_brick_minmax_parts(const float* vol, const int64_t n[3], const int64_t* boxes, int32_t nb,
                                      int zgroups, int zper, float* scratch, float* out2, hipStream_t s);
+hipError_t launch_fwd_save(const MarchArgs& a, const SaveArgs& sa, hipStream_t s);
+hipError_t launch_bwd(const MarchArgs& a, const BwdArgs& ba, hipStream_t s);
+int bwd_blocks(const MarchArgs& a);
+hipError_t launch_tf_reduce(const double* part, int nblocks, int n, float* grad_tf, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_batch(const BatchArgs& a, int blocks, hipStream_t s);
 hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
                            const int64_t dn[3], hipStream_t s);
 

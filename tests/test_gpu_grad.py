@@ -1,0 +1,193 @@
+"""GPU parity of the differentiable path (adjoint march) through the C ABI.
+
+* the checkpointing forward gives the same image bits as the plain forward;
+* table and voxel gradients vs the FP64 oracle's exact gradient (relative
+  error <= 1e-3 with the scale floor 1e-3 * max|g|), for several checkpoint
+  intervals, with and without early termination;
+* table gradients vs central finite differences of the FP64 forward (eps = 1e-3);
+* the torch.autograd.Function on an L2 loss against a perturbed-table target;
+* the 256x256x512 / 512^2 case on 2 of its 8 views.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1008_0135_amd as vr
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = vr.vr_create(0)
+    yield c
+    vr.vr_destroy(c)
+
+
+def _rel(g, ref):
+    scale = max(1e-3 * float(np.abs(ref).max()), 1e-30)
+    return np.abs(g - ref) / np.maximum(np.abs(ref), scale)
+
+
+def _case(seed=41, dims=(48, 40, 56), M=64, amul=3.0):
+    vol = synth.cube(*dims, seed=seed, n_sources=4, sigma_range=(2.0, 4.0))
+    tf = synth.tf_colour(M)
+    tf[:, 3] = np.minimum(1.0, tf[:, 3] * amul)
+    vmin, vmax = float(vol.min()) - 0.5, float(vol.max()) + 0.5
+    return vol, tf, vmin, vmax
+
+
+def _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout, tau=2.0, K=32):
+    n3, n2, n1 = vol.shape
+    dvol = torch.from_numpy(vol).cuda()
+    h = vr.vr_volume_wrap(ctx, dvol, (n1, n2, n3))
+    vr.vr_tf_set(ctx, tf, vmin, vmax)
+    out = torch.empty((len(views), H, W, 4), device="cuda")
+    p = vr.make_params(tau=tau, ckpt_K=K, ess=0)
+    vv = [vr.make_view(R, W, H) for R in views]
+    st = vr.vr_render(ctx, h, vv, p, out, save=True)
+    plain = torch.empty_like(out)
+    vr.vr_render(ctx, h, vv, p, plain)
+    g = torch.from_numpy(np.ascontiguousarray(gout, np.float32)).cuda()
+    gtf = torch.empty((tf.shape[0], 4), device="cuda")
+    gvol = torch.empty_like(dvol)
+    vr.vr_render_backward(ctx, h, st, g, gtf, gvol)
+    torch.cuda.synchronize()
+    res = (out.cpu().numpy(), plain.cpu().numpy(), gtf.cpu().numpy().astype(np.float64),
+           gvol.cpu().numpy().astype(np.float64))
+    vr.vr_state_destroy(st)
+    vr.vr_volume_destroy(h)
+    return res
+
+
+def _oracle_grad(vol, tf, views, W, H, vmin, vmax, gout, tau=2.0):
+    gtf = np.zeros((tf.shape[0], 4))
+    gvol = np.zeros(vol.shape)
+    imgs = []
+    for j, R in enumerate(views):
+        a, b, img = oracle.render_grad(vol, tf, R, W, H, gout[j], vmin, vmax, tau=tau)
+        gtf += a
+        gvol += b
+        imgs.append(img)
+    return gtf, gvol, np.stack(imgs)
+
+
+@pytest.mark.parametrize("K", [32, 7, 1, 64])
+def test_gradients_match_oracle(ctx, K):
+    _say(f"adjoint vs FP64 oracle, K = {K}")
+    vol, tf, vmin, vmax = _case()
+    views = synth.random_views(2, 42)
+    W = H = 64
+    rng = np.random.Generator(np.random.PCG64(43))
+    gout = rng.normal(0, 1, (2, H, W, 4))
+    img, plain, gtf, gvol = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout, K=K)
+    assert np.array_equal(img, plain)
+    otf, ovol, oimg = _oracle_grad(vol, tf, views, W, H, vmin, vmax, gout)
+    assert np.abs(img - oimg).max() <= 2e-5
+    r_tf = _rel(gtf, otf)
+    r_vol = _rel(gvol, ovol)
+    _say(f"max rel err: tf {r_tf.max():.3g}, voxels {r_vol.max():.3g}")
+    assert r_tf.max() <= 1e-3
+    assert r_vol.max() <= 1e-3
+
+
+def test_gradients_with_early_termination(ctx):
+    _say("adjoint with ERT (frozen termination index)")
+    vol, tf, vmin, vmax = _case(seed=44, amul=20.0)
+    views = synth.random_views(2, 45)
+    W = H = 64
+    rng = np.random.Generator(np.random.PCG64(46))
+    gout = rng.normal(0, 1, (2, H, W, 4))
+    # rays whose opacity lands within rounding of tau may stop one sample apart on
+    # the two sides: give them no upstream gradient so both sides exclude them
+    ref = oracle.render(vol, tf, views, W, H, vmin, vmax, tau=0.95)
+    tie = (ref["flags"] & oracle.FLAG_ERT) != 0
+    gout[tie] = 0.0
+    img, plain, gtf, gvol = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout, tau=0.95)
+    otf, ovol, oimg = _oracle_grad(vol, tf, views, W, H, vmin, vmax, gout, tau=0.95)
+    assert np.abs(img - oimg)[~tie].max() <= 2e-5
+    assert (1.0 - img[..., 3] <= 0.05 + 1e-6).mean() > 0.2  # termination fired on many rays
+    assert _rel(gtf, otf).max() <= 1e-3
+    assert _rel(gvol, ovol).max() <= 1e-3
+
+
+def test_tf_gradient_vs_central_fd(ctx):
+    """Configuration protocol: central differences, eps = 1e-3, on every table entry (FP64 forward)."""
+    _say("adjoint vs central finite differences of the FP64 forward")
+    vol, tf, vmin, vmax = _case(seed=47, dims=(24, 20, 28), M=16, amul=2.0)
+    views = synth.random_views(2, 48)
+    W = H = 24
+    target = np.stack([oracle.render(vol, synth.tf_perturbed(tf, 49), [R], W, H, vmin, vmax, tau=2.0)["image"][0]
+                       for R in views])
+    base = np.stack([oracle.render(vol, tf, [R], W, H, vmin, vmax, tau=2.0)["image"][0] for R in views])
+    gout = base - target
+    _, _, gtf, _ = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout)
+
+    def loss(t):
+        img = np.stack([oracle.render(vol, t, [R], W, H, vmin, vmax, tau=2.0)["image"][0] for R in views])
+        return 0.5 * float(((img - target) ** 2).sum())
+
+    eps = 1e-3
+    fd = np.zeros_like(gtf)
+    for i in range(tf.shape[0]):
+        for c in range(4):
+            tp, tm = tf.astype(np.float64), tf.astype(np.float64)
+            tp = tp.copy()
+            tm = tm.copy()
+            tp[i, c] += eps
+            tm[i, c] -= eps
+            tp32, tm32 = tp.astype(np.float32), tm.astype(np.float32)
+            fd[i, c] = (loss(tp32) - loss(tm32)) / (float(tp32[i, c]) - float(tm32[i, c]))
+    r = _rel(gtf, fd)
+    _say(f"max rel err vs FD: {r.max():.3g}")
+    assert r.max() <= 1e-3
+
+
+def test_autograd_function_l2_loss(ctx):
+    _say("torch.autograd.Function: L2 loss vs perturbed-table target")
+    from paper_1008_0135_amd.autograd import render
+    vol, tf, vmin, vmax = _case(seed=50)
+    views = synth.random_views(2, 51)
+    W = H = 48
+    vv = [vr.make_view(R, W, H) for R in views]
+    target_tf = synth.tf_perturbed(tf, 52)
+    target = np.stack([oracle.render(vol, target_tf, [R], W, H, vmin, vmax, tau=2.0)["image"][0] for R in views])
+    v = torch.from_numpy(vol).cuda().requires_grad_(True)
+    t = torch.from_numpy(tf).cuda().requires_grad_(True)
+    img = render(v, t, vv, ctx, vmin, vmax, ckpt_K=16)
+    loss = 0.5 * ((img - torch.from_numpy(target).float().cuda()) ** 2).sum()
+    loss.backward()
+    gout = img.detach().cpu().numpy().astype(np.float64) - target
+    otf, ovol, _ = _oracle_grad(vol, tf, views, W, H, vmin, vmax, gout)
+    assert _rel(t.grad.cpu().numpy().astype(np.float64), otf).max() <= 1e-3
+    assert _rel(v.grad.cpu().numpy().astype(np.float64), ovol).max() <= 1e-3
+
+
+def test_c5_full_size_two_views(ctx):
+    """256x256x512, 512^2: forward + adjoint on the GPU, FP64 gradient on 2 views."""
+    _say("C5: 256x256x512 volume, 2 views at 512^2")
+    c = synth.CONFIGS["C5"]
+    vol = synth.config_cube("C5")
+    tf = synth.tf_colour(256)
+    vmin, vmax = float(vol.min()) - 0.5, float(vol.max()) + 0.5
+    views = synth.random_views(c["nviews"], c["view_seed"])[:2]
+    W, H = c["image"]
+    target = np.stack([oracle.render(vol, synth.tf_perturbed(tf, c["tf_seed"]), [R], W, H, vmin, vmax,
+                                     tau=2.0)["image"][0] for R in views])
+    base = np.stack([oracle.render(vol, tf, [R], W, H, vmin, vmax, tau=2.0)["image"][0] for R in views])
+    gout = base - target
+    img, plain, gtf, gvol = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout)
+    assert np.abs(img - base).max() <= 2e-5
+    otf, ovol, _ = _oracle_grad(vol, tf, views, W, H, vmin, vmax, gout)
+    r_tf, r_vol = _rel(gtf, otf), _rel(gvol, ovol)
+    _say(f"C5 max rel err: tf {r_tf.max():.3g}, voxels {r_vol.max():.3g}")
+    assert r_tf.max() <= 1e-3
+    assert r_vol.max() <= 1e-3
