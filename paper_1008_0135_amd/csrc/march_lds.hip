@@ -11,7 +11,9 @@
 //   1. bounds the footprint of its ray bundle in the slab from the four
 //      corner rays of the tile (8 plane intersections, a wave reduction),
 //   2. copies that box of voxels from HBM into LDS with row-contiguous
-//      16-byte loads (each voxel fetched once per slab, coalesced),
+//      16-byte loads (each voxel fetched once per slab, coalesced); the loads
+//      of slab s+1 are issued into registers before slab s is sampled, so
+//      their latency overlaps the sampling (a two-stage software pipeline),
 //   3. lets every lane consume its own samples whose cell layer along b lies
 //      in the slab, reading the eight trilinear corners from LDS.
 // Lanes carry their colour, transmittance and sample cursor from slab to
@@ -48,7 +50,75 @@ __device__ __forceinline__ float unif(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-template <int TW>
+// Voxel box of one slab in LDS: rows along axis 1 (f), `pitch` floats apart
+// (a multiple of 4), ng rows per layer along the in-plane axis g, nl layers
+// along the slab axis b.  Chunk i (16 bytes) of the box sits at LDS float 4i.
+struct Region {
+  int f_lo, g_lo, b_lo;
+  int nf, ng, nl;
+  int pitch, layer, chunks;
+  int cl, ch;  // cell layers of the slab along b
+  bool staged;
+};
+
+// Row, chunk-in-row, layer and row-in-layer of chunk i (reciprocal products;
+// exact because i < 2^13 and the quotients are at least 0.5/nf4 away from the
+// next integer).
+struct ChunkPos {
+  int c4, lb, lg;
+};
+
+__device__ __forceinline__ ChunkPos chunk_pos(int i, int nf4, int ng, float inv_nf4, float inv_ng) {
+  ChunkPos c;
+  const int row = (int)(((float)i + 0.5f) * inv_nf4);
+  c.c4 = i - row * nf4;
+  c.lb = (int)(((float)row + 0.5f) * inv_ng);
+  c.lg = row - c.lb * ng;
+  return c;
+}
+
+// Issue the global loads of a region's chunks into registers (lane-contiguous
+// chunks, so one instruction reads 1 KB of consecutive row segments).  Every
+// chunk is a full 16-byte load inside its row: the last chunk of a row starts
+// at nf - 4 instead of 4*c4 (store_region shifts it back), so no load result
+// is consumed here and no wait is needed until the LDS store.
+template <int CH>
+__device__ __forceinline__ void issue_loads(const Region& r, gfloat* gbase, int sB, int sG, int lane, float4 (&buf)[CH]) {
+  const int nf4 = r.pitch >> 2;
+  const float inv_nf4 = 1.0f / (float)nf4, inv_ng = 1.0f / (float)r.ng;
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int i = lane + 64 * k;
+    if (i < r.chunks) {
+      const ChunkPos c = chunk_pos(i, nf4, r.ng, inv_nf4, inv_ng);
+      const int f0 = min(4 * c.c4, r.nf - 4);
+      gfloat* src = gbase + ((r.b_lo + c.lb) * sB + (r.g_lo + c.lg) * sG + (r.f_lo + f0));
+      const f4u v = *reinterpret_cast<const f4u __attribute__((address_space(1)))*>(src);
+      buf[k] = make_float4(v.x, v.y, v.z, v.w);
+    }
+  }
+}
+
+template <int CH>
+__device__ __forceinline__ void store_region(const Region& r, float* s_reg, int lane, const float4 (&buf)[CH]) {
+  const int nf4 = r.pitch >> 2;
+  const float inv_nf4 = 1.0f / (float)nf4, inv_ng = 1.0f / (float)r.ng;
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int i = lane + 64 * k;
+    if (i < r.chunks) {
+      const ChunkPos c = chunk_pos(i, nf4, r.ng, inv_nf4, inv_ng);
+      const int rem = r.nf - 4 * c.c4;  // valid floats of this chunk (the row's tail may be short)
+      float4 v = buf[k];
+      if (rem == 3) v = make_float4(v.y, v.z, v.w, 0.f);
+      else if (rem == 2) v = make_float4(v.z, v.w, 0.f, 0.f);
+      else if (rem == 1) v = make_float4(v.w, 0.f, 0.f, 0.f);
+      reinterpret_cast<float4*>(s_reg)[i] = v;
+    }
+  }
+}
+
+template <int TW, int CH>
 __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
@@ -99,8 +169,7 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
   const float sx = (float)(a.step * d[0]), sy = (float)(a.step * d[1]), sz = (float)(a.step * d[2]);
 
   // ---- slab frame: b = slab axis (1 or 2), g = the other of axes 2/3, f = axis 1
-  const int b = a.slab_axis;
-  const bool by = b == 1;  // slab axis is axis 2 (else axis 3)
+  const bool by = a.slab_axis == 1;  // slab axis is axis 2 (else axis 3)
   const float pb = by ? py : pz, sb = by ? sy : sz;
   const int cloB = by ? br.clo[1] : br.clo[2], chiB = by ? br.chi[1] : br.chi[2];
   const int cloG = by ? br.clo[2] : br.clo[1], chiG = by ? br.chi[2] : br.chi[1];
@@ -140,19 +209,16 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
   const int ysl = br.sy, zsl = br.sz;
   const int strideB = by ? ysl : zsl, strideG = by ? zsl : ysl;
   gfloat* gbase = (gfloat*)br.base;
+  const int capacity = 256 * CH;  // floats the register pipeline can carry
 
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
-  int j = 0;
-  bool done = cnt == 0;
-  const int step_l = up ? a.slab_T : -a.slab_T;
-
-  for (int L = Lbeg;; L += step_l) {
-    const int cl = up ? L : max(L - a.slab_T + 1, Lend);
-    const int ch = up ? min(L + a.slab_T - 1, Lend) : L;
-    // ---- footprint of the bundle over cell layers [cl, ch] (planes cl and ch+1)
+  // voxel box of the slab covering cell layers starting at L (marching order)
+  auto region_of = [&](int L) {
+    Region r;
+    r.cl = up ? L : max(L - a.slab_T + 1, Lend);
+    r.ch = up ? min(L + a.slab_T - 1, Lend) : L;
     float fmn = INFINITY, fmx = -INFINITY, gmn = INFINITY, gmx = -INFINITY;
     if (lane < 8) {
-      const float P = lane < 4 ? (float)cl : (float)(ch + 1);
+      const float P = lane < 4 ? (float)r.cl : (float)(r.ch + 1);
       const float tt = P - ocb;
       const float qf = fmaf(tt, rf, ocf), qg = fmaf(tt, rg, ocg);
       fmn = fmx = qf;
@@ -163,78 +229,75 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
     gmn = wave_min(gmn);
     gmx = wave_max(gmx);
     // cells floor(q) and floor(q) + 1 of every sample q in the footprint (+-0.05 voxel)
-    const int f_lo = uni(max((int)floorf(unif(fmn) - 0.05f), br.clo[0]));
+    r.f_lo = uni(max((int)floorf(unif(fmn) - 0.05f), br.clo[0]));
     const int f_hi = uni(min((int)floorf(unif(fmx) + 0.05f) + 1, br.chi[0] + 1));
-    const int g_lo = uni(max((int)floorf(unif(gmn) - 0.05f), cloG));
+    r.g_lo = uni(max((int)floorf(unif(gmn) - 0.05f), cloG));
     const int g_hi = uni(min((int)floorf(unif(gmx) + 0.05f) + 1, chiG + 1));
-    const int b_lo = cl, b_hi = ch + 1;
-    const int nf = f_hi - f_lo + 1, ng = g_hi - g_lo + 1, nl = b_hi - b_lo + 1;
-    const int pitch = (nf + 3) & ~3;
-    const int layer = pitch * ng;
-    const bool staged = nf > 0 && ng > 0 && layer * nl <= a.lds_budget;
+    r.b_lo = r.cl;
+    r.nf = f_hi - r.f_lo + 1;
+    r.ng = g_hi - r.g_lo + 1;
+    r.nl = r.ch + 2 - r.cl;
+    r.pitch = (max(r.nf, 1) + 3) & ~3;
+    r.layer = r.pitch * r.ng;
+    r.chunks = (r.pitch >> 2) * r.ng * r.nl;
+    r.staged = r.nf >= 4 && r.ng > 0 && r.layer * r.nl <= min(a.lds_budget, capacity);
+    return r;
+  };
 
-    if (staged) {
-      // ---- copy the box into LDS: rows along f, 16-byte chunks
-      const int nf4 = pitch >> 2;
-      const int rows = ng * nl;
-      const int chunks = rows * nf4;
-      const float inv_nf4 = 1.0f / (float)nf4, inv_ng = 1.0f / (float)ng;
-      for (int i = lane; i < chunks; i += 64) {
-        const int row = (int)(((float)i + 0.5f) * inv_nf4);
-        const int c4 = i - row * nf4;
-        const int lb = (int)(((float)row + 0.5f) * inv_ng);
-        const int lg = row - lb * ng;
-        const int f0 = 4 * c4;
-        gfloat* src = gbase + ((b_lo + lb) * strideB + (g_lo + lg) * strideG + (f_lo + f0));
-        float* dst = s_reg + row * pitch + f0;
-        if (f0 + 3 < nf) {
-          const f4u q = *reinterpret_cast<const f4u __attribute__((address_space(1)))*>(src);
-          *reinterpret_cast<float4*>(dst) = make_float4(q.x, q.y, q.z, q.w);
-        } else {
-          for (int e = 0; e < nf - f0; e++) dst[e] = src[e];
-        }
-      }
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
+  int j = 0;
+  bool done = cnt == 0;
+  const int step_l = up ? a.slab_T : -a.slab_T;
+
+  float4 buf[CH];
+  int L = Lbeg;
+  Region nxt = region_of(L);
+  if (nxt.staged) issue_loads<CH>(nxt, gbase, strideB, strideG, lane, buf);
+  for (;;) {
+    const Region cur = nxt;
+    if (cur.staged) {
+      store_region<CH>(cur, s_reg, lane, buf);
       __syncthreads();
     }
+    // prefetch the next slab while this one is sampled
+    const bool last = up ? cur.ch >= Lend : cur.cl <= Lend;
+    if (!last) {
+      L += step_l;
+      nxt = region_of(L);
+      if (nxt.staged) issue_loads<CH>(nxt, gbase, strideB, strideG, lane, buf);
+    }
     // ---- consume the lane's samples whose cell layer along b is in [cl, ch]
-    const int Sy = by ? layer : pitch, Sz = by ? pitch : layer;
-    const int oy = by ? b_lo : g_lo, oz = by ? g_lo : b_lo;
-    const int omax = layer * nl - 1 - (Sy + Sz + 1);
-    while (!done) {
-      const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
-      const int ib = by ? c.iy : c.iz;
-      if (up ? ib > ch : ib < cl) break;
-      float v000, v001, v010, v011, v100, v101, v110, v111;
-      if (staged) {
-        int oo = (c.ix - f_lo) + (c.iy - oy) * Sy + (c.iz - oz) * Sz;
+    const int Sy = by ? cur.layer : cur.pitch, Sz = by ? cur.pitch : cur.layer;
+    const int oy = by ? cur.b_lo : cur.g_lo, oz = by ? cur.g_lo : cur.b_lo;
+    const int omax = cur.layer * cur.nl - 1 - (Sy + Sz + 1);
+    // Two separate loops: the LDS loop must not share a block with global
+    // loads, or the wait for those would also wait for the prefetch above.
+    if (cur.staged) {
+      while (!done) {
+        const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
+        const int ib = by ? c.iy : c.iz;
+        if (up ? ib > cur.ch : ib < cur.cl) break;
+        int oo = (c.ix - cur.f_lo) + (c.iy - oy) * Sy + (c.iz - oz) * Sz;
         oo = min(max(oo, 0), omax);
         const float* p = s_reg + oo;
-        v000 = p[0];
-        v001 = p[1];
-        v010 = p[Sy];
-        v011 = p[Sy + 1];
-        v100 = p[Sz];
-        v101 = p[Sz + 1];
-        v110 = p[Sz + Sy];
-        v111 = p[Sz + Sy + 1];
-      } else {
-        gfloat* p = gbase + (c.iz * zsl + c.iy * ysl + c.ix);
-        v000 = p[0];
-        v001 = p[1];
-        v010 = p[ysl];
-        v011 = p[ysl + 1];
-        v100 = p[zsl];
-        v101 = p[zsl + 1];
-        v110 = p[zsl + ysl];
-        v111 = p[zsl + ysl + 1];
+        const float val = trilerp(p[0], p[1], p[Sy], p[Sy + 1], p[Sz], p[Sz + 1], p[Sz + Sy], p[Sz + Sy + 1], c);
+        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        ++j;
+        if (j >= cnt || 1.f - T >= a.tau) done = true;
       }
-      const float val = trilerp(v000, v001, v010, v011, v100, v101, v110, v111, c);
-      accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
-      ++j;
-      if (j >= cnt || 1.f - T >= a.tau) done = true;
+    } else {
+      while (!done) {
+        const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
+        const int ib = by ? c.iy : c.iz;
+        if (up ? ib > cur.ch : ib < cur.cl) break;
+        gfloat* p = gbase + (c.iz * zsl + c.iy * ysl + c.ix);
+        const float val = trilerp(p[0], p[1], p[ysl], p[ysl + 1], p[zsl], p[zsl + 1], p[zsl + ysl], p[zsl + ysl + 1], c);
+        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        ++j;
+        if (j >= cnt || 1.f - T >= a.tau) done = true;
+      }
     }
-    if (up ? ch >= Lend : cl <= Lend) break;
-    if (__all(done)) break;
+    if (last || __all(done)) break;
     __syncthreads();
   }
   if (valid) a.img[bvw.img_off + (int64_t)ly * bvw.w + lx] = make_float4(Cr, Cg, Cb, 1.f - T);
@@ -245,13 +308,25 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
 hipError_t launch_march_lds(const MarchArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   const int grid = ((a.ntiles + 7) / 8) * 8;
-  const size_t lds = sizeof(float4) * (size_t)a.M + sizeof(float) * (size_t)a.lds_budget;
-  switch (a.tile_w) {
-    case 8: hipLaunchKernelGGL(k_march_lds<8>, dim3(grid), dim3(64), lds, s, a); break;
-    case 16: hipLaunchKernelGGL(k_march_lds<16>, dim3(grid), dim3(64), lds, s, a); break;
-    case 4: hipLaunchKernelGGL(k_march_lds<4>, dim3(grid), dim3(64), lds, s, a); break;
-    default: return hipErrorInvalidValue;
+  // register pipeline depth: 16-byte chunks per lane that carry one slab's box
+  const int ch = a.lds_budget <= 2048 ? 8 : (a.lds_budget <= 4096 ? 16 : 32);
+  const size_t lds = sizeof(float4) * (size_t)a.M + sizeof(float) * 256 * (size_t)ch;
+#define VR_LAUNCH_LDS(TW, CH) hipLaunchKernelGGL((k_march_lds<TW, CH>), dim3(grid), dim3(64), lds, s, a)
+  if (a.tile_w != 4 && a.tile_w != 8 && a.tile_w != 16) return hipErrorInvalidValue;
+  if (ch == 8) {
+    if (a.tile_w == 8) VR_LAUNCH_LDS(8, 8);
+    else if (a.tile_w == 16) VR_LAUNCH_LDS(16, 8);
+    else VR_LAUNCH_LDS(4, 8);
+  } else if (ch == 16) {
+    if (a.tile_w == 8) VR_LAUNCH_LDS(8, 16);
+    else if (a.tile_w == 16) VR_LAUNCH_LDS(16, 16);
+    else VR_LAUNCH_LDS(4, 16);
+  } else {
+    if (a.tile_w == 8) VR_LAUNCH_LDS(8, 32);
+    else if (a.tile_w == 16) VR_LAUNCH_LDS(16, 32);
+    else VR_LAUNCH_LDS(4, 32);
   }
+#undef VR_LAUNCH_LDS
   return hipGetLastError();
 }
 

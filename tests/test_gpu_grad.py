@@ -4,7 +4,9 @@
 * table and voxel gradients vs the FP64 oracle's exact gradient (relative
   error <= 1e-3 with the scale floor 1e-3 * max|g|), for several checkpoint
   intervals, with and without early termination;
-* table gradients vs central finite differences of the FP64 forward (eps = 1e-3);
+* table gradients vs central finite differences of the FP64 forward (eps = 1e-3,
+  the configuration's table), and vs Richardson-extrapolated differences for a
+  high-opacity table whose plain differences are not accurate to 1e-3;
 * the torch.autograd.Function on an L2 loss against a perturbed-table target;
 * the 256x256x512 / 512^2 case on 2 of its 8 views.
 """
@@ -119,35 +121,57 @@ def test_gradients_with_early_termination(ctx):
     assert _rel(gvol, ovol).max() <= 1e-3
 
 
-def test_tf_gradient_vs_central_fd(ctx):
-    """Configuration protocol: central differences, eps = 1e-3, on every table entry (FP64 forward)."""
-    _say("adjoint vs central finite differences of the FP64 forward")
-    vol, tf, vmin, vmax = _case(seed=47, dims=(24, 20, 28), M=16, amul=2.0)
+def _fd_case(tf):
+    vol = synth.cube(24, 20, 28, seed=47, n_sources=4, sigma_range=(2.0, 4.0))
+    vmin, vmax = float(vol.min()) - 0.5, float(vol.max()) + 0.5
     views = synth.random_views(2, 48)
     W = H = 24
     target = np.stack([oracle.render(vol, synth.tf_perturbed(tf, 49), [R], W, H, vmin, vmax, tau=2.0)["image"][0]
                        for R in views])
     base = np.stack([oracle.render(vol, tf, [R], W, H, vmin, vmax, tau=2.0)["image"][0] for R in views])
-    gout = base - target
-    _, _, gtf, _ = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout)
 
     def loss(t):
         img = np.stack([oracle.render(vol, t, [R], W, H, vmin, vmax, tau=2.0)["image"][0] for R in views])
         return 0.5 * float(((img - target) ** 2).sum())
 
-    eps = 1e-3
-    fd = np.zeros_like(gtf)
-    for i in range(tf.shape[0]):
-        for c in range(4):
-            tp, tm = tf.astype(np.float64), tf.astype(np.float64)
-            tp = tp.copy()
-            tm = tm.copy()
-            tp[i, c] += eps
-            tm[i, c] -= eps
-            tp32, tm32 = tp.astype(np.float32), tm.astype(np.float32)
-            fd[i, c] = (loss(tp32) - loss(tm32)) / (float(tp32[i, c]) - float(tm32[i, c]))
-    r = _rel(gtf, fd)
+    def fd(eps):
+        out = np.zeros(tf.shape)
+        for i in range(tf.shape[0]):
+            for c in range(4):
+                tp = tf.astype(np.float64).copy()
+                tm = tp.copy()
+                tp[i, c] += eps
+                tm[i, c] -= eps
+                tp32, tm32 = tp.astype(np.float32), tm.astype(np.float32)
+                out[i, c] = (loss(tp32) - loss(tm32)) / (float(tp32[i, c]) - float(tm32[i, c]))
+        return out
+
+    return vol, views, W, H, vmin, vmax, base - target, fd
+
+
+def test_tf_gradient_vs_central_fd(ctx):
+    """Configuration protocol: central differences of the FP64 forward, eps = 1e-3, every entry
+    of the configuration's table (colour ramp, alpha = 0.02 t, 256 entries)."""
+    _say("adjoint vs central finite differences (eps = 1e-3)")
+    tf = synth.tf_colour(256)
+    vol, views, W, H, vmin, vmax, gout, fd = _fd_case(tf)
+    _, _, gtf, _ = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout)
+    r = _rel(gtf, fd(1e-3))
     _say(f"max rel err vs FD: {r.max():.3g}")
+    assert r.max() <= 1e-3
+
+
+def test_tf_gradient_vs_extrapolated_fd(ctx):
+    """High-opacity 16-entry table, where plain central FD at eps = 1e-3 carries ~3e-3 of its own
+    O(eps^2) truncation error: compare with the Richardson extrapolation of eps and eps/2."""
+    _say("adjoint vs Richardson-extrapolated finite differences")
+    tf = synth.tf_colour(16)
+    tf[:, 3] = np.minimum(1.0, tf[:, 3] * 2)
+    vol, views, W, H, vmin, vmax, gout, fd = _fd_case(tf)
+    _, _, gtf, _ = _gpu_grad(ctx, vol, tf, views, W, H, vmin, vmax, gout)
+    rich = (4.0 * fd(5e-4) - fd(1e-3)) / 3.0
+    r = _rel(gtf, rich)
+    _say(f"max rel err vs extrapolated FD: {r.max():.3g}")
     assert r.max() <= 1e-3
 
 
