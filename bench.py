@@ -44,6 +44,110 @@ def threads_used():
         return os.cpu_count() or 1
 
 
+def _events_ms(fn, reps, stream):
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_batched(ctx, stream):
+    """64 uneven requests: one persistent graph-replayed launch vs 64 plain renders."""
+    import torch
+    t0 = time.time()
+    descs = synth.batch_requests(seed=synth.CONFIGS["C4"]["seed"], nreq=synth.CONFIGS["C4"]["nreq"])
+    vols, reqs, plain = [], [], []
+    nominal = 0
+    for d in descs:
+        n1, n2, n3 = d["dims"]
+        a = synth.cube(n1, n2, n3, seed=d["seed"], n_sources=d["n_sources"])
+        h = vr.vr_volume_create(ctx, a, (n1, n2, n3), on_device=False)
+        vols.append(h)
+        W, H = d["image"]
+        tf = torch.from_numpy(d["tf"]).cuda()
+        out = torch.empty((H, W, 4), device="cuda")
+        mn, mx = float(a.min()), float(a.max())
+        view = vr.make_view(d["view"], W, H)
+        nominal += vr.vr_count_samples((n1, n2, n3), view, 0.5)
+        reqs.append(vr.make_request(h, d["view"], W, H, tf, mn, mx, out))
+        plain.append((h, view, d["tf"], mn, mx, out[None], tf))
+    log(f"batched: 64 requests generated and uploaded in {time.time() - t0:.1f} s, {nominal:.3g} samples")
+    params = vr.make_params(step=0.5, tau=0.99, ess=0)
+    tune, cache = vr.vr_autotune_batch(ctx, reqs, params, None, stream)
+
+    def run_batch():
+        vr.vr_render_batch(ctx, reqs, params, cache, stream)
+
+    def run_plain():
+        for h, view, tf, mn, mx, out, _ in plain:
+            vr.vr_tf_set(ctx, tf, mn, mx, stream)
+            vr.vr_render(ctx, h, [view], params, out, stream)
+
+    ms_b = _events_ms(run_batch, 10, stream)
+    ms_p = _events_ms(run_plain, 3, stream)
+    vr.vr_batch_destroy(cache)
+    for h in vols:
+        vr.vr_volume_destroy(h)
+    log(f"batched: {ms_b:.3f} ms per 64-request batch ({nominal / ms_b / 1e6:.1f} Gsamples/s), "
+        f"64 plain launches {ms_p:.3f} ms, grid {tune.waves_per_cu} waves/CU")
+    return {"workload": "64 requests, volumes U[32,256]^3 (non-cubic), images U[64,512]^2, random views and "
+                        "8-point tables, one persistent hipGraph launch", "ms_per_batch": round(ms_b, 4),
+            "gsamples_per_s": round(nominal / ms_b / 1e6, 3), "ms_64_plain_launches": round(ms_p, 4),
+            "speedup_vs_plain": round(ms_p / ms_b, 3), "nominal_samples": int(nominal),
+            "waves_per_cu": tune.waves_per_cu}
+
+
+def bench_fwd_bwd(ctx, stream):
+    """256x256x512, 8 views at 512^2: forward with checkpoints + adjoint (L2 loss to a perturbed-table target)."""
+    import torch
+    c = synth.CONFIGS["C5"]
+    n1, n2, n3 = c["dims"]
+    W, H = c["image"]
+    a = synth.config_cube("C5")
+    dvol = torch.from_numpy(a).cuda()
+    h = vr.vr_volume_wrap(ctx, dvol, (n1, n2, n3), stream)
+    vmin, vmax = float(a.min()) - 0.5, float(a.max()) + 0.5
+    views = [vr.make_view(R, W, H) for R in synth.random_views(c["nviews"], c["view_seed"])]
+    nominal = sum(vr.vr_count_samples((n1, n2, n3), v, 0.5) for v in views)
+    tf = synth.tf_colour(256)
+    target_tf = synth.tf_perturbed(tf, c["tf_seed"])
+    params = vr.make_params(step=0.5, tau=2.0, ess=0, ckpt_K=32)
+    target = torch.empty((len(views), H, W, 4), device="cuda")
+    vr.vr_tf_set(ctx, target_tf, vmin, vmax, stream)
+    vr.vr_render(ctx, h, views, params, target, stream)
+    vr.vr_tf_set(ctx, tf, vmin, vmax, stream)
+    out = torch.empty_like(target)
+    gtf = torch.empty((256, 4), device="cuda")
+    gvol = torch.empty_like(dvol)
+
+    def fwd():
+        vr.vr_render(ctx, h, views, params, out, stream)
+
+    def fwd_bwd():
+        st = vr.vr_render(ctx, h, views, params, out, stream, save=True)
+        g = out - target
+        vr.vr_render_backward(ctx, h, st, g, gtf, gvol, False, stream)
+        vr.vr_state_destroy(st)
+
+    ms_f = _events_ms(fwd, 5, stream)
+    ms_fb = _events_ms(fwd_bwd, 3, stream)
+    vr.vr_volume_destroy(h)
+    log(f"fwd+bwd: forward {ms_f:.3f} ms, forward+backward {ms_fb:.3f} ms for {len(views)} views of 512^2")
+    return {"workload": "256x256x512 f32 cube, 8 views at 512x512, colour-ramp table, L2 loss against a "
+                        "perturbed-table target, checkpoints every 32 samples, gradients to table and voxels",
+            "ms_forward": round(ms_f, 4), "ms_forward_backward": round(ms_fb, 4),
+            "gsamples_per_s_forward": round(nominal / ms_f / 1e6, 3),
+            "gsamples_per_s_forward_backward": round(nominal / ms_fb / 1e6, 3),
+            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3), "nominal_samples": int(nominal)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,9 +157,15 @@ def main():
     ap.add_argument("--views", type=int, default=0, help="views per step (default: the config's)")
     ap.add_argument("--tf", default="ramp", choices=["ramp", "suppress"])
     ap.add_argument("--materialize", action="store_true")
+    ap.add_argument("--macrocell", type=int, default=16,
+                    help="macrocell edge for empty-space skipping (0: none; used by tables with zero opacity)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--oracle-seconds", type=float, default=15.0)
     ap.add_argument("--no-oracle", action="store_true")
+    ap.add_argument("--per-view", action="store_true", help="print each view's march time to stderr")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and forward+backward legs")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only run a device-to-device copy of this many GiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build renders on a single MI355X "
@@ -65,6 +175,15 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe * 2**30)
+        x = torch.ones(nbytes // 4, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "launches": 3}))
+        return
     cfg = synth.CONFIGS[args.config]
     n1, n2, n3 = cfg["dims"]
     W, H = cfg["image"]
@@ -80,7 +199,7 @@ def main():
     vmin, vmax = vr.vr_volume_minmax(h)
     log(f"uploaded + min/max in {time.time() - t0:.1f} s: range [{vmin:.3f}, {vmax:.3f}]")
     t0 = time.time()
-    vr.vr_volume_brick(h, vr.grid_spec(cfg["bricks"], materialize=args.materialize))
+    vr.vr_volume_brick(h, vr.grid_spec(cfg["bricks"], materialize=args.materialize, macrocell=args.macrocell))
     bricks = vr.vr_volume_brick_info(h)
     log(f"bricked into {len(bricks)} bricks in {time.time() - t0:.1f} s")
     if args.tf == "ramp":
@@ -115,6 +234,16 @@ def main():
             img_bytes += 16 * im.w * im.h
         imgs_per_view.append((brick_bytes, img_bytes, len(imgs)))
     torch.cuda.synchronize()
+
+    if args.per_view:
+        vr.vr_set_profiling(ctx, True)
+        for i, v in enumerate(views):
+            o1 = out[i:i + 1]
+            vr.vr_render(ctx, h, [v], params, o1, stream)
+            ms, cnt = vr.vr_stage_times(ctx)
+            d = views_R[i][2]
+            log(f"view {i:2d} dir ({d[0]:+.3f},{d[1]:+.3f},{d[2]:+.3f}): march {ms[vr.VR_STAGE_MARCH]:.3f} ms")
+        vr.vr_set_profiling(ctx, False)
 
     vr.vr_set_profiling(ctx, True)
     march_ms = []
@@ -155,7 +284,7 @@ def main():
                         f"{cfg['bricks'][0]}^3 bricks, {W}x{H} frames, {nviews} views/step, step 0.5, "
                         f"tau 0.99 local ERT, TF {args.tf}" + (", materialised bricks" if args.materialize else ""),
             "volume": [n1, n2, n3], "bricks": list(cfg["bricks"]), "image": [W, H], "views_per_step": nviews,
-            "tf": args.tf, "tile": args.tile or 8,
+            "tf": args.tf, "tile": args.tile or 8, "macrocell": args.macrocell,
         },
         "ms_per_frame": round(ms_step / nviews, 4),
         "nominal_samples_per_frame": int(nominal // nviews),
@@ -173,6 +302,10 @@ def main():
             "alg_bytes_per_launch": int(alg_bytes),
         },
     }
+
+    if not args.no_extras:
+        result["batched"] = bench_batched(ctx, stream)
+        result["fwd_bwd"] = bench_fwd_bwd(ctx, stream)
 
     if not args.no_oracle:
         import oracle

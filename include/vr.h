@@ -85,7 +85,8 @@ enum { VR_MODE_DVR = 0 };    /* emission-absorption with the over operator */
 typedef struct {
   double step;       /* sample spacing along the ray in voxels, > 0 (0.5 typical) */
   double tau;        /* stop a ray after the sample where 1 - T >= tau; tau >= 1 disables */
-  int32_t ess;       /* 1: skip bricks whose transfer-function opacity is 0 over their range */
+  int32_t ess;       /* 1: empty-space skipping: skip bricks, and slabs of macrocells (when the
+                        volume has them), whose transfer-function opacity is 0 over their range */
   int32_t ert_scope; /* VR_ERT_LOCAL */
   int32_t mode;      /* VR_MODE_DVR */
   int32_t ckpt_K;    /* adjoint: transmittance checkpoint interval in samples (>= 1; 32 typical) */
@@ -158,7 +159,7 @@ typedef struct {
   int32_t nparts;      /* LONGEST_AXIS: number of sub-volumes, in [1, 4096] */
   int64_t size[3];     /* GRID: brick edge in cells per axis, each >= 1 */
   int32_t ghost;       /* ghost layer width: must be 1 */
-  int32_t macrocell;   /* reserved, must be 0 */
+  int32_t macrocell;   /* macrocell edge in cells for empty-space skipping: 0 = none, else in [2, 1024] */
   int32_t materialize; /* 1: copy each brick and its ghost layer into its own storage */
   int32_t reserved;
 } vr_brick_spec;
@@ -171,9 +172,17 @@ typedef struct {
  * proportional position (paper Sec. 2.3, equal weights).  Computes per-brick
  * (min, max) over each brick's stored voxels (ownership box plus a 1-voxel
  * ghost layer, clipped to the volume) and, with materialize = 1, copies the
- * bricks.  Re-bricking replaces the previous partition.  Synchronises.
+ * bricks.  With macrocell = e > 0 it also computes a grid of macrocells over
+ * the whole volume: macrocell (m1, m2, m3) holds the cells whose lower corner
+ * index lies in [m_i e, (m_i + 1) e) on every axis, ceil((n_i - 1) / e) per
+ * axis, and its (min, max) is taken over the voxels [m_i e, min((m_i + 1) e,
+ * n_i - 1)] (every voxel a trilinear sample in those cells reads; NaN min
+ * when one of them is not finite).  Rendering with ess = 1 then skips the
+ * samples of any slab whose macrocells all have zero opacity over their range
+ * (the result is unchanged: such samples add nothing and leave T as it is).
+ * Re-bricking replaces the previous partition and macrocells.  Synchronises.
  * Errors: VR_EINVAL (spec NULL, size < 1, nparts out of range, ghost != 1,
- * macrocell != 0, more than 65536 bricks), VR_ENOMEM, VR_EHIP.
+ * macrocell outside {0} U [2, 1024], more than 65536 bricks), VR_ENOMEM, VR_EHIP.
  */
 int vr_volume_brick(vr_volume *vol, const vr_brick_spec *spec, uintptr_t stream);
 
@@ -191,6 +200,16 @@ typedef struct {
  * capacity in *nb).  Errors: VR_EINVAL (NULL nb, capacity too small).
  */
 int vr_volume_brick_info(const vr_volume *vol, int32_t *nb, vr_brick_desc *out);
+
+/*
+ * Macrocell grid of the last vr_volume_brick call: *edge (0 when none),
+ * count[3] macrocells per axis and, if minmax is non-NULL, their (min, max)
+ * pairs copied to host memory as [count3][count2][count1][2] float32 (the
+ * caller provides 2 * count1 * count2 * count3 floats; call first with
+ * minmax = NULL to learn the counts).  Synchronises.
+ * Errors: VR_EINVAL (NULL vol, edge or count), VR_EHIP.
+ */
+int vr_volume_macrocell_info(const vr_volume *vol, int32_t *edge, int64_t count[3], float *minmax);
 
 /* ------------------------------------------------------------------ transfer function */
 /*

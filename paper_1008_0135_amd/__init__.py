@@ -16,6 +16,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "libvr.so")
 
@@ -97,6 +99,7 @@ _SIGS = {
     "vr_volume_dims": (_I, [_P, _P]),
     "vr_volume_brick": (_I, [_P, _P, _U]),
     "vr_volume_brick_info": (_I, [_P, _P, _P]),
+    "vr_volume_macrocell_info": (_I, [_P, _P, _P, _P]),
     "vr_tf_set": (_I, [_P, _P, _I32, _D, _D, _I, _U]),
     "vr_render": (_I, [_P, _P, _P, _I32, _P, _P, _U, _P]),
     "vr_render_bricks": (_I, [_P, _P, _P, _P, _P, _P, _P, _U]),
@@ -180,21 +183,23 @@ def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0) -> vr_params:
     return p
 
 
-def grid_spec(size, materialize=False) -> vr_brick_spec:
+def grid_spec(size, materialize=False, macrocell=0) -> vr_brick_spec:
     s = vr_brick_spec()
     s.mode = VR_BRICK_GRID
     for i in range(3):
         s.size[i] = int(size[i])
     s.ghost = 1
+    s.macrocell = int(macrocell)
     s.materialize = int(bool(materialize))
     return s
 
 
-def kd_spec(nparts, materialize=False) -> vr_brick_spec:
+def kd_spec(nparts, materialize=False, macrocell=0) -> vr_brick_spec:
     s = vr_brick_spec()
     s.mode = VR_BRICK_LONGEST_AXIS
     s.nparts = int(nparts)
     s.ghost = 1
+    s.macrocell = int(macrocell)
     s.materialize = int(bool(materialize))
     return s
 
@@ -271,6 +276,20 @@ def vr_volume_brick_info(vol):
     arr = (vr_brick_desc * max(1, nb.value))()
     _check(lib().vr_volume_brick_info(vol, C.byref(nb), arr), "vr_volume_brick_info")
     return [arr[i] for i in range(nb.value)]
+
+
+def vr_volume_macrocell_info(vol):
+    """(edge, (c1, c2, c3), minmax [c3][c2][c1][2] float32 numpy array or None when edge is 0)."""
+    edge = C.c_int32(0)
+    cnt = (C.c_int64 * 3)()
+    _check(lib().vr_volume_macrocell_info(vol, C.byref(edge), cnt, None), "vr_volume_macrocell_info")
+    if edge.value == 0:
+        return 0, (0, 0, 0), None
+    c1, c2, c3 = cnt[0], cnt[1], cnt[2]
+    mm = np.empty((c3, c2, c1, 2), dtype=np.float32)
+    _check(lib().vr_volume_macrocell_info(vol, C.byref(edge), cnt, mm.ctypes.data_as(C.c_void_p)),
+           "vr_volume_macrocell_info")
+    return edge.value, (c1, c2, c3), mm
 
 
 def vr_tf_set(ctx, tf, vmin=0.0, vmax=0.0, stream=None):

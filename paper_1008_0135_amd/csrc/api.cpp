@@ -216,6 +216,71 @@ void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, d
   a.tile_h = 64 / a.tile_w;
 }
 
+// (Re)build the macrocell grid of edge mc over the whole volume (mc = 0: drop it).
+int build_macrocells(vr_volume* vol, int32_t mc, hipStream_t s) {
+  if (vol->d_mc_mm || vol->d_mc_clear) {
+    VR_HIP(hipStreamSynchronize(s));
+    if (vol->d_mc_mm) VR_HIP(hipFree(vol->d_mc_mm));
+    if (vol->d_mc_clear) VR_HIP(hipFree(vol->d_mc_clear));
+  }
+  vol->d_mc_mm = nullptr;
+  vol->d_mc_clear = nullptr;
+  vol->d_mc_count = nullptr;
+  vol->mc_nclear = 0;
+  vol->mc = 0;
+  vol->mc_classified = false;
+  for (int i = 0; i < 3; i++) vol->mcn[i] = 0;
+  if (mc == 0) return VR_OK;
+  int64_t c[3];
+  for (int i = 0; i < 3; i++) c[i] = (vol->n[i] - 1 + mc - 1) / mc;
+  const int64_t count = c[0] * c[1] * c[2];
+  if (count >= ((int64_t)1 << 31)) return fail(VR_EINVAL, "%lld macrocells: too many", (long long)count);
+  const size_t cbytes = ((size_t)count + 255) & ~(size_t)255;  // flags, then the clear-cell counter
+  if (hipMalloc(&vol->d_mc_mm, (size_t)count * 8) != hipSuccess ||
+      hipMalloc(&vol->d_mc_clear, cbytes + 256) != hipSuccess) {
+    (void)hipGetLastError();
+    if (vol->d_mc_mm) (void)hipFree(vol->d_mc_mm);
+    vol->d_mc_mm = nullptr;
+    vol->d_mc_clear = nullptr;
+    return fail(VR_ENOMEM, "hipMalloc for %lld macrocells failed", (long long)count);
+  }
+  vol->d_mc_count = reinterpret_cast<unsigned int*>(vol->d_mc_clear + cbytes);
+  VR_HIP(launch_mc_minmax(vol->data, vol->n, mc, c, vol->d_mc_mm, s));
+  VR_HIP(hipStreamSynchronize(s));
+  vol->mc = mc;
+  for (int i = 0; i < 3; i++) vol->mcn[i] = c[i];
+  return VR_OK;
+}
+
+int prepare_macrocells(vr_ctx* ctx, vr_volume* vol, const vr_params* p, double vmin, double vmax, MarchArgs& a,
+                       hipStream_t s) {
+  a.mc = 0;
+  a.mc_clear = nullptr;
+  for (int i = 0; i < 3; i++) a.mcn[i] = 0;
+  // nothing to skip unless a run of at least three table entries is fully
+  // transparent (a macrocell's entry range spans three or more entries)
+  if (!p->ess || vol->mc <= 0 || ctx->tf_zero_run < 3) return VR_OK;
+  if (!vol->mc_classified || vol->mc_tf_version != ctx->tf_version || vol->mc_vmin != vmin || vol->mc_vmax != vmax) {
+    VR_HIP(launch_mc_classify(vol->d_mc_mm, vol->mcn[0] * vol->mcn[1] * vol->mcn[2], ctx->d_tf_nz, ctx->tf_m, vmin,
+                              vmax, vol->d_mc_clear, vol->d_mc_count, s));
+    // one read-back per table or window change: with no clear macrocell the
+    // marches skip the per-slab test altogether
+    unsigned int nclear = 0;
+    VR_HIP(hipMemcpyAsync(&nclear, vol->d_mc_count, sizeof nclear, hipMemcpyDeviceToHost, s));
+    VR_HIP(hipStreamSynchronize(s));
+    vol->mc_nclear = nclear;
+    vol->mc_classified = true;
+    vol->mc_tf_version = ctx->tf_version;
+    vol->mc_vmin = vmin;
+    vol->mc_vmax = vmax;
+  }
+  if (vol->mc_nclear == 0) return VR_OK;
+  a.mc = vol->mc;
+  a.mc_clear = vol->d_mc_clear;
+  for (int i = 0; i < 3; i++) a.mcn[i] = (int32_t)vol->mcn[i];
+  return VR_OK;
+}
+
 }  // namespace vr
 
 // ====================================================================== ABI
@@ -251,7 +316,8 @@ int vr_create(int device, vr_ctx** out) {
   vr_ctx* ctx = new (std::nothrow) vr_ctx();
   if (!ctx) return fail(VR_ENOMEM, "out of host memory");
   ctx->device = device;
-  if (const char* m = std::getenv("VR_MARCH")) ctx->march_mode = std::strcmp(m, "gather") == 0 ? 1 : 0;
+  if (const char* m = std::getenv("VR_MARCH"))
+    ctx->march_mode = std::strcmp(m, "gather") == 0 ? 1 : std::strcmp(m, "slab") == 0 ? 2 : std::strcmp(m, "ring") == 0 ? 3 : 0;
   if (const char* b = std::getenv("VR_LDS_BUDGET")) {
     const long v = std::strtol(b, nullptr, 10);
     if (v >= 256 && v <= 32768) ctx->lds_budget = (int32_t)v;
@@ -280,6 +346,7 @@ int vr_destroy(vr_ctx* ctx) {
     if (sl.copied) (void)hipEventDestroy(sl.copied);
   }
   if (ctx->d_tf) (void)hipFree(ctx->d_tf);
+  if (ctx->d_tf_nz) (void)hipFree(ctx->d_tf_nz);
   if (ctx->d_arena) (void)hipFree(ctx->d_arena);
   if (ctx->d_small) (void)hipFree(ctx->d_small);
   if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
@@ -338,6 +405,7 @@ static int make_whole_brick(vr_volume* vol) {
   b.closed = 7;
   b.vmin = vol->vmin;
   b.vmax = vol->vmax;
+  b.slack = vol->owned ? 1 : 0;
   vol->whole = b;
   return VR_OK;
 }
@@ -378,7 +446,8 @@ int vr_volume_create(vr_ctx* ctx, const float* src, int src_on_device, int64_t n
   for (int i = 0; i < 3; i++) vol->n[i] = dn[i];
   const int64_t count = dn[0] * dn[1] * dn[2];
   const size_t bytes = (size_t)count * sizeof(float);
-  if (hipMalloc(&vol->data, bytes) != hipSuccess) {
+  // 64 floats of slack after the voxels: staged loads may read past a row's end
+  if (hipMalloc(&vol->data, bytes + 256) != hipSuccess) {
     (void)hipGetLastError();
     delete vol;
     return fail(VR_ENOMEM, "hipMalloc(%zu bytes) for the volume failed", bytes);
@@ -448,6 +517,8 @@ int vr_volume_destroy(vr_volume* vol) {
   if (vol->owned && vol->data) (void)hipFree(vol->data);
   if (vol->d_bricks) (void)hipFree(vol->d_bricks);
   if (vol->d_store) (void)hipFree(vol->d_store);
+  if (vol->d_mc_mm) (void)hipFree(vol->d_mc_mm);
+  if (vol->d_mc_clear) (void)hipFree(vol->d_mc_clear);
   delete vol;
   return VR_OK;
 }
@@ -477,7 +548,8 @@ int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream)
   clear_error();
   if (!vol || !spec) return fail(VR_EINVAL, "vol and spec must be non-NULL");
   if (spec->ghost != 1) return fail(VR_EINVAL, "ghost must be 1");
-  if (spec->macrocell != 0) return fail(VR_EINVAL, "macrocell must be 0");
+  if (spec->macrocell != 0 && (spec->macrocell < 2 || spec->macrocell > 1024))
+    return fail(VR_EINVAL, "macrocell %d outside {0} U [2, 1024]", spec->macrocell);
   Partition P;
   std::string err;
   if (spec->mode == VR_BRICK_GRID) {
@@ -522,6 +594,7 @@ int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream)
       for (int i = 0; i < 3; i++) c *= sboxes[6 * b + 3 + i] - sboxes[6 * b + i] + 1;
       total += (c + 63) & ~(int64_t)63;
     }
+    total += 64;  // slack after the last brick
     if (hipMalloc(&vol->d_store, (size_t)total * sizeof(float)) != hipSuccess) {
       (void)hipGetLastError();
       vol->d_store = nullptr;
@@ -577,6 +650,7 @@ int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream)
     }
     r.vmin = mm[2 * b];
     r.vmax = mm[2 * b + 1];
+    r.slack = (mat || vol->owned) ? 1 : 0;
     vr_brick_desc& d = vol->bdesc[b];
     for (int i = 0; i < 3; i++) {
       d.lo[i] = bx.lo[i];
@@ -603,6 +677,7 @@ int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream)
   vol->bricked = true;
   vol->materialized = mat;
   vol->version++;
+  VR_TRY(build_macrocells(vol, spec->macrocell, s));
   VR_TRY(ctx_end(ctx, s));
   return VR_OK;
 }
@@ -616,6 +691,19 @@ int vr_volume_brick_info(const vr_volume* vol, int32_t* nb, vr_brick_desc* out) 
     for (int32_t i = 0; i < have; i++) out[i] = vol->bdesc[i];
   }
   *nb = have;
+  return VR_OK;
+}
+
+int vr_volume_macrocell_info(const vr_volume* vol, int32_t* edge, int64_t count[3], float* minmax) {
+  clear_error();
+  if (!vol || !edge || !count) return fail(VR_EINVAL, "vol, edge and count must be non-NULL");
+  *edge = vol->mc;
+  for (int i = 0; i < 3; i++) count[i] = vol->mcn[i];
+  if (minmax && vol->mc > 0) {
+    DeviceGuard g(vol->ctx->device);
+    VR_HIP(hipMemcpy(minmax, vol->d_mc_mm, (size_t)(vol->mcn[0] * vol->mcn[1] * vol->mcn[2]) * 8,
+                     hipMemcpyDeviceToHost));
+  }
   return VR_OK;
 }
 
@@ -650,9 +738,31 @@ int vr_tf_set(vr_ctx* ctx, const float* rgba, int32_t m, double vmin, double vma
     }
     ctx->tf_cap = m;
   }
-  // synchronous copy: the host vector dies with this call
+  // prefix count of entries with opacity != 0 (macrocell classification)
+  std::vector<int32_t> nz((size_t)m + 1, 0);
+  for (int32_t i = 0; i < m; i++) nz[i + 1] = nz[i] + (h[4 * (size_t)i + 3] != 0.0f ? 1 : 0);
+  if (m + 1 > ctx->tf_nz_cap) {
+    if (ctx->d_tf_nz) VR_HIP(hipFree(ctx->d_tf_nz));
+    ctx->d_tf_nz = nullptr;
+    if (hipMalloc(&ctx->d_tf_nz, sizeof(int32_t) * ((size_t)m + 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->d_tf_nz = nullptr;
+      ctx->tf_nz_cap = 0;
+      return fail(VR_ENOMEM, "hipMalloc for the table's opacity prefix failed");
+    }
+    ctx->tf_nz_cap = m + 1;
+  }
+  // synchronous copies: the host vectors die with this call
   VR_HIP(hipMemcpyAsync(ctx->d_tf, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+  VR_HIP(hipMemcpyAsync(ctx->d_tf_nz, nz.data(), nz.size() * 4, hipMemcpyHostToDevice, s));
   VR_HIP(hipStreamSynchronize(s));
+  ctx->tf_zero = m - nz[(size_t)m];
+  int32_t run = 0, best_run = 0;
+  for (int32_t i = 0; i < m; i++) {
+    run = h[4 * (size_t)i + 3] == 0.0f ? run + 1 : 0;
+    best_run = std::max(best_run, run);
+  }
+  ctx->tf_zero_run = best_run;
   ctx->h_tf = std::move(h);
   ctx->tf_m = m;
   ctx->tf_vmin = vmin;

@@ -18,6 +18,11 @@ namespace {
 
 size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
+// Ring march limits: window floats per slot, and wavefronts per compute unit
+// the kernel's registers allow (78 VGPRs: 6 per SIMD).
+constexpr int32_t kRingCap = 3072;
+constexpr int32_t kRingMaxWaves = 24;
+
 }  // namespace
 
 // Plan one view of a bricked volume: rectangles, culling (empty rectangle or
@@ -74,6 +79,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   vr_params pt = *p;
   pt.tile = tuned_tile;
   fill_march_common(base, vol, &pt, vmin, vmax, ctx->d_tf, ctx->tf_m);
+  if (!extras) VR_TRY(prepare_macrocells(ctx, vol, p, vmin, vmax, base, s));
   const int32_t tw = base.tile_w, th = base.tile_h;
 
   std::vector<ViewPlan> plans((size_t)nviews);
@@ -147,11 +153,26 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       a.img = reinterpret_cast<float4*>(out);
     }
     if (extras) extras->prepare(a, v);
-    bool lds = false;
-    if (!extras && mode == 0) lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
+    bool lds = false, ring = false;
+    int ring_wpb = 4;
     a.lds_budget = budget;
+    if (!extras && mode == 3 && a.mc == 0 && a.tile_w == 8 &&
+        choose_ring(cams[v], kRingCap, a.slab_axis, a.ring_slot)) {
+      int waves = 0;
+      ring_wpb = ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves);
+      ring = waves >= 4;
+    }
+    if (!ring && !extras && (mode == 0 || mode == 2)) {
+      lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
+      // rays nearly parallel to axis 1 need a wider slab box: retry with twice the budget
+      if (!lds && budget < 8192 && choose_slab(cams[v], a.tile_w, a.tile_h, 8192, a.slab_axis, a.slab_T)) {
+        lds = true;
+        a.lds_budget = 8192;
+      }
+    }
     VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
-    VR_HIP(extras ? extras->launch(a, s) : (lds ? launch_march_lds(a, s) : launch_march(a, s)));
+    VR_HIP(extras ? extras->launch(a, s)
+                  : (ring ? launch_march_ring(a, ring_wpb, s) : (lds ? launch_march_lds(a, s) : launch_march(a, s))));
     VR_TRY(stage_end(ctx, s));
     if (bricked && out) {
       CompArgs c;

@@ -16,6 +16,9 @@
 //      their latency overlaps the sampling (a two-stage software pipeline),
 //   3. lets every lane consume its own samples whose cell layer along b lies
 //      in the slab, reading the eight trilinear corners from LDS.
+// With macrocells (empty-space skipping), a slab whose box touches only
+// macrocells of zero opacity is neither loaded nor sampled: its samples would
+// add nothing, so the lanes only advance their cursors past it.
 // Lanes carry their colour, transmittance and sample cursor from slab to
 // slab, so the per-ray result is the sequential front-to-back chain.  A
 // wavefront stops when all of its lanes have finished or terminated early.
@@ -59,6 +62,7 @@ struct Region {
   int pitch, layer, chunks;
   int cl, ch;  // cell layers of the slab along b
   bool staged;
+  bool skip;   // every macrocell holding a cell of the box has opacity 0 over its range
 };
 
 // Row, chunk-in-row, layer and row-in-layer of chunk i (reciprocal products;
@@ -79,11 +83,14 @@ __device__ __forceinline__ ChunkPos chunk_pos(int i, int nf4, int ng, float inv_
 
 // Issue the global loads of a region's chunks into registers (lane-contiguous
 // chunks, so one instruction reads 1 KB of consecutive row segments).  Every
-// chunk is a full 16-byte load inside its row: the last chunk of a row starts
-// at nf - 4 instead of 4*c4 (store_region shifts it back), so no load result
-// is consumed here and no wait is needed until the LDS store.
+// chunk is a full 16-byte load: with slack after the storage the last chunk of
+// a row simply reads past the row's end (the extra floats land in the row's
+// LDS padding); without it the chunk starts at nf - 4 instead (store_region
+// shifts it back).  No load result is consumed here, so no wait is needed
+// until the LDS store.
 template <int CH>
-__device__ __forceinline__ void issue_loads(const Region& r, gfloat* gbase, int sB, int sG, int lane, float4 (&buf)[CH]) {
+__device__ __forceinline__ void issue_loads(const Region& r, gfloat* gbase, int sB, int sG, int lane, bool slack,
+                                            float4 (&buf)[CH]) {
   const int nf4 = r.pitch >> 2;
   const float inv_nf4 = 1.0f / (float)nf4, inv_ng = 1.0f / (float)r.ng;
 #pragma unroll
@@ -91,7 +98,7 @@ __device__ __forceinline__ void issue_loads(const Region& r, gfloat* gbase, int 
     const int i = lane + 64 * k;
     if (i < r.chunks) {
       const ChunkPos c = chunk_pos(i, nf4, r.ng, inv_nf4, inv_ng);
-      const int f0 = min(4 * c.c4, r.nf - 4);
+      const int f0 = slack ? 4 * c.c4 : min(4 * c.c4, r.nf - 4);
       gfloat* src = gbase + ((r.b_lo + c.lb) * sB + (r.g_lo + c.lg) * sG + (r.f_lo + f0));
       const f4u v = *reinterpret_cast<const f4u __attribute__((address_space(1)))*>(src);
       buf[k] = make_float4(v.x, v.y, v.z, v.w);
@@ -100,7 +107,15 @@ __device__ __forceinline__ void issue_loads(const Region& r, gfloat* gbase, int 
 }
 
 template <int CH>
-__device__ __forceinline__ void store_region(const Region& r, float* s_reg, int lane, const float4 (&buf)[CH]) {
+__device__ __forceinline__ void store_region(const Region& r, float* s_reg, int lane, bool slack, const float4 (&buf)[CH]) {
+  if (slack) {  // chunks were read at their own position: store as loaded
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int i = lane + 64 * k;
+      if (i < r.chunks) reinterpret_cast<float4*>(s_reg)[i] = buf[k];
+    }
+    return;
+  }
   const int nf4 = r.pitch >> 2;
   const float inv_nf4 = 1.0f / (float)nf4, inv_ng = 1.0f / (float)r.ng;
 #pragma unroll
@@ -173,6 +188,7 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
   const float pb = by ? py : pz, sb = by ? sy : sz;
   const int cloB = by ? br.clo[1] : br.clo[2], chiB = by ? br.chi[1] : br.chi[2];
   const int cloG = by ? br.clo[2] : br.clo[1], chiG = by ? br.chi[2] : br.chi[1];
+  const int loB = by ? br.lo[1] : br.lo[2], loG = by ? br.lo[2] : br.lo[1];
   const double db = by ? d[1] : d[2], dg = by ? d[2] : d[1];
   const bool up = db > 0.0;
 
@@ -240,7 +256,25 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
     r.pitch = (max(r.nf, 1) + 3) & ~3;
     r.layer = r.pitch * r.ng;
     r.chunks = (r.pitch >> 2) * r.ng * r.nl;
-    r.staged = r.nf >= 4 && r.ng > 0 && r.layer * r.nl <= min(a.lds_budget, capacity);
+    r.skip = false;
+    if (a.mc > 0) {
+      // macrocells of the cells (global lower-corner indices) the slab's samples can use
+      const int mc = a.mc;
+      const int mf0 = (r.f_lo + br.lo[0]) / mc, mf1 = (max(f_hi - 1, r.f_lo) + br.lo[0]) / mc;
+      const int mg0 = (r.g_lo + loG) / mc, mg1 = (max(g_hi - 1, r.g_lo) + loG) / mc;
+      const int mb0 = (r.cl + loB) / mc, mb1 = (r.ch + loB) / mc;
+      const int nmf = mf1 - mf0 + 1, nmg = mg1 - mg0 + 1;
+      const int tot = nmf * nmg * (mb1 - mb0 + 1);
+      bool opaque = false;
+      for (int i = lane; i < tot; i += 64) {
+        const int qf = i % nmf, rest = i / nmf;
+        const int mg = mg0 + rest % nmg, mb = mb0 + rest / nmg;
+        const int my = by ? mb : mg, mz = by ? mg : mb;
+        opaque |= a.mc_clear[((int64_t)mz * a.mcn[1] + my) * a.mcn[0] + (mf0 + qf)] == 0;
+      }
+      r.skip = !__any(opaque);
+    }
+    r.staged = !r.skip && r.nf >= 4 && r.ng > 0 && r.layer * r.nl <= min(a.lds_budget, capacity);
     return r;
   };
 
@@ -252,11 +286,12 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
   float4 buf[CH];
   int L = Lbeg;
   Region nxt = region_of(L);
-  if (nxt.staged) issue_loads<CH>(nxt, gbase, strideB, strideG, lane, buf);
+  const bool slack = br.slack != 0;
+  if (nxt.staged) issue_loads<CH>(nxt, gbase, strideB, strideG, lane, slack, buf);
   for (;;) {
     const Region cur = nxt;
     if (cur.staged) {
-      store_region<CH>(cur, s_reg, lane, buf);
+      store_region<CH>(cur, s_reg, lane, slack, buf);
       __syncthreads();
     }
     // prefetch the next slab while this one is sampled
@@ -264,22 +299,35 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
     if (!last) {
       L += step_l;
       nxt = region_of(L);
-      if (nxt.staged) issue_loads<CH>(nxt, gbase, strideB, strideG, lane, buf);
+      if (nxt.staged) issue_loads<CH>(nxt, gbase, strideB, strideG, lane, slack, buf);
     }
     // ---- consume the lane's samples whose cell layer along b is in [cl, ch]
     const int Sy = by ? cur.layer : cur.pitch, Sz = by ? cur.pitch : cur.layer;
     const int oy = by ? cur.b_lo : cur.g_lo, oz = by ? cur.g_lo : cur.b_lo;
-    const int omax = cur.layer * cur.nl - 1 - (Sy + Sz + 1);
+    const int obase = cur.f_lo + oy * Sy + oz * Sz;
     // Two separate loops: the LDS loop must not share a block with global
     // loads, or the wait for those would also wait for the prefetch above.
-    if (cur.staged) {
+    // a sample is in the slab while its cell layer (signed by the march
+    // direction) has not passed the slab's last layer
+    const int lim = up ? cur.ch : -cur.cl;
+    if (cur.skip) {
+      // every sample in the slab has opacity 0 (adds nothing, leaves T as it
+      // is, cannot trigger termination): only move the cursor past them, with
+      // the same layer test as the sampling loops
+      const float fclo = (float)cloB, fchi = (float)chiB;
+      while (!done) {
+        const int ib = (int)floorf(__builtin_amdgcn_fmed3f(fmaf((float)j, sb, pb), fclo, fchi));
+        if ((up ? ib : -ib) > lim) break;
+        ++j;
+        if (j >= cnt) done = true;
+      }
+    } else if (cur.staged) {
       while (!done) {
         const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
         const int ib = by ? c.iy : c.iz;
-        if (up ? ib > cur.ch : ib < cur.cl) break;
-        int oo = (c.ix - cur.f_lo) + (c.iy - oy) * Sy + (c.iz - oz) * Sz;
-        oo = min(max(oo, 0), omax);
-        const float* p = s_reg + oo;
+        if ((up ? ib : -ib) > lim) break;
+        // the cell lies in the slab's box by construction (footprint + margins)
+        const float* p = s_reg + (c.ix + c.iy * Sy + c.iz * Sz - obase);
         const float val = trilerp(p[0], p[1], p[Sy], p[Sy + 1], p[Sz], p[Sz + 1], p[Sz + Sy], p[Sz + Sy + 1], c);
         accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
         ++j;
@@ -289,7 +337,7 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
       while (!done) {
         const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
         const int ib = by ? c.iy : c.iz;
-        if (up ? ib > cur.ch : ib < cur.cl) break;
+        if ((up ? ib : -ib) > lim) break;
         gfloat* p = gbase + (c.iz * zsl + c.iy * ysl + c.ix);
         const float val = trilerp(p[0], p[1], p[ysl], p[ysl + 1], p[zsl], p[zsl + 1], p[zsl + ysl], p[zsl + ysl + 1], c);
         accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);

@@ -1,0 +1,321 @@
+// march_ring.hip -- forward march with per-layer voxel windows kept in an LDS
+// ring and filled by direct global->LDS loads (gfx950).
+//
+// Same samples, same per-sample arithmetic and the same order as the gather
+// march (paper Sec. 2.4: each ray is sampled between its entry and exit points
+// and accumulated front to back with early termination); only the way the
+// eight trilinear corners reach the lanes differs.
+//
+// A wavefront owns an 8 x 8 tile of pixel rays inside one brick and walks the
+// brick one cell layer at a time along a slab axis b (y or z, chosen per view
+// on the host so that rows along x -- the contiguous storage axis -- stay
+// long).  Cell layer c is sampled from voxel layers c and c + 1.  For every
+// voxel layer V the wavefront loads a window of rows along x: the box that
+// holds the cells of every sample of its 64 rays lying between the planes
+// b = V - 1 and b = V + 1, bounded from the four corner rays of the tile (the
+// rays are parallel, so the corners bound the bundle on any plane).  Windows
+// go into a ring of three LDS slots: while cell layer c is sampled from the
+// slots of V = c and c + 1, the window of the layer after next is already in
+// flight (global_load_lds_dwordx4: 16 bytes per lane straight into LDS, no
+// registers, no store instructions).  Every voxel layer is read once per
+// tile, with no halo layer read twice.
+//
+// The layer index, the window origins and the slot addresses are uniform over
+// the wavefront (scalar registers); lanes step through their own samples of
+// the current layer (two to three on typical views).  Four wavefronts share a
+// workgroup only to share the transfer-function table in LDS; after loading it
+// each wavefront runs on its own, with no workgroup barrier.
+#include "sample.h"
+#include "vr_internal.h"
+
+namespace vr {
+
+namespace {
+
+typedef const float __attribute__((address_space(1))) gfloat;
+
+constexpr int kSlots = 3;
+
+__device__ __forceinline__ float wmin4(float v) {
+  v = fminf(v, __shfl_xor(v, 1));
+  return fminf(v, __shfl_xor(v, 2));
+}
+__device__ __forceinline__ float wmax4(float v) {
+  v = fmaxf(v, __shfl_xor(v, 1));
+  return fmaxf(v, __shfl_xor(v, 2));
+}
+__device__ __forceinline__ int wave_imin(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ int wave_imax(int v) {
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Wait until every global->LDS load this wavefront issued has landed (the
+// memory clobber keeps LDS reads from moving above the wait).
+__device__ __forceinline__ void wait_loads() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 16 bytes per lane from global memory straight into LDS at lds_base + 16 lane
+// (lds_base is a byte address, uniform over the wavefront).  Written as inline
+// assembly so that the compiler does not guard later LDS reads with waits for
+// these loads: the code waits for them explicitly with wait_loads().
+__device__ __forceinline__ void lds_dma16(gfloat* src, unsigned lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+               :
+               : "v"(src), "s"(lds_base)
+               : "memory", "m0");
+}
+
+__device__ __forceinline__ unsigned lds_addr(const float* p) {
+  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float*)p;
+}
+
+// Window of one voxel layer: rows along axis 1 (f), `pitch` floats each, NG rows
+// along the in-plane axis g; origin (f0, g0) in brick-local voxel indices.
+struct Window {
+  int f0, g0;
+};
+
+__global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
+  extern __shared__ float4 smem[];
+  float4* s_tf = smem;
+  for (int i = threadIdx.x; i < a.M; i += blockDim.x) s_tf[i] = a.tf[i];
+  __syncthreads();
+
+  const int wpb = (int)(blockDim.x >> 6);
+  const int wave = uni((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int slot = a.ring_slot;  // floats per ring slot
+  float* s_ring = reinterpret_cast<float*>(smem + a.M) + (size_t)wave * kSlots * slot;
+
+  // XCD-aware order: workgroup b runs on XCD b % 8; give each XCD a
+  // contiguous range of tiles so that neighbouring tiles share its L2
+  const int ngroups = (a.ntiles + wpb - 1) / wpb;
+  const int per = (ngroups + 7) >> 3;
+  const int tile = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * wpb + wave;
+  if (tile >= a.ntiles) return;
+
+  int lo = 0, hi = a.nbv - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.bv[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  const DevBrickView bvw = a.bv[lo];
+  const DevBrick br = a.bricks[bvw.brick];
+  const int t = tile - bvw.tile_begin;
+  const int tx = t % bvw.tiles_x, ty = t / bvw.tiles_x;
+  const int lx = tx * 8 + (lane & 7), ly = ty * 8 + (lane >> 3);
+  const bool valid = lx < bvw.w && ly < bvw.h;
+  const int u = bvw.x0 + min(lx, bvw.w - 1), v = bvw.y0 + min(ly, bvw.h - 1);
+
+  // ---- per-lane ray setup (double precision, shared with every march)
+  const double* d = a.cam.e3;
+  double o[3];
+  pixel_origin(a.cam, u, v, o);
+  int cnt = 0;
+  float px = 0.f, py = 0.f, pz = 0.f;
+  double tin;
+  int64_t n;
+  if (valid && ray_lattice(o, d, a.hi, a.step, tin, n)) {
+    int64_t k0, k1;
+    brick_krange(o, d, tin, a.step, n, br.lo, br.hi, br.closed, k0, k1);
+    if (k1 > k0) {
+      const double t0 = tin + ((double)k0 + 0.5) * a.step;
+      px = (float)(o[0] + t0 * d[0] - (double)br.lo[0]);
+      py = (float)(o[1] + t0 * d[1] - (double)br.lo[1]);
+      pz = (float)(o[2] + t0 * d[2] - (double)br.lo[2]);
+      cnt = (int)(k1 - k0);
+    }
+  }
+  const float sx = (float)(a.step * d[0]), sy = (float)(a.step * d[1]), sz = (float)(a.step * d[2]);
+
+  // ---- frame: b = slab axis (axis 2 or 3), g = the other of axes 2/3, f = axis 1
+  const bool by = a.slab_axis == 1;
+  const float pb = by ? py : pz, sb = by ? sy : sz;
+  const int cloB = by ? br.clo[1] : br.clo[2], chiB = by ? br.chi[1] : br.chi[2];
+  const int cloG = by ? br.clo[2] : br.clo[1], chiG = by ? br.chi[2] : br.chi[1];
+  const int cloF = br.clo[0], chiF = br.chi[0];
+  const double db = by ? d[1] : d[2], dg = by ? d[2] : d[1];
+  const bool up = db > 0.0;
+
+  // cell layers (along b) of the lane's first and last samples
+  int c_first = up ? 0x7fffffff : -0x7fffffff, c_last = up ? -0x7fffffff : 0x7fffffff;
+  if (cnt > 0) {
+    c_first = (int)floorf(__builtin_amdgcn_fmed3f(pb, (float)cloB, (float)chiB));
+    c_last = (int)floorf(__builtin_amdgcn_fmed3f(fmaf((float)(cnt - 1), sb, pb), (float)cloB, (float)chiB));
+  }
+  int Lbeg, Lend;  // first and last cell layer in marching order
+  if (up) {
+    Lbeg = uni(wave_imin(c_first));
+    Lend = uni(wave_imax(c_last));
+  } else {
+    Lbeg = uni(wave_imax(c_first));
+    Lend = uni(wave_imin(c_last));
+  }
+  float4* dst = a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
+  if (up ? Lbeg > Lend : Lbeg < Lend) {
+    if (valid) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
+
+  // ---- window geometry from the tile's corner rays (lanes 0..3)
+  // A corner ray meets the plane b = P at f = Af + P rf, g = Ag + P rg.
+  const double rfd = d[0] / db, rgd = dg / db;
+  const float rf = (float)rfd, rg = (float)rgd;
+  float Af, Ag;
+  {
+    const int cx = bvw.x0 + tx * 8, cy = bvw.y0 + ty * 8;
+    const int ex = min(cx + 7, bvw.x0 + bvw.w - 1), ey = min(cy + 7, bvw.y0 + bvw.h - 1);
+    const int cc = lane & 3;
+    double oc[3];
+    pixel_origin(a.cam, (cc & 1) ? ex : cx, (cc & 2) ? ey : cy, oc);
+    const double ob = (by ? oc[1] : oc[2]) - (double)(by ? br.lo[1] : br.lo[2]);
+    Af = (float)(oc[0] - (double)br.lo[0] - ob * rfd);
+    Ag = (float)((by ? oc[2] : oc[1]) - (double)(by ? br.lo[2] : br.lo[1]) - ob * rgd);
+  }
+  const float Af_lo = unif(wmin4(Af)), Af_hi = unif(wmax4(Af));
+  const float Ag_lo = unif(wmin4(Ag)), Ag_hi = unif(wmax4(Ag));
+  const float arf = fabsf(rf), arg = fabsf(rg);
+  // window extents: f_hi - f_lo + 1 <= floor(span + 0.1) + 3 for the 0.05 margins
+  const int NF = uni((int)floorf(Af_hi - Af_lo + 2.f * arf + 0.2f) + 3);
+  const int pitch = (NF + 3) & ~3;
+  int NG = uni((int)floorf(Ag_hi - Ag_lo + 2.f * arg + 0.2f) + 3);
+  NG = min(NG, chiG + 2 - cloG);
+  const int ysl = br.sy, zsl = br.sz;
+  const int sB = by ? ysl : zsl, sG = by ? zsl : ysl;
+  gfloat* gbase = (gfloat*)br.base;
+
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
+  int j = 0;
+  bool done = cnt == 0;
+
+  if (pitch > chiF + 2 - cloF || pitch * NG > slot || (int64_t)NG * sG + pitch >= ((int64_t)1 << 31)) {
+    // the window does not fit: read the corners from global memory
+    while (!done) {
+      const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
+      gfloat* p = gbase + (c.iz * zsl + c.iy * ysl + c.ix);
+      const float val = trilerp(p[0], p[1], p[ysl], p[ysl + 1], p[zsl], p[zsl + 1], p[zsl + ysl], p[zsl + ysl + 1], c);
+      accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+      ++j;
+      if (j >= cnt || 1.f - T >= a.tau) done = true;
+    }
+    if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
+    return;
+  }
+
+  // window of voxel layer V (brick-local): rows [g0, g0 + NG), columns [f0, f0 + pitch)
+  auto window = [&](int V) {
+    Window w;
+    const float Pf = (float)V * rf, Pg = (float)V * rg;
+    const int flo = max((int)floorf(Af_lo + Pf - arf - 0.05f), cloF);
+    const int glo = max((int)floorf(Ag_lo + Pg - arg - 0.05f), cloG);
+    w.f0 = uni(max(cloF, min(flo, chiF + 2 - pitch)));
+    w.g0 = uni(max(cloG, min(glo, chiG + 2 - NG)));
+    return w;
+  };
+  // chunk (16 bytes) i of a window: row i / (pitch / 4), column 4 (i % (pitch / 4))
+  const int nf4 = pitch >> 2;
+  const int chunks = nf4 * NG;
+  const int nload = (chunks + 63) >> 6;  // load instructions per layer
+  // row r and column chunk c4 of chunk lane + 64 k (offset r sG + 4 c4 floats
+  // from the window origin) advance by (dr, dc) per instruction
+  const int r0 = lane / nf4, c0 = lane - r0 * nf4, off0 = r0 * sG + 4 * c0;
+  const int dr = uni(64 / nf4), dc = uni(64 - dr * nf4);
+  const int doff = uni(dr * sG + 4 * dc), dwrap = uni(sG - 4 * nf4);
+  auto issue = [&](int V, const Window& w, float* sdst) {
+    gfloat* lbase = gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0);
+    const unsigned lds0 = uni(lds_addr(sdst));
+    int r = r0, c4 = c0, off = off0;
+    for (int k = 0; k < nload; ++k) {
+      if (r < NG) lds_dma16(lbase + off, lds0 + 1024u * k);
+      c4 += dc;
+      r += dr;
+      off += doff;
+      if (c4 >= nf4) {
+        c4 -= nf4;
+        ++r;
+        off += dwrap;
+      }
+    }
+  };
+
+  // voxel layers in marching order: V_k = Lbeg + k (up) or Lbeg + 1 - k (down);
+  // cell layer c_k = Lbeg +- k reads V_k and V_{k+1}
+  const int nlay = up ? Lend - Lbeg + 1 : Lbeg - Lend + 1;  // cell layers
+  const int vstep = up ? 1 : -1;
+  const int V0 = up ? Lbeg : Lbeg + 1;
+  Window w0 = window(V0), w1 = window(V0 + vstep);
+  issue(V0, w0, s_ring);
+  issue(V0 + vstep, w1, s_ring + slot);
+  int s0 = 0;  // slot of V_k
+  const float fclo = (float)cloB, fchi = (float)chiB;
+  for (int k = 0; k < nlay; ++k) {
+    wait_loads();  // V_k and V_{k+1} are in LDS
+    // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished)
+    const int s1 = s0 == kSlots - 1 ? 0 : s0 + 1;
+    const int s2 = s1 == kSlots - 1 ? 0 : s1 + 1;
+    Window w2;
+    if (k + 1 < nlay) {
+      const int V2 = V0 + (k + 2) * vstep;
+      w2 = window(V2);
+      issue(V2, w2, s_ring + s2 * slot);
+    }
+    // lower and upper voxel layer of cell layer c_k
+    const int c = up ? Lbeg + k : Lbeg - k;
+    const Window& wl = up ? w0 : w1;
+    const Window& wu = up ? w1 : w0;
+    const int sl = up ? s0 : s1, su = up ? s1 : s0;
+    const float* baseL = s_ring + (sl * slot - wl.g0 * pitch - wl.f0);
+    const int dU = (su * slot - wu.g0 * pitch - wu.f0) - (sl * slot - wl.g0 * pitch - wl.f0);
+    while (!done) {
+      const SamplePos q = sample_pos(j, px, py, pz, sx, sy, sz);
+      const int ib = (int)floorf(__builtin_amdgcn_fmed3f(by ? q.y : q.z, fclo, fchi));
+      if (ib != c) break;
+      const Cell cl = cell_of(q, br);
+      const int ig = by ? cl.iz : cl.iy;
+      const float* p = baseL + (ig * pitch + cl.ix);
+      const float* pu = p + dU;
+      // corners v[dz][dy][dx]: within a window rows run along g, layers along b
+      const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];
+      const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
+      const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
+                           : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
+      accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+      ++j;
+      if (j >= cnt || 1.f - T >= a.tau) done = true;
+    }
+    if (__all(done)) break;
+    s0 = s1;
+    w0 = w1;
+    w1 = w2;
+  }
+  wait_loads();  // no load may still target LDS when the wavefront ends
+  if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
+}
+
+}  // namespace
+
+size_t ring_lds_bytes(const MarchArgs& a, int wpb) {
+  return sizeof(float4) * (size_t)a.M + sizeof(float) * (size_t)wpb * kSlots * (size_t)a.ring_slot;
+}
+
+hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4))
+    return hipErrorInvalidValue;
+  const int groups = (a.ntiles + wpb - 1) / wpb;
+  const int grid = ((groups + 7) / 8) * 8;
+  hipLaunchKernelGGL(k_march_ring, dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a);
+  return hipGetLastError();
+}
+
+}  // namespace vr

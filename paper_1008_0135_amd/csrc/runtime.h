@@ -50,6 +50,10 @@ struct vr_ctx {
   double tf_vmin = 0.0, tf_vmax = 0.0;
   bool tf_set = false;
   uint64_t tf_version = 0;
+  int32_t* d_tf_nz = nullptr;  // [M + 1] prefix count of entries with opacity != 0
+  int32_t tf_nz_cap = 0;
+  int32_t tf_zero = 0;         // entries with opacity == 0
+  int32_t tf_zero_run = 0;     // longest run of consecutive entries with opacity == 0
   // brick-image arena and general scratch
   void* d_arena = nullptr;
   size_t arena_bytes = 0;
@@ -79,7 +83,8 @@ struct vr_ctx {
   std::vector<Timed> timed;
   std::vector<hipEvent_t> event_pool;
   hipStream_t prof_stream = nullptr;
-  // march selection: 0 = LDS-staged slabs when a slab fits, else gather; 1 = gather only
+  // march selection: 0 = automatic (LDS-staged slabs when a slab fits, else gather);
+  // 1 = gather only; 2 = LDS-staged slabs (else gather); 3 = per-layer ring (else as 0)
   int32_t march_mode = 0;
   int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
@@ -107,6 +112,17 @@ struct vr_volume {
   std::vector<vr_brick_desc> bdesc;
   vr::DevBrick* d_bricks = nullptr;
   float* d_store = nullptr;  // materialised brick storage
+  // macrocells (empty-space skipping): edge in cells, counts, (min, max), and the
+  // per-table "opacity is 0 over the range" flags with the table they were made for
+  int32_t mc = 0;
+  int64_t mcn[3] = {0, 0, 0};
+  float* d_mc_mm = nullptr;
+  uint8_t* d_mc_clear = nullptr;
+  unsigned int* d_mc_count = nullptr;  // clear macrocells of the last classification
+  int64_t mc_nclear = 0;
+  bool mc_classified = false;
+  uint64_t mc_tf_version = 0;
+  double mc_vmin = 0.0, mc_vmax = 0.0;
   uint64_t version = 0;
 };
 
@@ -125,6 +141,10 @@ int check_params(const vr_params* p);
 int resolve_window(vr_ctx* ctx, vr_volume* vol, hipStream_t s, double& vmin, double& vmax);
 void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, double vmin, double vmax,
                        const float4* tf, int32_t M);
+// Macrocell skipping for a forward march: classifies the macrocells for the
+// context's table and window when needed and fills a.mc* (a.mc = 0: off).
+int prepare_macrocells(vr_ctx* ctx, vr_volume* vol, const vr_params* p, double vmin, double vmax, MarchArgs& a,
+                       hipStream_t s);
 // Tuned launch shape for a render (tile edge, LDS budget, march mode); defaults when untuned.
 void tuned_shape(const vr_ctx* ctx, const vr_volume* vol, int32_t W, int32_t H, const vr_params* p, int32_t& tile,
                  int32_t& budget, int32_t& mode);

@@ -25,14 +25,19 @@ struct Cell {
   float wx, wy, wz;
 };
 
+// clamp(floor(q), lo, hi) == floor(clamp(q, lo, hi)) for integer bounds, and the
+// clamp of q is one v_med3_f32; the fraction reuses the floored float.
 __device__ __forceinline__ Cell cell_of(const SamplePos& q, const DevBrick& br) {
   Cell c;
-  c.ix = min(max((int)floorf(q.x), br.clo[0]), br.chi[0]);
-  c.iy = min(max((int)floorf(q.y), br.clo[1]), br.chi[1]);
-  c.iz = min(max((int)floorf(q.z), br.clo[2]), br.chi[2]);
-  c.wx = q.x - (float)c.ix;
-  c.wy = q.y - (float)c.iy;
-  c.wz = q.z - (float)c.iz;
+  const float fx = floorf(__builtin_amdgcn_fmed3f(q.x, (float)br.clo[0], (float)br.chi[0]));
+  const float fy = floorf(__builtin_amdgcn_fmed3f(q.y, (float)br.clo[1], (float)br.chi[1]));
+  const float fz = floorf(__builtin_amdgcn_fmed3f(q.z, (float)br.clo[2], (float)br.chi[2]));
+  c.ix = (int)fx;
+  c.iy = (int)fy;
+  c.iz = (int)fz;
+  c.wx = q.x - fx;
+  c.wy = q.y - fy;
+  c.wz = q.z - fz;
   return c;
 }
 

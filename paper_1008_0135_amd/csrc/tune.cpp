@@ -58,7 +58,7 @@ void tune_load(vr_ctx* ctx) {
       ctx->tune_waves_per_cu = tile;
       continue;
     }
-    if ((tile == 4 || tile == 8 || tile == 16) && budget >= 256 && budget <= 32768 && (mode == 0 || mode == 1))
+    if ((tile == 4 || tile == 8 || tile == 16) && budget >= 256 && budget <= 32768 && mode >= 0 && mode <= 3)
       ctx->tune.push_back(vr_ctx::TuneEntry{key, tile, budget, mode, ms});
   }
   std::fclose(f);

@@ -1,7 +1,9 @@
 // volume.hip -- once-per-cube kernels: global (min, max) with a non-finite
 // count (paper Sec. 2.2: each GPU reduces its portion, the results are
 // combined into the global range), per-brick (min, max) over each brick's
-// stored voxels, and box copies (sub-cube upload, brick materialisation).
+// stored voxels, box copies (sub-cube upload, brick materialisation), and the
+// macrocell (min, max) grid with its per-table classification used for
+// empty-space skipping.
 #include "vr_internal.h"
 
 namespace vr {
@@ -133,6 +135,83 @@ __global__ __launch_bounds__(256) void k_copy_box(const float* __restrict__ src,
   }
 }
 
+// Macrocell (min, max).  A work unit is (run of `per` macrocells along axis 1,
+// macrocell row m2, macrocell plane m3): its threads first reduce each voxel
+// column x of the unit over the unit's (mc + 1)^2 rows (coalesced row reads)
+// into LDS, then one thread per macrocell reduces its mc + 1 columns.
+constexpr int kMcCols = 2049;  // per * mc + 1 with per = floor(2048 / mc)
+
+__global__ __launch_bounds__(256) void k_mc_minmax(const float* __restrict__ vol, int64_t n1, int64_t n2, int64_t n3,
+                                                   int mc, int per, int64_t c1, int64_t c2, int64_t c3,
+                                                   float2* __restrict__ out) {
+  __shared__ float s_mn[kMcCols], s_mx[kMcCols];
+  const int64_t runs = (c1 + per - 1) / per;
+  const int64_t units = runs * c2 * c3;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t r = u % runs, m2 = (u / runs) % c2, m3 = u / (runs * c2);
+    const int64_t m1 = r * per;
+    const int64_t x0 = m1 * mc, x1 = min(x0 + (int64_t)per * mc, n1 - 1);
+    const int64_t y0 = m2 * mc, y1 = min(y0 + mc, n2 - 1);
+    const int64_t z0 = m3 * mc, z1 = min(z0 + mc, n3 - 1);
+    const int ncol = (int)(x1 - x0 + 1);
+    for (int c = threadIdx.x; c < ncol; c += 256) {
+      float mn = INFINITY, mx = -INFINITY;
+      bool bad = false;
+      for (int64_t z = z0; z <= z1; z++) {
+        const float* col = vol + (z * n2 + y0) * n1 + x0 + c;
+#pragma unroll 4
+        for (int64_t y = 0; y <= y1 - y0; y++) {
+          const float v = col[y * n1];
+          bad |= !isfinite(v);
+          mn = fminf(mn, v);
+          mx = fmaxf(mx, v);
+        }
+      }
+      s_mn[c] = bad ? NAN : mn;
+      s_mx[c] = mx;
+    }
+    __syncthreads();
+    const int nm = (int)min((int64_t)per, c1 - m1);
+    for (int m = threadIdx.x; m < nm; m += 256) {
+      const int a = m * mc, b = min(a + mc, ncol - 1);
+      float mn = INFINITY, mx = -INFINITY;
+      bool bad = false;
+      for (int c = a; c <= b; c++) {
+        bad |= isnan(s_mn[c]);
+        mn = fminf(mn, s_mn[c]);
+        mx = fmaxf(mx, s_mx[c]);
+      }
+      out[(m3 * c2 + m2) * c1 + m1 + m] = make_float2(bad ? NAN : mn, mx);
+    }
+    __syncthreads();
+  }
+}
+
+// Same rule as the host's brick test: entries floor(u(min)) - 1 .. ceil(u(max)) + 1
+// (clamped to the table) must all have opacity 0; the one-entry margin covers
+// the rounding of a single-precision trilinear value and table coordinate.
+__global__ __launch_bounds__(256) void k_mc_classify(const float2* __restrict__ mm, int64_t count,
+                                                     const int32_t* __restrict__ nz, int M, double vmin, double vmax,
+                                                     uint8_t* __restrict__ clear, unsigned int* nclear) {
+  unsigned int mine = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (int64_t)gridDim.x * 256) {
+    const float2 r = mm[i];
+    uint8_t c = 0;
+    if (isfinite(r.x) && isfinite(r.y)) {
+      const double inv = vmax > vmin ? 1.0 / (vmax - vmin) : 0.0;
+      const double s0 = fmin(1.0, fmax(0.0, ((double)r.x - vmin) * inv));
+      const double s1 = fmin(1.0, fmax(0.0, ((double)r.y - vmin) * inv));
+      const int64_t i0 = max((int64_t)0, (int64_t)floor(s0 * (double)(M - 1)) - 1);
+      const int64_t i1 = min((int64_t)(M - 1), (int64_t)ceil(s1 * (double)(M - 1)) + 1);
+      c = (nz[i1 + 1] - nz[i0]) == 0 ? 1 : 0;
+    }
+    clear[i] = c;
+    mine += c;
+  }
+  for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+  if ((threadIdx.x & 63) == 0 && mine) atomicAdd(nclear, mine);
+}
+
 }  // namespace
 
 hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s) {
@@ -166,6 +245,28 @@ hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t 
   const int grid = (int)(rows < 65536 ? rows : 65536);
   hipLaunchKernelGGL(k_copy_box, dim3(grid), dim3(256), 0, s, src, sn[0], sn[1], so[0], so[1], so[2], dst, dn[0],
                      dn[1], dn[2]);
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_minmax(const float* vol, const int64_t n[3], int mc, const int64_t c[3], float* out2,
+                            hipStream_t s) {
+  if (mc < 2 || mc > 1024) return hipErrorInvalidValue;
+  const int per = 2048 / mc;
+  const int64_t units = ((c[0] + per - 1) / per) * c[1] * c[2];
+  const int grid = (int)(units < 65536 ? units : 65536);
+  hipLaunchKernelGGL(k_mc_minmax, dim3(grid), dim3(256), 0, s, vol, n[0], n[1], n[2], mc, per, c[0], c[1], c[2],
+                     reinterpret_cast<float2*>(out2));
+  return hipGetLastError();
+}
+
+hipError_t launch_mc_classify(const float* mm2, int64_t count, const int32_t* nz, int M, double vmin, double vmax,
+                              uint8_t* clear, unsigned int* nclear, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(nclear, 0, sizeof(unsigned int), s);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = (count + 255) / 256;
+  const int grid = (int)(blocks < 16384 ? blocks : 16384);
+  hipLaunchKernelGGL(k_mc_classify, dim3(grid), dim3(256), 0, s, reinterpret_cast<const float2*>(mm2), count, nz, M,
+                     vmin, vmax, clear, nclear);
   return hipGetLastError();
 }
 

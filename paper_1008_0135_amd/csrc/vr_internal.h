@@ -134,7 +134,7 @@ struct DevBrick {
   int32_t closed;         // bit i: closed along axis i
   int32_t clo[3], chi[3]; // clamps of the local cell index (global [0, n-2] shifted by -lo)
   float vmin, vmax;       // range of the stored voxels
-  int32_t pad;
+  int32_t slack;          // 1: the storage is followed by >= 64 readable floats (row tails may be over-read)
 };
 
 // Per (view, rendered brick) record, in launch order.
@@ -168,11 +168,14 @@ struct MarchArgs {
   int32_t slab_axis;     // LDS-staged march: slab axis (1 = axis 2, 2 = axis 3); 0 = gather march
   int32_t slab_T;        // cell layers per slab
   int32_t lds_budget;    // floats of LDS for one slab's voxel box
-  int32_t pad;
+  int32_t ring_slot;     // ring march: floats per LDS ring slot (one voxel layer's window)
   const float4* tf;      // [M] RGBA
   const DevBrick* bricks;
   const DevBrickView* bv;
   float4* img;           // image arena (or the output frame)
+  const uint8_t* mc_clear; // per macrocell [m3][m2][m1]: 1 = opacity 0 over its whole range
+  int32_t mc;            // macrocell edge in cells; 0 = no macrocell skipping
+  int32_t mcn[3];        // macrocells per axis
 };
 
 struct CompArgs {
@@ -225,6 +228,10 @@ struct BatchArgs {
 
 // Launchers (defined in the .hip files); all asynchronous on `s`.
 hipError_t launch_march(const MarchArgs& a, hipStream_t s);
+// Ring march (march_ring.hip): 8 x 8 tiles, a.ring_slot floats per window slot,
+// `wpb` wavefronts per workgroup (1, 2 or 4).
+hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s);
+size_t ring_lds_bytes(const MarchArgs& a, int wpb);
 hipError_t launch_march_lds(const MarchArgs& a, hipStream_t s);
 hipError_t launch_composite(const CompArgs& a, hipStream_t s);
 hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s);
@@ -242,5 +249,12 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int blocks, hipStream_t s);
 hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
                            const int64_t dn[3], hipStream_t s);
+// Macrocell (min, max) pairs [c3][c2][c1] of edge `mc` over the volume (mc in [2, 1024]).
+hipError_t launch_mc_minmax(const float* vol, const int64_t n[3], int mc, const int64_t c[3], float* out2,
+                            hipStream_t s);
+// clear[i] = 1 when the table's opacity is 0 over every entry macrocell i can reach
+// (nz: [M + 1] prefix count of entries with opacity != 0); *nclear = number of such cells.
+hipError_t launch_mc_classify(const float* mm2, int64_t count, const int32_t* nz, int M, double vmin, double vmax,
+                              uint8_t* clear, unsigned int* nclear, hipStream_t s);
 
 }  // namespace vr

@@ -241,36 +241,53 @@ def test_c2_full_size_strided_rays(ctx):
     vr.vr_volume_destroy(h)
 
 
-def test_lds_and_gather_marches_identical():
-    """The LDS-staged march and the gather march compute the same samples in the same order."""
-    _say("LDS-staged vs gather march: bit-identical images")
+def _ctx_with_march(mode):
     import os
+    old = os.environ.get("VR_MARCH")
+    os.environ["VR_MARCH"] = mode
+    try:
+        return vr.vr_create(0)
+    finally:
+        if old is None:
+            del os.environ["VR_MARCH"]
+        else:
+            os.environ["VR_MARCH"] = old
+
+
+def test_marches_identical():
+    """The LDS-slab, ring and gather marches compute the same samples in the same order."""
+    _say("slab / ring / gather marches: bit-identical images")
     dims = (160, 144, 176)
     vol = synth.cube(*dims, seed=27, n_sources=15, sigma_range=(2.0, 5.0))
     tf = synth.tf_ramp(256)
     tf[:, 3] = np.minimum(1.0, tf[:, 3] * 6)
     views = synth.random_views(5, 28) + [synth.rot_axis(2, 90.0), synth.rot_axis(2, 87.0) @ synth.rot_axis(1, 3.0)]
     imgs = {}
-    for mode in ("gather", "auto"):
-        old = os.environ.get("VR_MARCH")
-        os.environ["VR_MARCH"] = mode
-        try:
-            c = vr.vr_create(0)
-        finally:
-            if old is None:
-                del os.environ["VR_MARCH"]
-            else:
-                os.environ["VR_MARCH"] = old
+    layouts = {"grid": vr.grid_spec((48, 64, 80)), "mat": vr.grid_spec((48, 64, 80), materialize=True),
+               "kd": vr.kd_spec(7), "whole": None}
+    for mode in ("gather", "slab", "ring"):
+        _say(f"  march {mode}")
+        c = _ctx_with_march(mode)
         h = _upload(c, vol)
-        vr.vr_volume_brick(h, vr.grid_spec((48, 64, 80)))
         vr.vr_tf_set(c, tf)
-        for W in (96, 333):
-            imgs[(mode, W)] = _render(c, h, views, W, W, vr.make_params(tau=0.99))
+        for name, spec in layouts.items():
+            if spec is None:
+                h2 = _upload(c, vol)
+            else:
+                h2 = h
+                vr.vr_volume_brick(h, spec)
+            for W in (96, 333):
+                imgs[(mode, name, W)] = _render(c, h2, views, W, W, vr.make_params(tau=0.99))
+            if spec is None:
+                vr.vr_volume_destroy(h2)
         vr.vr_volume_destroy(h)
         vr.vr_destroy(c)
-    for W in (96, 333):
-        a, b = imgs[("gather", W)], imgs[("auto", W)]
-        assert np.array_equal(a, b), (W, float(np.abs(a - b).max()))
+    for name in layouts:
+        for W in (96, 333):
+            a = imgs[("gather", name, W)]
+            for mode in ("slab", "ring"):
+                b = imgs[(mode, name, W)]
+                assert np.array_equal(a, b), (mode, name, W, float(np.abs(a - b).max()))
     mn, mx = float(vol.min()), float(vol.max())
     ref = oracle.render(vol, tf, views, 96, 96, mn, mx, tau=0.99, bricks={"grid": (48, 64, 80)})
-    parity(imgs[("auto", 96)], ref, label="lds march")
+    parity(imgs[("ring", "grid", 96)], ref, label="ring march")
