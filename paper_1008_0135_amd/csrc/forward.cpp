@@ -20,8 +20,10 @@ size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 
 // Ring march limits: window floats per slot, and wavefronts per compute unit
 // the kernel's registers allow (78 VGPRs: 6 per SIMD).
-constexpr int32_t kRingCap = 3072;
+constexpr int32_t kRingCap = 8192;
 constexpr int32_t kRingMaxWaves = 24;
+constexpr int32_t kRingWantWaves = 12;  // below this the march starts to wait on its loads
+constexpr int32_t kRingMinWaves = 2;
 
 }  // namespace
 
@@ -156,13 +158,10 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     bool lds = false, ring = false;
     int ring_wpb = 4;
     a.lds_budget = budget;
-    if (!extras && mode == 3 && a.mc == 0 && a.tile_w == 8 &&
-        choose_ring(cams[v], kRingCap, a.slab_axis, a.ring_slot)) {
-      int waves = 0;
-      ring_wpb = ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves);
-      ring = waves >= 4;
-    }
-    if (!ring && !extras && (mode == 0 || mode == 2)) {
+    if (!extras && (mode == 0 || mode == 3) && a.mc == 0 && a.tile_w == 8)
+      ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
+                         a.ring_slot, ring_wpb);
+    if (!ring && !extras && mode != 1) {
       lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
       // rays nearly parallel to axis 1 need a wider slab box: retry with twice the budget
       if (!lds && budget < 8192 && choose_slab(cams[v], a.tile_w, a.tile_h, 8192, a.slab_axis, a.slab_T)) {

@@ -53,6 +53,13 @@ __device__ __forceinline__ int wave_imax(int v) {
   return v;
 }
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// a pointer the compiler must treat as uniform (it lives in scalar registers)
+__device__ __forceinline__ gfloat* unip(gfloat* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gfloat*)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ float unif(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
@@ -64,14 +71,16 @@ __device__ __forceinline__ void wait_loads() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// 16 bytes per lane from global memory straight into LDS at lds_base + 16 lane
-// (lds_base is a byte address, uniform over the wavefront).  Written as inline
-// assembly so that the compiler does not guard later LDS reads with waits for
-// these loads: the code waits for them explicitly with wait_loads().
-__device__ __forceinline__ void lds_dma16(gfloat* src, unsigned lds_base) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+// 16 bytes per lane from global memory (base + voff bytes; base uniform, voff
+// per lane) straight into LDS at lds_base + 16 lane (a byte address, uniform
+// over the wavefront).  Written as inline assembly so that the compiler does
+// not guard later LDS reads with waits for these loads: the code waits for
+// them explicitly with wait_loads().  The kernel keeps no value of its own in
+// M0 (it uses no instruction that reads M0 besides this one).
+__device__ __forceinline__ void lds_dma16(gfloat* base, unsigned voff, unsigned lds_base) {
+  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
                :
-               : "v"(src), "s"(lds_base)
+               : "v"(voff), "s"(base), "s"(lds_base)
                : "memory", "m0");
 }
 
@@ -198,7 +207,8 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
   int j = 0;
   bool done = cnt == 0;
 
-  if (pitch > chiF + 2 - cloF || pitch * NG > slot || (int64_t)NG * sG + pitch >= ((int64_t)1 << 31)) {
+  if (pitch > chiF + 2 - cloF || pitch * NG > slot || pitch > 256 ||
+      ((int64_t)(64 / (pitch >> 2)) * sG + pitch) * 4 >= ((int64_t)1 << 32)) {
     // the window does not fit: read the corners from global memory
     while (!done) {
       const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
@@ -223,29 +233,22 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
     return w;
   };
   // chunk (16 bytes) i of a window: row i / (pitch / 4), column 4 (i % (pitch / 4))
+  // A load instruction carries R whole rows (R = 64 / (pitch / 4) lanes per
+  // row group; the remaining lanes idle), so a lane's offset from the group's
+  // first row is fixed for the tile and only the uniform group base moves.
   const int nf4 = pitch >> 2;
-  const int chunks = nf4 * NG;
-  const int nload = (chunks + 63) >> 6;  // load instructions per layer
-  // row r and column chunk c4 of chunk lane + 64 k (offset r sG + 4 c4 floats
-  // from the window origin) advance by (dr, dc) per instruction
-  const int r0 = lane / nf4, c0 = lane - r0 * nf4, off0 = r0 * sG + 4 * c0;
-  const int dr = uni(64 / nf4), dc = uni(64 - dr * nf4);
-  const int doff = uni(dr * sG + 4 * dc), dwrap = uni(sG - 4 * nf4);
+  const int R = uni(64 / nf4);
+  const int rl = lane / nf4, c4l = lane - rl * nf4;
+  const bool lane_on = rl < R;
+  const int nload = uni((NG + R - 1) / R);  // load instructions per layer
+  const unsigned voff = (unsigned)(rl * sG + 4 * c4l) * 4u;
+  const int64_t gstep = (int64_t)R * sG;
+  const unsigned lstep = (unsigned)(R * pitch) * 4u;
   auto issue = [&](int V, const Window& w, float* sdst) {
-    gfloat* lbase = gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0);
-    const unsigned lds0 = uni(lds_addr(sdst));
-    int r = r0, c4 = c0, off = off0;
-    for (int k = 0; k < nload; ++k) {
-      if (r < NG) lds_dma16(lbase + off, lds0 + 1024u * k);
-      c4 += dc;
-      r += dr;
-      off += doff;
-      if (c4 >= nf4) {
-        c4 -= nf4;
-        ++r;
-        off += dwrap;
-      }
-    }
+    gfloat* gb = gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0);
+    const unsigned l0 = uni(lds_addr(sdst));
+    for (int k = 0; k < nload; ++k)
+      if (lane_on && k * R + rl < NG) lds_dma16(unip(gb + k * gstep), voff, l0 + (unsigned)k * lstep);
   };
 
   // voxel layers in marching order: V_k = Lbeg + k (up) or Lbeg + 1 - k (down);
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
       if (ib != c) break;
       const Cell cl = cell_of(q, br);
       const int ig = by ? cl.iz : cl.iy;
-      const float* p = baseL + (ig * pitch + cl.ix);
+      const float* p = baseL + (__mul24(ig, pitch) + cl.ix);
       const float* pu = p + dU;
       // corners v[dz][dy][dx]: within a window rows run along g, layers along b
       const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];

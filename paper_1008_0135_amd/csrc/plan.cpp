@@ -220,34 +220,6 @@ bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int3
   return found;
 }
 
-bool choose_ring(const Camera& cam, int32_t cap, int32_t& axis, int32_t& slot) {
-  const double p = cam.S / (double)cam.W;
-  double best = INFINITY;
-  bool found = false;
-  for (int b = 1; b <= 2; b++) {
-    const int g = 3 - b;
-    const double db = cam.e3[b];
-    if (std::fabs(db) < 1e-3) continue;
-    const double rf = cam.e3[0] / db, rg = cam.e3[g] / db;
-    const double Wf = p * 7.0 * (std::fabs(cam.e1[0] - cam.e1[b] * rf) + std::fabs(cam.e2[0] - cam.e2[b] * rf));
-    const double Wg = p * 7.0 * (std::fabs(cam.e1[g] - cam.e1[b] * rg) + std::fabs(cam.e2[g] - cam.e2[b] * rg));
-    // the kernel's bound is floor(span + 0.2) + 3 per axis; one more for rounding
-    const double nf = std::floor(Wf + 2.0 * std::fabs(rf) + 0.2) + 4.0;
-    const double ng = std::floor(Wg + 2.0 * std::fabs(rg) + 0.2) + 4.0;
-    const double size = 4.0 * std::ceil(nf / 4.0) * ng;
-    if (size > (double)cap) continue;
-    // window floats per sample: one window per layer, 2 / |db| samples per ray and layer
-    const double cost = size * std::fabs(db);
-    if (cost < best) {
-      best = cost;
-      axis = b;
-      slot = (int32_t)size;
-      found = true;
-    }
-  }
-  return found;
-}
-
 int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* waves_per_cu) {
   const int64_t lds = 160 * 1024;
   int best_w = 1, best_waves = -1;
@@ -263,6 +235,41 @@ int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* wa
   }
   if (waves_per_cu) *waves_per_cu = best_waves;
   return best_w;
+}
+
+bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves,
+                 int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb) {
+  const double p = cam.S / (double)cam.W;
+  double best = INFINITY;
+  bool found = false;
+  for (int b = 1; b <= 2; b++) {
+    const int g = 3 - b;
+    const double db = cam.e3[b];
+    if (std::fabs(db) < 1e-3) continue;
+    const double rf = cam.e3[0] / db, rg = cam.e3[g] / db;
+    const double Wf = p * 7.0 * (std::fabs(cam.e1[0] - cam.e1[b] * rf) + std::fabs(cam.e2[0] - cam.e2[b] * rf));
+    const double Wg = p * 7.0 * (std::fabs(cam.e1[g] - cam.e1[b] * rg) + std::fabs(cam.e2[g] - cam.e2[b] * rg));
+    // the kernel's bound is floor(span + 0.2) + 3 per axis; one more for rounding
+    const double nf = std::floor(Wf + 2.0 * std::fabs(rf) + 0.2) + 4.0;
+    const double ng = std::floor(Wg + 2.0 * std::fabs(rg) + 0.2) + 4.0;
+    const double pitch = 4.0 * std::ceil(nf / 4.0);
+    const double size = pitch * ng;
+    if (size > (double)cap || pitch > 256.0) continue;
+    int32_t waves = 0;
+    const int w = ring_waves_per_block((int32_t)size, M, max_waves, &waves);
+    if (waves < min_waves) continue;
+    // window floats per sample (one window per layer, 2 / |db| samples per ray
+    // and layer), weighted by the occupancy shortfall
+    const double cost = size * std::fabs(db) * std::max(1.0, (double)want_waves / (double)waves);
+    if (cost < best) {
+      best = cost;
+      axis = b;
+      slot = (int32_t)size;
+      wpb = w;
+      found = true;
+    }
+  }
+  return found;
 }
 
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step) {

@@ -70,17 +70,20 @@ bool brick_transparent(float bmin, float bmax, const float* tf_rgba, int32_t M, 
 // voxels): the gather march is used then.
 bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int32_t& axis, int32_t& T);
 
-// Ring march for one view (8 x 8 tiles): the slab axis (as above) whose
-// per-layer window -- the box of voxels that the samples of one tile between
-// two planes b = V - 1 and b = V + 1 can touch, with its row length rounded up
-// to whole 16-byte chunks -- loads the fewest voxels per sample, among the
-// axes whose window bound fits `cap` floats.  *slot receives that bound.
-bool choose_ring(const Camera& cam, int32_t cap, int32_t& axis, int32_t& slot);
-
 // Wavefronts per workgroup (1, 2 or 4) for a ring launch: the choice that fits
 // the most wavefronts per compute unit into 160 KB of LDS (M-entry table per
 // workgroup, three slots per wavefront), at most `max_waves` per unit.
 int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* waves_per_cu);
+
+// Ring march for one view (8 x 8 tiles).  For each slab axis (as above) the
+// per-layer window bound -- the box of voxels that the samples of one tile
+// between the planes b = V - 1 and b = V + 1 can touch, rows rounded up to
+// whole 16-byte chunks -- and the wavefronts per compute unit that its LDS
+// slots allow; picks the axis with the fewest window voxels per sample,
+// weighted by how far occupancy falls below `want_waves`.  Needs a bound of
+// at most `cap` floats and at least `min_waves` wavefronts per unit.
+bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves,
+                 int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb);
 
 // Sum over pixels of the whole-volume lattice count (no ERT, no skipping).
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step);

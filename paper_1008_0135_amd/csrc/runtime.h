@@ -83,8 +83,9 @@ struct vr_ctx {
   std::vector<Timed> timed;
   std::vector<hipEvent_t> event_pool;
   hipStream_t prof_stream = nullptr;
-  // march selection: 0 = automatic (LDS-staged slabs when a slab fits, else gather);
-  // 1 = gather only; 2 = LDS-staged slabs (else gather); 3 = per-layer ring (else as 0)
+  // march selection: 0 = automatic (per-layer ring when its windows fit, else
+  // LDS-staged slabs when a slab fits, else gather); 1 = gather only;
+  // 2 = LDS-staged slabs (else gather); 3 = same as 0
   int32_t march_mode = 0;
   int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)

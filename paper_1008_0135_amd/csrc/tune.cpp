@@ -124,8 +124,9 @@ int vr_autotune(vr_ctx* ctx, const vr_volume* cvol, const vr_view* view, const v
   struct Cand {
     int32_t tile, budget, mode;
   };
-  std::vector<Cand> cands = {{8, 4096, 0}, {8, 2048, 0}, {8, 6144, 0}, {8, 8192, 0}, {4, 4096, 0},
-                             {16, 4096, 0}, {8, 0, 1}, {4, 0, 1}, {16, 0, 1}};
+  // default (ring, else slabs), slab-only budgets, slab tiles, gathers
+  std::vector<Cand> cands = {{8, 4096, 0}, {8, 4096, 2}, {8, 2048, 2}, {8, 6144, 2}, {8, 8192, 2},
+                             {4, 4096, 2}, {16, 4096, 2}, {8, 0, 1}, {4, 0, 1}, {16, 0, 1}};
   double best = INFINITY, dflt = INFINITY;
   Cand pick = cands[0];
   int rc = VR_OK;
