@@ -158,7 +158,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     bool lds = false, ring = false;
     int ring_wpb = 4;
     a.lds_budget = budget;
-    if (!extras && (mode == 0 || mode == 3) && a.mc == 0 && a.tile_w == 8)
+    if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8)
       ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
                          a.ring_slot, ring_wpb);
     if (!ring && !extras && mode != 1) {

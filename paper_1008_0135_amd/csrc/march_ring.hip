@@ -94,6 +94,7 @@ struct Window {
   int f0, g0;
 };
 
+template <bool ESS>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
@@ -256,50 +257,146 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
   const int nlay = up ? Lend - Lbeg + 1 : Lbeg - Lend + 1;  // cell layers
   const int vstep = up ? 1 : -1;
   const int V0 = up ? Lbeg : Lbeg + 1;
-  Window w0 = window(V0), w1 = window(V0 + vstep);
-  issue(V0, w0, s_ring);
-  issue(V0 + vstep, w1, s_ring + slot);
-  int s0 = 0;  // slot of V_k
-  const float fclo = (float)cloB, fchi = (float)chiB;
-  for (int k = 0; k < nlay; ++k) {
-    wait_loads();  // V_k and V_{k+1} are in LDS
-    // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished)
-    const int s1 = s0 == kSlots - 1 ? 0 : s0 + 1;
-    const int s2 = s1 == kSlots - 1 ? 0 : s1 + 1;
-    Window w2;
-    if (k + 1 < nlay) {
-      const int V2 = V0 + (k + 2) * vstep;
-      w2 = window(V2);
-      issue(V2, w2, s_ring + s2 * slot);
+  if constexpr (!ESS) {
+    const float fclo = (float)cloB, fchi = (float)chiB;
+    Window w0 = window(V0), w1 = window(V0 + vstep);
+    issue(V0, w0, s_ring);
+    issue(V0 + vstep, w1, s_ring + slot);
+    int s0 = 0;  // slot of V_k
+    for (int k = 0; k < nlay; ++k) {
+      wait_loads();  // V_k and V_{k+1} are in LDS
+      // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished)
+      const int s1 = s0 == kSlots - 1 ? 0 : s0 + 1;
+      const int s2 = s1 == kSlots - 1 ? 0 : s1 + 1;
+      Window w2;
+      if (k + 1 < nlay) {
+        const int V2 = V0 + (k + 2) * vstep;
+        w2 = window(V2);
+        issue(V2, w2, s_ring + s2 * slot);
+      }
+      // lower and upper voxel layer of cell layer c_k
+      const int c = up ? Lbeg + k : Lbeg - k;
+      const Window& wl = up ? w0 : w1;
+      const Window& wu = up ? w1 : w0;
+      const int sl = up ? s0 : s1, su = up ? s1 : s0;
+      const float* baseL = s_ring + (sl * slot - wl.g0 * pitch - wl.f0);
+      const int dU = (su * slot - wu.g0 * pitch - wu.f0) - (sl * slot - wl.g0 * pitch - wl.f0);
+      while (!done) {
+        const SamplePos q = sample_pos(j, px, py, pz, sx, sy, sz);
+        const int ib = (int)floorf(__builtin_amdgcn_fmed3f(by ? q.y : q.z, fclo, fchi));
+        if (ib != c) break;
+        const Cell cl = cell_of(q, br);
+        const int ig = by ? cl.iz : cl.iy;
+        const float* p = baseL + (__mul24(ig, pitch) + cl.ix);
+        const float* pu = p + dU;
+        // corners v[dz][dy][dx]: within a window rows run along g, layers along b
+        const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];
+        const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
+        const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
+                             : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
+        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        ++j;
+        if (j >= cnt || 1.f - T >= a.tau) done = true;
+      }
+      if (__all(done)) break;
+      s0 = s1;
+      w0 = w1;
+      w1 = w2;
     }
-    // lower and upper voxel layer of cell layer c_k
-    const int c = up ? Lbeg + k : Lbeg - k;
-    const Window& wl = up ? w0 : w1;
-    const Window& wu = up ? w1 : w0;
-    const int sl = up ? s0 : s1, su = up ? s1 : s0;
-    const float* baseL = s_ring + (sl * slot - wl.g0 * pitch - wl.f0);
-    const int dU = (su * slot - wu.g0 * pitch - wu.f0) - (sl * slot - wl.g0 * pitch - wl.f0);
-    while (!done) {
-      const SamplePos q = sample_pos(j, px, py, pz, sx, sy, sz);
-      const int ib = (int)floorf(__builtin_amdgcn_fmed3f(by ? q.y : q.z, fclo, fchi));
-      if (ib != c) break;
-      const Cell cl = cell_of(q, br);
-      const int ig = by ? cl.iz : cl.iy;
-      const float* p = baseL + (__mul24(ig, pitch) + cl.ix);
-      const float* pu = p + dU;
-      // corners v[dz][dy][dx]: within a window rows run along g, layers along b
-      const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];
-      const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
-      const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
-                           : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
-      accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
-      ++j;
-      if (j >= cnt || 1.f - T >= a.tau) done = true;
+  } else {
+    const float fclo = (float)cloB, fchi = (float)chiB;
+    const int loB = by ? br.lo[1] : br.lo[2], loG = by ? br.lo[2] : br.lo[1];
+    // Empty-space skipping: cell layers are taken in steps that end at macrocell
+    // boundaries along b; a step whose cells all lie in macrocells with zero
+    // opacity over their range is neither loaded nor sampled (its samples would
+    // add nothing and leave T as it is), the lanes only move their cursors.
+    auto step_clear = [&](int c, int c_end) {
+      const int P0 = min(c, c_end), P1 = max(c, c_end) + 1;  // planes bounding the step
+      const float lo_f = fminf((float)P0 * rf, (float)P1 * rf), hi_f = fmaxf((float)P0 * rf, (float)P1 * rf);
+      const float lo_g = fminf((float)P0 * rg, (float)P1 * rg), hi_g = fmaxf((float)P0 * rg, (float)P1 * rg);
+      const int f0 = max((int)floorf(Af_lo + lo_f - 0.05f), cloF), f1 = min((int)floorf(Af_hi + hi_f + 0.05f), chiF);
+      const int g0 = max((int)floorf(Ag_lo + lo_g - 0.05f), cloG), g1 = min((int)floorf(Ag_hi + hi_g + 0.05f), chiG);
+      const int mc = a.mc;
+      const int mf0 = (f0 + br.lo[0]) / mc, mf1 = (max(f1, f0) + br.lo[0]) / mc;
+      const int mg0 = (g0 + loG) / mc, mg1 = (max(g1, g0) + loG) / mc;
+      const int mb = (c + loB) / mc;
+      const int nmf = mf1 - mf0 + 1, tot = nmf * (mg1 - mg0 + 1);
+      bool opaque = false;
+#pragma nounroll
+      for (int i = lane; i < tot; i += 64) {
+        const int mf = mf0 + i % nmf, mg = mg0 + i / nmf;
+        const int my = by ? mb : mg, mz = by ? mg : mb;
+        opaque |= a.mc_clear[((int64_t)mz * a.mcn[1] + my) * a.mcn[0] + mf] == 0;
+      }
+      return !__any(opaque);
+    };
+
+    // voxel layer V_i lives in slot i % 3; `issued` counts the layers started
+    auto start = [&](int i) {
+      const int V = V0 + i * vstep;
+      issue(V, window(V), s_ring + (i % kSlots) * slot);
+    };
+    int issued = 0;
+    int next_check = 0;  // first layer of the next skipping step
+    int k = 0;
+    while (k < nlay) {
+      const int c = up ? Lbeg + k : Lbeg - k;
+      if (ESS && k >= next_check) {
+        const int mb = (c + loB) / a.mc;
+        const int c_end = up ? min(Lend, (mb + 1) * a.mc - 1 - loB) : max(Lend, mb * a.mc - loB);
+        const int k_end = up ? c_end - Lbeg : Lbeg - c_end;
+        if (step_clear(c, c_end)) {
+#pragma nounroll
+          while (!done) {
+            const int ib = (int)floorf(__builtin_amdgcn_fmed3f(fmaf((float)j, sb, pb), fclo, fchi));
+            if (up ? ib > c_end : ib < c_end) break;
+            ++j;
+            if (j >= cnt) done = true;
+          }
+          k = k_end + 1;
+          next_check = k;
+          if (__all(done)) break;
+          continue;
+        }
+        next_check = k_end + 1;
+        if (issued < k) {  // after a skipped step: restart the ring at V_k
+          wait_loads();    // loads started before the step may still be landing
+          issued = k;
+        }
+      }
+#pragma nounroll
+      while (issued <= k + 1) start(issued++);
+      wait_loads();  // V_k and V_{k+1} are in LDS
+      // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished)
+      if (k + 2 <= nlay) start(issued++);
+      // lower and upper voxel layer of cell layer c_k
+      const Window w0 = window(V0 + k * vstep), w1 = window(V0 + (k + 1) * vstep);
+      const int s0 = k % kSlots, s1 = (k + 1) % kSlots;
+      const Window& wl = up ? w0 : w1;
+      const Window& wu = up ? w1 : w0;
+      const int sl = up ? s0 : s1, su = up ? s1 : s0;
+      const float* baseL = s_ring + (sl * slot - wl.g0 * pitch - wl.f0);
+      const int dU = (su * slot - wu.g0 * pitch - wu.f0) - (sl * slot - wl.g0 * pitch - wl.f0);
+      while (!done) {
+        const SamplePos q = sample_pos(j, px, py, pz, sx, sy, sz);
+        const int ib = (int)floorf(__builtin_amdgcn_fmed3f(by ? q.y : q.z, fclo, fchi));
+        if (ib != c) break;
+        const Cell cl = cell_of(q, br);
+        const int ig = by ? cl.iz : cl.iy;
+        const float* p = baseL + (__mul24(ig, pitch) + cl.ix);
+        const float* pu = p + dU;
+        // corners v[dz][dy][dx]: within a window rows run along g, layers along b
+        const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];
+        const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
+        const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
+                             : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
+        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        ++j;
+        if (j >= cnt || 1.f - T >= a.tau) done = true;
+      }
+      if (__all(done)) break;
+      ++k;
     }
-    if (__all(done)) break;
-    s0 = s1;
-    w0 = w1;
-    w1 = w2;
   }
   wait_loads();  // no load may still target LDS when the wavefront ends
   if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
@@ -317,7 +414,10 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
     return hipErrorInvalidValue;
   const int groups = (a.ntiles + wpb - 1) / wpb;
   const int grid = ((groups + 7) / 8) * 8;
-  hipLaunchKernelGGL(k_march_ring, dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a);
+  // macrocell skipping lives in its own instantiation: its bookkeeping costs
+  // registers the plain march does not need
+  if (a.mc > 0) hipLaunchKernelGGL(k_march_ring<true>, dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a);
+  else hipLaunchKernelGGL(k_march_ring<false>, dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a);
   return hipGetLastError();
 }
 

@@ -6,7 +6,8 @@
 * rendering with skipping on is bit-identical to skipping off, for tables
   whose zero-opacity entries sit at the bottom, in the middle or nowhere,
   across table changes (re-classification), grid and longest-axis bricks,
-  virtual and materialised storage, with and without early termination;
+  virtual and materialised storage, with and without early termination, in
+  the default (ring) march and in the LDS-slab march;
 * parity of a skipped render with the FP64 oracle.
 """
 import numpy as np
@@ -104,10 +105,25 @@ def _render(ctx, h, views, W, H, params):
     return out.cpu().numpy()
 
 
-@pytest.mark.parametrize("spec_name", ["grid", "grid_mat", "kd"])
-def test_skip_bit_identical(ctx, spec_name):
+def _ctx_with_march(mode):
+    import os
+    old = os.environ.get("VR_MARCH")
+    os.environ["VR_MARCH"] = mode
+    try:
+        return vr.vr_create(0)
+    finally:
+        if old is None:
+            del os.environ["VR_MARCH"]
+        else:
+            os.environ["VR_MARCH"] = old
+
+
+@pytest.mark.parametrize("spec_name,march", [("grid", "auto"), ("grid_mat", "auto"), ("kd", "auto"),
+                                             ("grid", "slab"), ("kd", "slab")])
+def test_skip_bit_identical(ctx, spec_name, march):
     n1, n2, n3 = 150, 120, 170
-    _say(f"skip on/off bit identity {n1}x{n2}x{n3} {spec_name}")
+    _say(f"skip on/off bit identity {n1}x{n2}x{n3} {spec_name} march {march}")
+    ctx = _ctx_with_march(march)
     vol = synth.cube(n1, n2, n3, seed=83, n_sources=10, sigma_range=(2.0, 4.0))
     h = vr.vr_volume_create(ctx, vol, (n1, n2, n3))
     spec = {"grid": vr.grid_spec((64, 64, 64), macrocell=8),
@@ -123,6 +139,7 @@ def test_skip_bit_identical(ctx, spec_name):
             off = _render(ctx, h, views, 160, 136, vr.make_params(tau=tau, ess=0))
             assert np.array_equal(on, off), (spec_name, name, tau, float(np.abs(on - off).max()))
     vr.vr_volume_destroy(h)
+    vr.vr_destroy(ctx)
 
 
 def test_skip_parity_with_oracle(ctx):
