@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "forward.h"
+#include "plan.h"
 #include "runtime.h"
 #include "vr_internal.h"
 
@@ -19,7 +20,17 @@ struct vr_state {
   vr_params p;
   double vmin = 0.0, vmax = 0.0;
   int32_t W = 0, H = 0, nviews = 0, K = 32, nseg = 0;
-  float* d_ckpt = nullptr;     // [view][segment][pixel]
+  // per view: checkpoint layout.  Ring views keep, per group of L cell layers
+  // of each 8 x 8 tile, T and the sample cursor at the group's start; the
+  // others keep T before every K-th sample.
+  struct View {
+    bool ring = false;
+    int32_t axis = 0, slot = 0, fwd_wpb = 4, bwd_wpb = 1, L = 0, smax = 0, ngrp = 0;
+    int64_t off = 0;  // offset of this view's checkpoints (floats / ints) in d_ckpt / d_ckpt_j
+  };
+  std::vector<View> vs;
+  float* d_ckpt = nullptr;     // checkpoints, all views
+  int32_t* d_ckpt_j = nullptr; // ring views: sample cursors at group starts
   int32_t* d_nused = nullptr;  // [view][pixel]
 };
 
@@ -55,6 +66,45 @@ void pack_whole(const vr_volume* vol, int32_t W, int32_t H, int32_t tw, int32_t 
 
 int ntiles_of(int32_t W, int32_t H, int32_t tw, int32_t th) { return ((W + tw - 1) / tw) * ((H + th - 1) / th); }
 
+// Ring layout for the differentiable pair of one view: slab axis, window slot,
+// forward launch shape, cell layers per checkpoint group (about K samples),
+// and the adjoint's wavefronts per workgroup under 160 KB of LDS.  False when
+// the view needs the sample-segment kernels.
+bool plan_ring_view(const Camera& cam, const vr_params* p, int32_t M, const int64_t n[3], vr_state::View& rv) {
+  if (p->tile != 0 && p->tile != 8) return false;
+  int32_t axis = 0, slot = 0, wpb = 4;
+  if (!choose_ring(cam, 4096, M, 24, 12, 2, axis, slot, wpb)) return false;
+  const double db = std::fabs(cam.e3[axis]);
+  const int Lmax = std::max(1, std::min(16, (int)std::lround((double)p->ckpt_K * p->step * db)));
+  for (int L = Lmax; L >= 1; L = L > 1 ? L / 2 : 0) {
+    const int smax = (int)std::floor((double)L / (p->step * db)) + 3;
+    const double per_wave = 4.0 * (2.0 * (L + 1) * slot + 64.0 + 64.0 * smax);
+    const double fixed = 48.0 * M;  // table (float4) and table gradients (double x 4)
+    int best_w = 0, best_waves = 0;
+    for (int w : {4, 2, 1}) {
+      const double lds = fixed + w * per_wave;
+      if (lds > 160.0 * 1024.0) continue;
+      int blocks = (int)std::floor(160.0 * 1024.0 / lds);
+      blocks = std::min(blocks, 16 / w);  // 99 VGPRs: 4 wavefronts per SIMD
+      if (blocks * w > best_waves) {
+        best_waves = blocks * w;
+        best_w = w;
+      }
+    }
+    if (best_w == 0) continue;
+    rv.ring = true;
+    rv.axis = axis;
+    rv.slot = slot;
+    rv.fwd_wpb = wpb;
+    rv.bwd_wpb = best_w;
+    rv.L = L;
+    rv.smax = smax;
+    rv.ngrp = (int32_t)((n[axis] - 1 + L - 1) / L) + 1;
+    return true;
+  }
+  return false;
+}
+
 }  // namespace
 
 int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p,
@@ -84,8 +134,26 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
   const int64_t nmax = (int64_t)std::ceil(std::sqrt(diag) / p->step) + 2;
   st->nseg = (int32_t)((nmax + st->K - 1) / st->K);
   const int64_t npix = (int64_t)W * H;
-  const size_t ck_bytes = sizeof(float) * (size_t)nviews * (size_t)st->nseg * (size_t)npix;
-  if (hipMalloc(&st->d_ckpt, ck_bytes) != hipSuccess || hipMalloc(&st->d_nused, sizeof(int32_t) * nviews * npix) != hipSuccess) {
+  // per-view layout and checkpoint offsets
+  std::vector<Camera> cams((size_t)nviews);
+  st->vs.assign((size_t)nviews, vr_state::View());
+  int64_t ck_total = 0, ckj_total = 0;
+  for (int32_t v = 0; v < nviews; v++) {
+    make_camera(views[v], vol->n, cams[v]);
+    vr_state::View& rv = st->vs[v];
+    if (ctx->march_mode != 1 && plan_ring_view(cams[v], p, ctx->tf_m, vol->n, rv)) {
+      rv.off = ck_total;
+      ck_total += (int64_t)rv.ngrp * npix;
+      ckj_total += (int64_t)rv.ngrp * npix;
+    } else {
+      rv.off = ck_total;
+      ck_total += (int64_t)st->nseg * npix;
+    }
+  }
+  const size_t ck_bytes = sizeof(float) * (size_t)ck_total;
+  if (hipMalloc(&st->d_ckpt, ck_bytes) != hipSuccess ||
+      hipMalloc(&st->d_nused, sizeof(int32_t) * nviews * npix) != hipSuccess ||
+      (ckj_total > 0 && hipMalloc(&st->d_ckpt_j, sizeof(int32_t) * (size_t)ck_total) != hipSuccess)) {
     (void)hipGetLastError();
     vr_state_destroy(st);
     return fail(VR_ENOMEM, "hipMalloc for %zu bytes of checkpoints failed", ck_bytes);
@@ -99,21 +167,31 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
   void* dtab = nullptr;
   int rc = upload_tables(ctx, s, host.data(), host.size(), &dtab);
   for (int32_t v = 0; v < nviews && rc == VR_OK; v++) {
+    const vr_state::View& rv = st->vs[v];
     MarchArgs a = base;
-    make_camera(views[v], vol->n, a.cam);
+    a.cam = cams[v];
     a.nbv = 1;
     a.ntiles = ntiles_of(W, H, a.tile_w, a.tile_h);
     a.bricks = reinterpret_cast<const DevBrick*>(dtab);
     a.bv = reinterpret_cast<const DevBrickView*>(reinterpret_cast<unsigned char*>(dtab) + off_bv[v]);
     a.img = reinterpret_cast<float4*>(out);
     SaveArgs sa;
-    sa.ckpt = st->d_ckpt + (int64_t)v * st->nseg * npix;
+    std::memset(&sa, 0, sizeof sa);
+    sa.ckpt = st->d_ckpt + rv.off;
+    sa.ckpt_j = rv.ring ? st->d_ckpt_j + rv.off : nullptr;
     sa.nused = st->d_nused + (int64_t)v * npix;
-    sa.K = st->K;
+    sa.K = rv.ring ? rv.L : st->K;
     sa.npix = (int32_t)npix;
     rc = stage_begin(ctx, VR_STAGE_MARCH, s);
     if (rc == VR_OK) {
-      hipError_t e = launch_fwd_save(a, sa, s);
+      hipError_t e;
+      if (rv.ring) {
+        a.slab_axis = rv.axis;
+        a.ring_slot = rv.slot;
+        e = launch_march_ring_save(a, sa, rv.fwd_wpb, s);
+      } else {
+        e = launch_fwd_save(a, sa, s);
+      }
       if (e != hipSuccess) rc = fail(VR_EHIP, "forward launch: %s", hipGetErrorString(e));
     }
     if (rc == VR_OK) rc = stage_end(ctx, s);
@@ -138,6 +216,7 @@ int vr_state_destroy(vr_state* st) {
   DeviceGuard g(st->ctx->device);
   (void)hipDeviceSynchronize();
   if (st->d_ckpt) (void)hipFree(st->d_ckpt);
+  if (st->d_ckpt_j) (void)hipFree(st->d_ckpt_j);
   if (st->d_nused) (void)hipFree(st->d_nused);
   delete st;
   return VR_OK;
@@ -172,10 +251,13 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
   VR_TRY(upload_tables(ctx, s, host.data(), host.size(), &dtab));
   MarchArgs a0 = base;
   a0.ntiles = ntiles_of(W, H, base.tile_w, base.tile_h);
-  const int nblocks = bwd_blocks(a0);
-  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes, sizeof(double) * 4 * (size_t)M * (size_t)std::max(nblocks, 1)));
+  int nblocks_max = std::max(bwd_blocks(a0), 1);
+  for (const auto& rv : st->vs)
+    if (rv.ring) nblocks_max = std::max(nblocks_max, bwd_ring_blocks(a0, rv.bwd_wpb));
+  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes, sizeof(double) * 4 * (size_t)M * (size_t)nblocks_max));
   double* part = reinterpret_cast<double*>(ctx->d_scratch);
   for (int32_t v = 0; v < st->nviews; v++) {
+    const vr_state::View& rv = st->vs[v];
     MarchArgs a = base;
     make_camera(st->views[v], vol->n, a.cam);
     a.nbv = 1;
@@ -183,17 +265,29 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
     a.bricks = reinterpret_cast<const DevBrick*>(dtab);
     a.bv = reinterpret_cast<const DevBrickView*>(reinterpret_cast<unsigned char*>(dtab) + off_bv[v]);
     BwdArgs ba;
-    ba.ckpt = st->d_ckpt + (int64_t)v * st->nseg * npix;
+    std::memset(&ba, 0, sizeof ba);
+    ba.ckpt = st->d_ckpt + rv.off;
+    ba.ckpt_j = rv.ring ? st->d_ckpt_j + rv.off : nullptr;
     ba.nused = st->d_nused + (int64_t)v * npix;
     ba.gout = reinterpret_cast<const float4*>(grad_out) + (int64_t)v * npix;
     ba.gvol = grad_vol;
     ba.tf_part = part;
     ba.vmin = st->vmin;
     ba.inv_range = st->vmax > st->vmin ? 1.0 / (st->vmax - st->vmin) : 0.0;
-    ba.K = st->K;
+    ba.K = rv.ring ? rv.L : st->K;
     ba.npix = (int32_t)npix;
+    ba.smax = rv.smax;
     VR_TRY(stage_begin(ctx, VR_STAGE_BACKWARD, s));
-    VR_HIP(launch_bwd(a, ba, s));
+    int nblocks;
+    if (rv.ring) {
+      a.slab_axis = rv.axis;
+      a.ring_slot = rv.slot;
+      VR_HIP(launch_bwd_ring(a, ba, rv.bwd_wpb, s));
+      nblocks = bwd_ring_blocks(a, rv.bwd_wpb);
+    } else {
+      VR_HIP(launch_bwd(a, ba, s));
+      nblocks = bwd_blocks(a0);
+    }
     VR_HIP(launch_tf_reduce(part, nblocks, M * 4, grad_tf, s));
     VR_TRY(stage_end(ctx, s));
   }

@@ -25,6 +25,9 @@
 // the current layer (two to three on typical views).  Four wavefronts share a
 // workgroup only to share the transfer-function table in LDS; after loading it
 // each wavefront runs on its own, with no workgroup barrier.
+#include <cstring>
+
+#include "ring_common.h"
 #include "sample.h"
 #include "vr_internal.h"
 
@@ -32,70 +35,15 @@ namespace vr {
 
 namespace {
 
-typedef const float __attribute__((address_space(1))) gfloat;
+using namespace ring;
 
 constexpr int kSlots = 3;
 
-__device__ __forceinline__ float wmin4(float v) {
-  v = fminf(v, __shfl_xor(v, 1));
-  return fminf(v, __shfl_xor(v, 2));
-}
-__device__ __forceinline__ float wmax4(float v) {
-  v = fmaxf(v, __shfl_xor(v, 1));
-  return fmaxf(v, __shfl_xor(v, 2));
-}
-__device__ __forceinline__ int wave_imin(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
-  return v;
-}
-__device__ __forceinline__ int wave_imax(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
-}
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-// a pointer the compiler must treat as uniform (it lives in scalar registers)
-__device__ __forceinline__ gfloat* unip(gfloat* p) {
-  const uint64_t v = (uint64_t)p;
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-  return (gfloat*)(((uint64_t)hi << 32) | lo);
-}
-__device__ __forceinline__ float unif(float v) {
-  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
-// Wait until every global->LDS load this wavefront issued has landed (the
-// memory clobber keeps LDS reads from moving above the wait).
-__device__ __forceinline__ void wait_loads() {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// 16 bytes per lane from global memory (base + voff bytes; base uniform, voff
-// per lane) straight into LDS at lds_base + 16 lane (a byte address, uniform
-// over the wavefront).  Written as inline assembly so that the compiler does
-// not guard later LDS reads with waits for these loads: the code waits for
-// them explicitly with wait_loads().  The kernel keeps no value of its own in
-// M0 (it uses no instruction that reads M0 besides this one).
-__device__ __forceinline__ void lds_dma16(gfloat* base, unsigned voff, unsigned lds_base) {
-  asm volatile("s_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, %1"
-               :
-               : "v"(voff), "s"(base), "s"(lds_base)
-               : "memory", "m0");
-}
-
-__device__ __forceinline__ unsigned lds_addr(const float* p) {
-  return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float*)p;
-}
-
-// Window of one voxel layer: rows along axis 1 (f), `pitch` floats each, NG rows
-// along the in-plane axis g; origin (f0, g0) in brick-local voxel indices.
-struct Window {
-  int f0, g0;
-};
-
-template <bool ESS>
-__global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
+// SAVE (differentiable forward, whole volume): also store, for every group of
+// sa.K cell layers of the tile (in marching order), each ray's transmittance
+// and sample cursor at the group's start, and the samples applied per ray.
+template <bool ESS, bool SAVE>
+__global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
   for (int i = threadIdx.x; i < a.M; i += blockDim.x) s_tf[i] = a.tf[i];
@@ -172,10 +120,21 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
     Lend = uni(wave_imin(c_last));
   }
   float4* dst = a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
+  const int pix = ly * bvw.w + lx;  // SAVE: pixel of the whole-volume image
   if (up ? Lbeg > Lend : Lbeg < Lend) {
     if (valid) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (SAVE && valid) sa.nused[pix] = 0;
     return;
   }
+  const int nlay = up ? Lend - Lbeg + 1 : Lbeg - Lend + 1;  // cell layers
+  // SAVE: state of the ray at the start of group g (cell layers gK .. gK + K - 1)
+  auto save_group = [&](int g, float Tg, int jg) {
+    if (valid) {
+      sa.ckpt[(int64_t)g * sa.npix + pix] = Tg;
+      sa.ckpt_j[(int64_t)g * sa.npix + pix] = jg;
+    }
+  };
+  const int ngrp_tile = SAVE ? (nlay + sa.K - 1) / sa.K : 0;
 
   // ---- window geometry from the tile's corner rays (lanes 0..3)
   // A corner ray meets the plane b = P at f = Af + P rf, g = Ag + P rg.
@@ -211,13 +170,23 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
   if (pitch > chiF + 2 - cloF || pitch * NG > slot || pitch > 256 ||
       ((int64_t)(64 / (pitch >> 2)) * sG + pitch) * 4 >= ((int64_t)1 << 32)) {
     // the window does not fit: read the corners from global memory
+    int gnext = 0;  // SAVE: next group whose start state is to be stored
     while (!done) {
       const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
+      if (SAVE) {
+        const int ib = by ? c.iy : c.iz;
+        const int gi = (up ? ib - Lbeg : Lbeg - ib) / sa.K;
+        while (gnext <= gi) save_group(gnext++, T, j);
+      }
       gfloat* p = gbase + (c.iz * zsl + c.iy * ysl + c.ix);
       const float val = trilerp(p[0], p[1], p[ysl], p[ysl + 1], p[zsl], p[zsl + 1], p[zsl + ysl], p[zsl + ysl + 1], c);
       accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
       ++j;
       if (j >= cnt || 1.f - T >= a.tau) done = true;
+    }
+    if (SAVE) {
+      while (gnext < ngrp_tile) save_group(gnext++, T, j);
+      if (valid) sa.nused[pix] = j;
     }
     if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
     return;
@@ -254,7 +223,6 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
 
   // voxel layers in marching order: V_k = Lbeg + k (up) or Lbeg + 1 - k (down);
   // cell layer c_k = Lbeg +- k reads V_k and V_{k+1}
-  const int nlay = up ? Lend - Lbeg + 1 : Lbeg - Lend + 1;  // cell layers
   const int vstep = up ? 1 : -1;
   const int V0 = up ? Lbeg : Lbeg + 1;
   if constexpr (!ESS) {
@@ -264,6 +232,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
     issue(V0 + vstep, w1, s_ring + slot);
     int s0 = 0;  // slot of V_k
     for (int k = 0; k < nlay; ++k) {
+      if (SAVE && k % sa.K == 0) save_group(k / sa.K, T, j);
       wait_loads();  // V_k and V_{k+1} are in LDS
       // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished)
       const int s1 = s0 == kSlots - 1 ? 0 : s0 + 1;
@@ -298,7 +267,11 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
         ++j;
         if (j >= cnt || 1.f - T >= a.tau) done = true;
       }
-      if (__all(done)) break;
+      if (__all(done)) {
+        if (SAVE)
+          for (int g = k / sa.K + 1; g < ngrp_tile; ++g) save_group(g, T, j);
+        break;
+      }
       s0 = s1;
       w0 = w1;
       w1 = w2;
@@ -399,6 +372,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a) {
     }
   }
   wait_loads();  // no load may still target LDS when the wavefront ends
+  if (SAVE && valid) sa.nused[pix] = j;
   if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
 }
 
@@ -416,8 +390,21 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   const int grid = ((groups + 7) / 8) * 8;
   // macrocell skipping lives in its own instantiation: its bookkeeping costs
   // registers the plain march does not need
-  if (a.mc > 0) hipLaunchKernelGGL(k_march_ring<true>, dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a);
-  else hipLaunchKernelGGL(k_march_ring<false>, dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a);
+  SaveArgs none;
+  std::memset(&none, 0, sizeof none);
+  if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  else hipLaunchKernelGGL((k_march_ring<false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  return hipGetLastError();
+}
+
+hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wpb, hipStream_t s) {
+  if (a.ntiles <= 0) return hipSuccess;
+  if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4) ||
+      a.mc != 0 || sa.K < 1 || !sa.ckpt_j)
+    return hipErrorInvalidValue;
+  const int groups = (a.ntiles + wpb - 1) / wpb;
+  const int grid = ((groups + 7) / 8) * 8;
+  hipLaunchKernelGGL((k_march_ring<false, true>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, sa);
   return hipGetLastError();
 }
 

@@ -188,21 +188,26 @@ struct CompArgs {
 
 // Differentiable path (whole volume).  Checkpoints are stored [segment][pixel].
 struct SaveArgs {
-  float* ckpt;        // T before samples 0, K, 2K, ... of each ray
+  float* ckpt;        // sample segments: T before samples 0, K, 2K, ... [segment][pixel];
+                      // layer groups: T at the start of each group [group][pixel]
+  int32_t* ckpt_j;    // layer groups: sample cursor at the start of each group [group][pixel]
   int32_t* nused;     // samples applied per ray (early termination included)
-  int32_t K;
+  int32_t K;          // samples per segment, or cell layers per group
   int32_t npix;       // W * H
 };
 
 struct BwdArgs {
   const float* ckpt;
+  const int32_t* ckpt_j;  // layer groups: sample cursor at each group start (null for sample segments)
   const int32_t* nused;
   const float4* gout; // dL/d(image) of this view, [H][W]
   float* gvol;        // dL/d(voxels), [n3][n2][n1], or null
   double* tf_part;    // per-workgroup table gradients, [blocks][M][4]
   double vmin, inv_range;  // normalisation window in double precision
-  int32_t K;
+  int32_t K;          // samples per segment, or cell layers per group
   int32_t npix;
+  int32_t smax;       // layer groups: samples of one ray in one group, at most
+  int32_t pad;
 };
 
 // Batched rendering: one descriptor per request (whole volume, own view,
@@ -232,6 +237,13 @@ hipError_t launch_march(const MarchArgs& a, hipStream_t s);
 // `wpb` wavefronts per workgroup (1, 2 or 4).
 hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s);
 size_t ring_lds_bytes(const MarchArgs& a, int wpb);
+// Differentiable forward on the ring layout (whole volume): also stores the
+// per-group checkpoints of sa (layer groups of sa.K cell layers).
+hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wpb, hipStream_t s);
+// Adjoint on the ring layout (grad_ring.hip): layer groups of ba.K cell layers.
+hipError_t launch_bwd_ring(const MarchArgs& a, const BwdArgs& ba, int wpb, hipStream_t s);
+size_t bwd_ring_lds_bytes(const MarchArgs& a, const BwdArgs& ba, int wpb);
+int bwd_ring_blocks(const MarchArgs& a, int wpb);
 hipError_t launch_march_lds(const MarchArgs& a, hipStream_t s);
 hipError_t launch_composite(const CompArgs& a, hipStream_t s);
 hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s);
