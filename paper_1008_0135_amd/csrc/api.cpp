@@ -316,6 +316,10 @@ int vr_create(int device, vr_ctx** out) {
   vr_ctx* ctx = new (std::nothrow) vr_ctx();
   if (!ctx) return fail(VR_ENOMEM, "out of host memory");
   ctx->device = device;
+  if (const char* m = std::getenv("VR_BWD_LAYERS")) {
+    const int k = std::atoi(m);
+    if (k >= 1 && k <= 16) ctx->bwd_layer_cap = k;
+  }
   if (const char* m = std::getenv("VR_MARCH"))
     ctx->march_mode = std::strcmp(m, "gather") == 0 ? 1 : std::strcmp(m, "slab") == 0 ? 2 : std::strcmp(m, "ring") == 0 ? 3 : 0;
   if (const char* b = std::getenv("VR_LDS_BUDGET")) {

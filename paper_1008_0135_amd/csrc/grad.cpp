@@ -70,12 +70,15 @@ int ntiles_of(int32_t W, int32_t H, int32_t tw, int32_t th) { return ((W + tw - 
 // forward launch shape, cell layers per checkpoint group (about K samples),
 // and the adjoint's wavefronts per workgroup under 160 KB of LDS.  False when
 // the view needs the sample-segment kernels.
-bool plan_ring_view(const Camera& cam, const vr_params* p, int32_t M, const int64_t n[3], vr_state::View& rv) {
+bool plan_ring_view(const Camera& cam, const vr_params* p, int32_t M, const int64_t n[3], int layer_cap,
+                    vr_state::View& rv) {
   if (p->tile != 0 && p->tile != 8) return false;
   int32_t axis = 0, slot = 0, wpb = 4;
   if (!choose_ring(cam, 4096, M, 24, 12, 2, axis, slot, wpb)) return false;
   const double db = std::fabs(cam.e3[axis]);
-  const int Lmax = std::max(1, std::min(16, (int)std::lround((double)p->ckpt_K * p->step * db)));
+  // layers per group: about K samples, at most `layer_cap` (LDS per wavefront
+  // grows with the group and occupancy falls)
+  const int Lmax = std::max(1, std::min(layer_cap, (int)std::lround((double)p->ckpt_K * p->step * db)));
   for (int L = Lmax; L >= 1; L = L > 1 ? L / 2 : 0) {
     const int smax = (int)std::floor((double)L / (p->step * db)) + 3;
     const double per_wave = 4.0 * (2.0 * (L + 1) * slot + 64.0 + 64.0 * smax);
@@ -141,7 +144,7 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
   for (int32_t v = 0; v < nviews; v++) {
     make_camera(views[v], vol->n, cams[v]);
     vr_state::View& rv = st->vs[v];
-    if (ctx->march_mode != 1 && plan_ring_view(cams[v], p, ctx->tf_m, vol->n, rv)) {
+    if (ctx->march_mode != 1 && plan_ring_view(cams[v], p, ctx->tf_m, vol->n, ctx->bwd_layer_cap, rv)) {
       rv.off = ck_total;
       ck_total += (int64_t)rv.ngrp * npix;
       ckj_total += (int64_t)rv.ngrp * npix;

@@ -88,6 +88,7 @@ struct vr_ctx {
   // 2 = LDS-staged slabs (else gather); 3 = same as 0
   int32_t march_mode = 0;
   int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
+  int32_t bwd_layer_cap = 4;  // adjoint on the ring layout: cell layers per checkpoint group, at most
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
   struct TuneEntry {
     std::string key;
