@@ -79,7 +79,16 @@ typedef struct {
 } vr_view;
 
 enum { VR_ERT_LOCAL = 0 };   /* opacity threshold tested per brick (sort-last, Sec. 2.3/2.5) */
-enum { VR_MODE_DVR = 0 };    /* emission-absorption with the over operator */
+/* VR_MODE_DVR: emission-absorption accumulated front to back, sub-volume
+ * images over-composited in depth order.  VR_MODE_MIP: maximum intensity
+ * projection (paper Sec. 2.4: the kernel's output is the maximum scalar value
+ * recorded along each ray, and a ray stops once that value reaches its
+ * maximum): M = max over the ray's samples of s = clamp((v - vmin)/(vmax -
+ * vmin), 0, 1) (M = 0 without samples), stored as (M, M, M, M); sub-volume
+ * images combine with the element-wise maximum; the table is not used, and
+ * neither empty-space skipping nor tau applies (a ray stops when M reaches 1,
+ * which leaves M unchanged). */
+enum { VR_MODE_DVR = 0, VR_MODE_MIP = 1 };
 
 /* Per-render parameters (paper Sec. 2.4: sampling distance, early termination). */
 typedef struct {
@@ -88,7 +97,7 @@ typedef struct {
   int32_t ess;       /* 1: empty-space skipping: skip bricks, and slabs of macrocells (when the
                         volume has them), whose transfer-function opacity is 0 over their range */
   int32_t ert_scope; /* VR_ERT_LOCAL */
-  int32_t mode;      /* VR_MODE_DVR */
+  int32_t mode;      /* VR_MODE_DVR or VR_MODE_MIP */
   int32_t ckpt_K;    /* adjoint: transmittance checkpoint interval in samples (>= 1; 32 typical) */
   int32_t tile;      /* pixel tile edge of one wavefront: 0 = autotuned/default (8) */
   int32_t reserved;
@@ -240,9 +249,12 @@ int vr_tf_set(vr_ctx *ctx, const float *rgba, int32_t m, double vmin, double vma
  * holds it.  If save is non-NULL (unbricked volumes only), forward state for
  * vr_render_backward is kept and returned (library-owned; free it with
  * vr_state_destroy).
+ * p->mode selects emission-absorption or maximum intensity projection (see
+ * VR_MODE_MIP above).
  * Errors: VR_EINVAL (NULL, nviews < 1, W/H out of range or differing, bad
  * params), VR_ESTATE (no transfer function set), VR_EUNSUPPORTED (save with a
- * bricked volume; an unbricked volume of 2^31 voxels or more), VR_ENOMEM, VR_EHIP.
+ * bricked volume or with VR_MODE_MIP; an unbricked volume of 2^31 voxels or
+ * more), VR_ENOMEM, VR_EHIP.
  */
 int vr_render(vr_ctx *ctx, const vr_volume *vol, const vr_view *views, int32_t nviews,
               const vr_params *p, float *out, uintptr_t stream, vr_state **save);
@@ -267,7 +279,9 @@ int vr_render_bricks(vr_ctx *ctx, const vr_volume *vol, const vr_view *view, con
 /*
  * Sort-last second half: over-composite n brick images front to back into out
  * ([H][W][4] float32, device, fully written) (paper Sec. 2.5).  order lists
- * indices into imgs, front first (NULL: array order).
+ * indices into imgs, front first (NULL: array order).  (Images of VR_MODE_MIP
+ * renders combine with the element-wise maximum instead; vr_render does that
+ * itself.)
  * Errors: VR_EINVAL (a rectangle outside W x H, an index out of range), VR_EHIP.
  */
 int vr_composite(vr_ctx *ctx, const vr_brick_image *imgs, int32_t n, const int32_t *order, int32_t W,
@@ -280,9 +294,11 @@ int vr_composite(vr_ctx *ctx, const vr_brick_image *imgs, int32_t n, const int32
  * save.  grad_out: [nviews][H][W][4] float32 device.  grad_tf: [m][4] float32
  * device.  grad_vol: [n3][n2][n1] float32 device or NULL.  accumulate = 0
  * overwrites the outputs, 1 adds to them.  The normalisation window is a
- * constant.  Each ray is walked back to front from its saved final colour and
- * transmittance, recomputing each segment of ckpt_K samples forward from its
- * saved transmittance checkpoint.
+ * constant.  Each ray is walked back to front, recomputing each stretch of
+ * about ckpt_K samples forward from its saved transmittance checkpoint: on the
+ * ring-window layout (the default where its windows fit) a stretch is a group
+ * of cell layers of the ray's 8 x 8 tile holding about ckpt_K of its samples,
+ * otherwise a segment of exactly ckpt_K samples.
  * Errors: VR_EINVAL, VR_ESTATE (state from another volume, or the transfer
  * function changed since the forward), VR_EHIP.
  */
@@ -309,7 +325,8 @@ typedef struct {
  * graph held in *cache (created when *cache is NULL) and replayed while the
  * request shapes (count, volumes, image sizes, table sizes) match; otherwise
  * it is rebuilt.  Table values, views, windows and output pointers may change
- * between calls.  Errors: VR_EINVAL, VR_ENOMEM, VR_EHIP.
+ * between calls.  Errors: VR_EINVAL, VR_EUNSUPPORTED (p->mode other than
+ * VR_MODE_DVR), VR_ENOMEM, VR_EHIP.
  */
 int vr_render_batch(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_params *p, vr_batch **cache,
                     uintptr_t stream);

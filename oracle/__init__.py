@@ -48,7 +48,12 @@ class Scene(C.Structure):
         ("vmin", C.c_double), ("vmax", C.c_double), ("step", C.c_double), ("tau", C.c_double),
         ("nboxes", C.c_int), ("boxes", C.c_void_p), ("grid", C.c_int), ("gb", C.c_int64 * 3),
         ("gnb", C.c_int * 3), ("ert_margin", C.c_double), ("geom_margin", C.c_double),
+        ("mode", C.c_int),
     ]
+
+
+MODE_DVR = 0
+MODE_MIP = 1
 
 
 _lib = None
@@ -130,7 +135,7 @@ def kd_boxes(dims, nparts):
 
 
 # ---------------------------------------------------------------- rendering
-def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin):
+def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode=0):
     vol = np.ascontiguousarray(vol, dtype=np.float32)
     tf = np.ascontiguousarray(tf, dtype=np.float32).reshape(-1, 4)
     sc = Scene()
@@ -140,6 +145,7 @@ def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin):
     sc.M = tf.shape[0]
     sc.vmin, sc.vmax, sc.step, sc.tau = float(vmin), float(vmax), float(step), float(tau)
     sc.ert_margin, sc.geom_margin = float(ert_margin), float(geom_margin)
+    sc.mode = int(mode)
     keep = [vol, tf]
     if bricks is not None:
         dims = (vol.shape[2], vol.shape[1], vol.shape[0])
@@ -173,9 +179,12 @@ def _views(views, W, H, extent):
 
 
 def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bricks=None,
-           ert_margin=1e-5, geom_margin=1e-9, nthreads=0):
-    """Render full images.  Returns dict(image [nv][H][W][4] f64, tol, flags, nsamples)."""
-    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin)
+           ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR):
+    """Render full images.  Returns dict(image [nv][H][W][4] f64, tol, flags, nsamples).
+
+    mode=MODE_MIP: maximum intensity projection, (M, M, M, M) per pixel with M the
+    largest normalised sample value along the ray (the table is not used)."""
+    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode)
     vw = _views(views, W, H, extent)
     nv = len(views)
     img = np.zeros((nv, H, W, 4), np.float64)
@@ -191,9 +200,9 @@ def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bri
 
 
 def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0.5, tau=0.99,
-                extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0):
+                extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR):
     """Render selected rays (view index, pixel u, pixel v).  Returns dict like ``render``."""
-    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin)
+    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode)
     vw = _views(views, W, H, extent)
     rv = np.ascontiguousarray(ray_view, np.int32)
     ru = np.ascontiguousarray(ray_u, np.int32)

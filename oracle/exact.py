@@ -94,8 +94,11 @@ def _owner(p, boxes):
 
 
 def render(vol, tf, R, W, H, extent, vmin, vmax, step=0.5, tau=0.99, boxes=None,
-           dvol=None, dtf=None):
+           dvol=None, dtf=None, mip=False):
     """Exact image [H][W][4] as Fractions (or Duals when dvol/dtf give a direction).
+
+    mip=True: maximum intensity projection (M, M, M, M), M = max over samples of
+    the normalised value clamped to [0, 1] (Fractions only).
 
     vol: nested [n3][n2][n1] numbers; tf: [M][4]; R: 3x3; boxes: optional list of
     (lo, hi, closed) ownership boxes.  Returns a list of rows of pixel tuples.
@@ -188,6 +191,21 @@ def render(vol, tf, R, W, H, extent, vmin, vmax, step=0.5, tau=0.99, boxes=None,
                 row.append((zero, zero, zero, zero))
                 continue
             tin, tout = iv
+            if mip:
+                m = Fr(0)
+                k = 0
+                while True:
+                    t = tin + (k + Fr(1, 2)) * dt
+                    if not t < tout:
+                        break
+                    p = [o[i] + t * d[i] for i in range(3)]
+                    if bx is not None and _owner(p, bx) is None:
+                        raise AssertionError("sample inside the volume owned by no box")
+                    s_raw = (value_at(p) - lo_w) / (hi_w - lo_w) if hi_w > lo_w else Fr(0)
+                    m = max(m, min(Fr(1), max(Fr(0), s_raw)))
+                    k += 1
+                row.append((m, m, m, m))
+                continue
             chains = {}  # owner -> [C(3), T, stopped, tfirst]
             k = 0
             while True:

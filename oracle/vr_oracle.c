@@ -86,7 +86,19 @@ typedef struct {
   int gnb[3];          /* grid brick count per axis; box index = (k3*gnb2 + k2)*gnb1 + k1 */
   double ert_margin;   /* opacity window around tau treated as a tie */
   double geom_margin;  /* distance (voxels) treated as a geometric tie */
+  int mode;            /* OR_MODE_DVR or OR_MODE_MIP */
 } or_scene;
+
+/*
+ * Maximum intensity projection (Sec. 2.4: the kernel's output is the maximum
+ * scalar value recorded along each ray; termination once the pixel value
+ * reaches its maximum).  Read here as: M = max over the ray's samples of the
+ * normalised value s = clamp((v - vmin) / (vmax - vmin), 0, 1) (s = 0 when
+ * vmax = vmin; M = 0 without samples), written as (M, M, M, M).  Sub-volume
+ * images combine with the element-wise maximum, in any order.
+ */
+#define OR_MODE_DVR 0
+#define OR_MODE_MIP 1
 
 typedef struct {
   double c[3], e1[3], e2[3], e3[3], S;
@@ -287,6 +299,27 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
   if (fabs(X - floor(X + 0.5)) < sc->geom_margin / sc->step) gtie = 1;
   *nsamp = n;
 
+  if (sc->mode == OR_MODE_MIP) {
+    double m = 0.0;
+    for (int64_t k = 0; k < n; k++) {
+      double t = tin + ((double)k + 0.5) * sc->step;
+      double p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+      if (sc->nboxes > 0 && owner(sc, p, &gtie) < 0) {
+        gtie = 1;
+        continue;
+      }
+      int64_t i0[3];
+      double f[3];
+      double val = trilinear(sc, p, i0, f);
+      double s = sc->vmax > sc->vmin ? (val - sc->vmin) / (sc->vmax - sc->vmin) : 0.0;
+      if (s < 0.0) s = 0.0;
+      if (s > 1.0) s = 1.0;
+      if (s > m) m = s;
+    }
+    for (int c = 0; c < 4; c++) out[c] = m;
+    if (gtie) flags |= OR_FLAG_GEOM;
+    return flags;
+  }
   rs->ntouched = 0;
   for (int64_t k = 0; k < n; k++) {
     double t = tin + ((double)k + 0.5) * sc->step;

@@ -31,6 +31,8 @@ VR_EUNSUPPORTED = -6
 _NAMES = {0: "VR_OK", -1: "VR_EINVAL", -2: "VR_ENOMEM", -3: "VR_EHIP", -4: "VR_ENONFINITE",
           -5: "VR_ESTATE", -6: "VR_EUNSUPPORTED"}
 
+VR_MODE_DVR = 0
+VR_MODE_MIP = 1
 VR_BRICK_GRID = 0
 VR_BRICK_LONGEST_AXIS = 1
 VR_STAGE_SETUP, VR_STAGE_MARCH, VR_STAGE_COMPOSITE, VR_STAGE_BACKWARD, VR_STAGE_BATCH = range(5)
@@ -176,10 +178,12 @@ def make_view(R, W, H, extent=0.0) -> vr_view:
     return v
 
 
-def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0) -> vr_params:
+def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0, mode=0) -> vr_params:
+    """mode: VR_MODE_DVR (emission-absorption) or VR_MODE_MIP (maximum intensity projection)."""
     p = vr_params()
     lib().vr_params_default(C.byref(p))
     p.step, p.tau, p.ess, p.ckpt_K, p.tile = float(step), float(tau), int(ess), int(ckpt_K), int(tile)
+    p.mode = int(mode)
     return p
 
 

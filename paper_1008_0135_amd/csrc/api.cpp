@@ -171,7 +171,7 @@ int check_params(const vr_params* p) {
   if (!(p->step > 0.0) || !std::isfinite(p->step)) return fail(VR_EINVAL, "step must be > 0");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(VR_EINVAL, "tau must be > 0 (>= 1 disables)");
   if (p->ert_scope != VR_ERT_LOCAL) return fail(VR_EUNSUPPORTED, "only VR_ERT_LOCAL is implemented");
-  if (p->mode != VR_MODE_DVR) return fail(VR_EUNSUPPORTED, "only VR_MODE_DVR is implemented");
+  if (p->mode != VR_MODE_DVR && p->mode != VR_MODE_MIP) return fail(VR_EINVAL, "unknown mode %d", p->mode);
   if (p->ckpt_K < 1) return fail(VR_EINVAL, "ckpt_K must be >= 1");
   if (p->tile != 0 && p->tile != 4 && p->tile != 8 && p->tile != 16)
     return fail(VR_EINVAL, "tile must be 0, 4, 8 or 16");
@@ -212,6 +212,7 @@ void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, d
   a.inv_range = vmax > vmin ? (float)(1.0 / (vmax - vmin)) : 0.0f;
   a.M = M;
   a.tf = tf;
+  a.mip = p->mode == VR_MODE_MIP ? 1 : 0;
   a.tile_w = p->tile ? p->tile : 8;
   a.tile_h = 64 / a.tile_w;
 }
@@ -258,8 +259,9 @@ int prepare_macrocells(vr_ctx* ctx, vr_volume* vol, const vr_params* p, double v
   a.mc_clear = nullptr;
   for (int i = 0; i < 3; i++) a.mcn[i] = 0;
   // nothing to skip unless a run of at least three table entries is fully
-  // transparent (a macrocell's entry range spans three or more entries)
-  if (!p->ess || vol->mc <= 0 || ctx->tf_zero_run < 3) return VR_OK;
+  // transparent (a macrocell's entry range spans three or more entries);
+  // maximum intensity projection does not use the table
+  if (!p->ess || p->mode != VR_MODE_DVR || vol->mc <= 0 || ctx->tf_zero_run < 3) return VR_OK;
   if (!vol->mc_classified || vol->mc_tf_version != ctx->tf_version || vol->mc_vmin != vmin || vol->mc_vmax != vmax) {
     VR_HIP(launch_mc_classify(vol->d_mc_mm, vol->mcn[0] * vol->mcn[1] * vol->mcn[2], ctx->d_tf_nz, ctx->tf_m, vmin,
                               vmax, vol->d_mc_clear, vol->d_mc_count, s));

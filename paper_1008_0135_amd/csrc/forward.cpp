@@ -44,7 +44,9 @@ void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params*
   for (int32_t b = 0; b < nb; b++) {
     rects[b] = brick_rect(cam, P.boxes[b]);
     if (rects[b].w == 0 || rects[b].h == 0) continue;
-    if (p->ess && brick_transparent(vol->bricks[b].vmin, vol->bricks[b].vmax, tf, M, vmin, vmax)) continue;
+    if (p->ess && p->mode == VR_MODE_DVR &&
+        brick_transparent(vol->bricks[b].vmin, vol->bricks[b].vmax, tf, M, vmin, vmax))
+      continue;
     DevBrickView v;
     std::memset(&v, 0, sizeof v);
     v.brick = b;
@@ -161,7 +163,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8)
       ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
                          a.ring_slot, ring_wpb);
-    if (!ring && !extras && mode != 1) {
+    if (!ring && !extras && mode != 1 && !a.mip) {  // (the slab march has no projection mode)
       lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
       // rays nearly parallel to axis 1 need a wider slab box: retry with twice the budget
       if (!lds && budget < 8192 && choose_slab(cams[v], a.tile_w, a.tile_h, 8192, a.slab_axis, a.slab_T)) {
@@ -180,6 +182,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       c.n = (int32_t)vp.layers_order.size();
       c.W = W;
       c.H = H;
+      c.mip = base.mip;
       c.out = reinterpret_cast<float4*>(out) + (int64_t)v * W * H;
       VR_TRY(stage_begin(ctx, VR_STAGE_COMPOSITE, s));
       VR_HIP(launch_composite(c, s));

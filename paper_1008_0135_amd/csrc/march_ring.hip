@@ -42,7 +42,8 @@ constexpr int kSlots = 3;
 // SAVE (differentiable forward, whole volume): also store, for every group of
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
-template <bool ESS, bool SAVE>
+// MIP: maximum intensity projection (no table, no skipping, no saving).
+template <bool ESS, bool SAVE, bool MIP>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   const int sB = by ? ysl : zsl, sG = by ? zsl : ysl;
   gfloat* gbase = (gfloat*)br.base;
 
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f, mx = 0.f;
   int j = 0;
   bool done = cnt == 0;
 
@@ -180,15 +181,20 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
       }
       gfloat* p = gbase + (c.iz * zsl + c.iy * ysl + c.ix);
       const float val = trilerp(p[0], p[1], p[ysl], p[ysl + 1], p[zsl], p[zsl + 1], p[zsl + ysl], p[zsl + ysl + 1], c);
-      accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
       ++j;
-      if (j >= cnt || 1.f - T >= a.tau) done = true;
+      if (MIP) {
+        mx = fmaxf(mx, norm_value(val, a.vmin, a.inv_range));
+        if (j >= cnt || mx >= 1.f) done = true;
+      } else {
+        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        if (j >= cnt || 1.f - T >= a.tau) done = true;
+      }
     }
     if (SAVE) {
       while (gnext < ngrp_tile) save_group(gnext++, T, j);
       if (valid) sa.nused[pix] = j;
     }
-    if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
+    if (valid) *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, 1.f - T);
     return;
   }
 
@@ -263,9 +269,14 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
         const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
         const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
                              : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
-        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
         ++j;
-        if (j >= cnt || 1.f - T >= a.tau) done = true;
+        if (MIP) {
+          mx = fmaxf(mx, norm_value(val, a.vmin, a.inv_range));
+          if (j >= cnt || mx >= 1.f) done = true;
+        } else {
+          accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+          if (j >= cnt || 1.f - T >= a.tau) done = true;
+        }
       }
       if (__all(done)) {
         if (SAVE)
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   wait_loads();  // no load may still target LDS when the wavefront ends
   if (SAVE && valid) sa.nused[pix] = j;
-  if (valid) *dst = make_float4(Cr, Cg, Cb, 1.f - T);
+  if (valid) *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, 1.f - T);
 }
 
 }  // namespace
@@ -392,19 +403,25 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   // registers the plain march does not need
   SaveArgs none;
   std::memset(&none, 0, sizeof none);
-  if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
-  else hipLaunchKernelGGL((k_march_ring<false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  if (a.mip) {
+    if (a.mc > 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_march_ring<false, false, true>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  } else if (a.mc > 0) {
+    hipLaunchKernelGGL((k_march_ring<true, false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  } else {
+    hipLaunchKernelGGL((k_march_ring<false, false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wpb, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4) ||
-      a.mc != 0 || sa.K < 1 || !sa.ckpt_j)
+      a.mc != 0 || a.mip != 0 || sa.K < 1 || !sa.ckpt_j)
     return hipErrorInvalidValue;
   const int groups = (a.ntiles + wpb - 1) / wpb;
   const int grid = ((groups + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_march_ring<false, true>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, sa);
+  hipLaunchKernelGGL((k_march_ring<false, true, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, sa);
   return hipGetLastError();
 }
 

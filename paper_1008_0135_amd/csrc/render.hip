@@ -11,7 +11,12 @@
 //
 // Composite (paper Sec. 2.5): one lane per output pixel walks the brick
 // images front to back and applies the over operator where its pixel lies
-// inside a brick's rectangle.
+// inside a brick's rectangle (the element-wise maximum for maximum intensity
+// projection, which needs no order).
+//
+// Maximum intensity projection (paper Sec. 2.4): the march keeps the largest
+// normalised sample value M of the ray and stops once M reaches 1; pixels are
+// (M, M, M, M).
 #include "sample.h"
 #include "vr_internal.h"
 
@@ -36,7 +41,7 @@ __device__ __forceinline__ int xcd_block(int nblk) {
   return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
 }
 
-template <int TW>
+template <int TW, bool MIP>
 __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   extern __shared__ float4 s_tf[];
   for (int i = threadIdx.x; i < a.M; i += 256) s_tf[i] = a.tf[i];
@@ -68,7 +73,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   double o[3];
   pixel_origin(a.cam, u, v, o);
   const double* d = a.cam.e3;
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
+  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f, mx = 0.f;
   double tin;
   int64_t n;
   if (ray_lattice(o, d, a.hi, a.step, tin, n)) {
@@ -88,12 +93,18 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         gfloat* p = base + (c.iz * zs + c.iy * ys + c.ix);
         const f2u a00 = ld_pair(p), a01 = ld_pair(p + ys), a10 = ld_pair(p + zs), a11 = ld_pair(p + zs + ys);
         const float val = trilerp(a00.x, a00.y, a01.x, a01.y, a10.x, a10.y, a11.x, a11.y, c);
-        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
-        if (1.f - T >= a.tau) break;
+        if (MIP) {
+          mx = fmaxf(mx, norm_value(val, a.vmin, a.inv_range));
+          if (mx >= 1.f) break;
+        } else {
+          accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+          if (1.f - T >= a.tau) break;
+        }
       }
     }
   }
-  a.img[bvw.img_off + (int64_t)ly * bvw.w + lx] = make_float4(Cr, Cg, Cb, 1.f - T);
+  a.img[bvw.img_off + (int64_t)ly * bvw.w + lx] =
+      MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, 1.f - T);
 }
 
 __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
@@ -106,11 +117,18 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
     const unsigned lx = (unsigned)(x - L.x0), ly = (unsigned)(y - L.y0);
     if (lx < (unsigned)L.w && ly < (unsigned)L.h) {
       const float4 c = L.rgba[(int64_t)ly * L.w + lx];
-      const float t = 1.f - A;
-      Cr = fmaf(t, c.x, Cr);
-      Cg = fmaf(t, c.y, Cg);
-      Cb = fmaf(t, c.z, Cb);
-      A = fmaf(t, c.w, A);
+      if (a.mip) {
+        Cr = fmaxf(Cr, c.x);
+        Cg = fmaxf(Cg, c.y);
+        Cb = fmaxf(Cb, c.z);
+        A = fmaxf(A, c.w);
+      } else {
+        const float t = 1.f - A;
+        Cr = fmaf(t, c.x, Cr);
+        Cg = fmaf(t, c.y, Cg);
+        Cb = fmaf(t, c.z, Cb);
+        A = fmaf(t, c.w, A);
+      }
     }
   }
   a.out[(int64_t)y * a.W + x] = make_float4(Cr, Cg, Cb, A);
@@ -123,11 +141,20 @@ hipError_t launch_march(const MarchArgs& a, hipStream_t s) {
   const int nblk = (a.ntiles + 3) / 4;
   const int grid = ((nblk + 7) / 8) * 8;
   const size_t lds = sizeof(float4) * (size_t)a.M;
-  switch (a.tile_w) {
-    case 8: hipLaunchKernelGGL(k_march<8>, dim3(grid), dim3(256), lds, s, a); break;
-    case 16: hipLaunchKernelGGL(k_march<16>, dim3(grid), dim3(256), lds, s, a); break;
-    case 4: hipLaunchKernelGGL(k_march<4>, dim3(grid), dim3(256), lds, s, a); break;
-    default: return hipErrorInvalidValue;
+  if (a.mip) {
+    switch (a.tile_w) {
+      case 8: hipLaunchKernelGGL((k_march<8, true>), dim3(grid), dim3(256), lds, s, a); break;
+      case 16: hipLaunchKernelGGL((k_march<16, true>), dim3(grid), dim3(256), lds, s, a); break;
+      case 4: hipLaunchKernelGGL((k_march<4, true>), dim3(grid), dim3(256), lds, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (a.tile_w) {
+      case 8: hipLaunchKernelGGL((k_march<8, false>), dim3(grid), dim3(256), lds, s, a); break;
+      case 16: hipLaunchKernelGGL((k_march<16, false>), dim3(grid), dim3(256), lds, s, a); break;
+      case 4: hipLaunchKernelGGL((k_march<4, false>), dim3(grid), dim3(256), lds, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }

@@ -150,7 +150,7 @@ int prepare_macrocells(vr_ctx* ctx, vr_volume* vol, const vr_params* p, double v
 // Tuned launch shape for a render (tile edge, LDS budget, march mode); defaults when untuned.
 void tuned_shape(const vr_ctx* ctx, const vr_volume* vol, int32_t W, int32_t H, const vr_params* p, int32_t& tile,
                  int32_t& budget, int32_t& mode);
-std::string tune_key(const vr_volume* vol, int32_t W, int32_t H);
+std::string tune_key(const vr_volume* vol, int32_t W, int32_t H, int32_t mode);
 void tune_load(vr_ctx* ctx);
 int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, vr_batch** cache, hipStream_t s,
                  int32_t force_blocks);

@@ -74,6 +74,12 @@ __device__ __forceinline__ Classified classify(float val, float vmin, float inv_
   return k;
 }
 
+// Normalised value clamped to [0, 1] (the table coordinate before scaling by
+// M - 1): what maximum intensity projection keeps the largest of.
+__device__ __forceinline__ float norm_value(float val, float vmin, float inv_range) {
+  return fminf(fmaxf((val - vmin) * inv_range, 0.f), 1.f);
+}
+
 // One front-to-back emission-absorption step: C += T a rgb, T *= (1 - a).
 __device__ __forceinline__ void accumulate(const Classified& k, float& Cr, float& Cg, float& Cb, float& T) {
   const float Ta = T * k.a;

@@ -22,10 +22,10 @@ static int size_class(int64_t n) {
   return c;  // floor(log2 n)
 }
 
-std::string tune_key(const vr_volume* vol, int32_t W, int32_t H) {
+std::string tune_key(const vr_volume* vol, int32_t W, int32_t H, int32_t mode) {
   char buf[128];
-  snprintf(buf, sizeof buf, "render/%d.%d.%d/%s/%dx%d", size_class(vol->n[0]), size_class(vol->n[1]),
-           size_class(vol->n[2]), vol->bricked ? "bricked" : "whole", W, H);
+  snprintf(buf, sizeof buf, "render/%d.%d.%d/%s/%dx%d%s", size_class(vol->n[0]), size_class(vol->n[1]),
+           size_class(vol->n[2]), vol->bricked ? "bricked" : "whole", W, H, mode == VR_MODE_MIP ? "/mip" : "");
   return buf;
 }
 
@@ -35,7 +35,7 @@ void tuned_shape(const vr_ctx* ctx, const vr_volume* vol, int32_t W, int32_t H, 
   budget = ctx->lds_budget;
   mode = ctx->march_mode;
   if (p->tile) return;
-  const std::string key = tune_key(vol, W, H);
+  const std::string key = tune_key(vol, W, H, p->mode);
   for (const auto& e : ctx->tune)
     if (e.key == key) {
       tile = e.tile;
@@ -113,7 +113,7 @@ int vr_autotune(vr_ctx* ctx, const vr_volume* cvol, const vr_view* view, const v
     (void)hipGetLastError();
     return fail(VR_ENOMEM, "hipMalloc for the tuning image failed");
   }
-  const std::string key = tune_key(vol, view->W, view->H);
+  const std::string key = tune_key(vol, view->W, view->H, p->mode);
   // drop a previous entry for this key so the candidates run as given
   for (size_t i = 0; i < ctx->tune.size(); i++)
     if (ctx->tune[i].key == key) {

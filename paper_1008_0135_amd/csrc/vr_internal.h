@@ -169,6 +169,8 @@ struct MarchArgs {
   int32_t slab_T;        // cell layers per slab
   int32_t lds_budget;    // floats of LDS for one slab's voxel box
   int32_t ring_slot;     // ring march: floats per LDS ring slot (one voxel layer's window)
+  int32_t mip;           // 1: maximum intensity projection (pixels (M, M, M, M)), 0: emission-absorption
+  int32_t pad2;
   const float4* tf;      // [M] RGBA
   const DevBrick* bricks;
   const DevBrickView* bv;
@@ -182,7 +184,7 @@ struct CompArgs {
   const CompLayer* layers;
   int32_t n;
   int32_t W, H;
-  int32_t pad;
+  int32_t mip;        // 1: element-wise maximum instead of the over operator
   float4* out;
 };
 
