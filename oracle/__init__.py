@@ -35,7 +35,8 @@ def build(force: bool = True) -> str:
 
 
 class View(C.Structure):
-    _fields_ = [("R", C.c_double * 9), ("W", C.c_int), ("H", C.c_int), ("extent", C.c_double)]
+    _fields_ = [("R", C.c_double * 9), ("W", C.c_int), ("H", C.c_int), ("extent", C.c_double),
+                ("eye_dist", C.c_double)]
 
 
 class Box(C.Structure):
@@ -168,24 +169,27 @@ def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode
     return sc, keep
 
 
-def _views(views, W, H, extent):
+def _views(views, W, H, extent, eye_dist=0.0):
     arr = (View * len(views))()
     for j, R in enumerate(views):
         R = np.asarray(R, dtype=np.float64).reshape(9)
         for i in range(9):
             arr[j].R[i] = R[i]
         arr[j].W, arr[j].H, arr[j].extent = int(W), int(H), float(extent)
+        arr[j].eye_dist = float(eye_dist)
     return arr
 
 
 def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bricks=None,
-           ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR):
+           ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR, eye_dist=0.0):
     """Render full images.  Returns dict(image [nv][H][W][4] f64, tol, flags, nsamples).
 
     mode=MODE_MIP: maximum intensity projection, (M, M, M, M) per pixel with M the
-    largest normalised sample value along the ray (the table is not used)."""
+    largest normalised sample value along the ray (the table is not used).
+    eye_dist > 0: perspective camera with the eye at distance eye_dist from the box
+    centre (0: orthographic)."""
     sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode)
-    vw = _views(views, W, H, extent)
+    vw = _views(views, W, H, extent, eye_dist)
     nv = len(views)
     img = np.zeros((nv, H, W, 4), np.float64)
     tol = np.zeros_like(img)
@@ -200,10 +204,11 @@ def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bri
 
 
 def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0.5, tau=0.99,
-                extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR):
+                extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR,
+                eye_dist=0.0):
     """Render selected rays (view index, pixel u, pixel v).  Returns dict like ``render``."""
     sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode)
-    vw = _views(views, W, H, extent)
+    vw = _views(views, W, H, extent, eye_dist)
     rv = np.ascontiguousarray(ray_view, np.int32)
     ru = np.ascontiguousarray(ray_u, np.int32)
     rr = np.ascontiguousarray(ray_v, np.int32)
@@ -221,13 +226,13 @@ def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0
 
 
 def render_grad(vol, tf, view, W, H, grad_out, vmin, vmax, step=0.5, tau=2.0, extent=0.0,
-                want_vol=True, nthreads=0):
+                want_vol=True, nthreads=0, eye_dist=0.0):
     """Exact FP64 gradient of sum(grad_out * image) w.r.t. the TF table and the voxels.
 
     Returns (grad_tf [M][4], grad_vol [n3][n2][n1] or None, image [H][W][4]).
     """
     sc, keep = _scene(vol, tf, vmin, vmax, step, tau, None, 0.0, 0.0)
-    vw = _views([view], W, H, extent)
+    vw = _views([view], W, H, extent, eye_dist)
     g = np.ascontiguousarray(grad_out, np.float64).reshape(H, W, 4)
     M = sc.M
     gtf = np.zeros((M, 4), np.float64)

@@ -31,6 +31,12 @@
  *     x = ((u+1/2)/W - 1/2) S, y = ((v+1/2)/H - 1/2) S H/W with S the extent
  *     (box diagonal when 0), the ray starts at c + x e1 + y e2 - S e3 and runs
  *     along e3;
+ *   - perspective camera (the projection a render request may carry, Sec. 2.2;
+ *     evaluated in Sec. 3): the eye sits at c - D e3 (D = eye distance, larger
+ *     than half the box diagonal so the whole box lies in front of it), the
+ *     pixel grid above lies on the plane through c normal to e3, and the ray of
+ *     pixel (u,v) starts at the eye and runs along the unit vector of
+ *     x e1 + y e2 + D e3; samples are still a step apart along the ray;
  *   - samples sit on one global lattice per ray anchored at the whole-volume
  *     entry: t_k = t_in + (k + 1/2) step while t_k < t_out;
  *   - trilinear interpolation with the cell index clamped to [0, n-2];
@@ -64,7 +70,8 @@
 typedef struct {
   double R[9]; /* row-major rotation; row i is view axis e_{i+1} in volume coordinates */
   int W, H;
-  double extent; /* S; <= 0 means the box diagonal */
+  double extent;   /* S; <= 0 means the box diagonal */
+  double eye_dist; /* D: 0 = orthographic, > 0 = perspective with the eye at c - D e3 */
 } or_view;
 
 typedef struct {
@@ -101,7 +108,7 @@ typedef struct {
 #define OR_MODE_MIP 1
 
 typedef struct {
-  double c[3], e1[3], e2[3], e3[3], S;
+  double c[3], e1[3], e2[3], e3[3], S, D;
   int W, H;
 } camera;
 
@@ -115,6 +122,7 @@ static void make_camera(const or_scene *sc, const or_view *vw, camera *cam) {
     cam->e3[i] = vw->R[6 + i];
   }
   cam->S = vw->extent > 0.0 ? vw->extent : sqrt(diag);
+  cam->D = vw->eye_dist > 0.0 ? vw->eye_dist : 0.0;
   cam->W = vw->W;
   cam->H = vw->H;
 }
@@ -123,6 +131,17 @@ static void make_camera(const or_scene *sc, const or_view *vw, camera *cam) {
 static void pixel_ray(const camera *cam, int u, int v, double o[3], double d[3]) {
   double x = (((double)u + 0.5) / (double)cam->W - 0.5) * cam->S;
   double y = (((double)v + 0.5) / (double)cam->H - 0.5) * cam->S * (double)cam->H / (double)cam->W;
+  if (cam->D > 0.0) {
+    double w[3], len = 0.0;
+    for (int i = 0; i < 3; i++) {
+      o[i] = cam->c[i] - cam->D * cam->e3[i];
+      w[i] = x * cam->e1[i] + y * cam->e2[i] + cam->D * cam->e3[i];
+      len += w[i] * w[i];
+    }
+    len = sqrt(len);
+    for (int i = 0; i < 3; i++) d[i] = w[i] / len;
+    return;
+  }
   for (int i = 0; i < 3; i++) {
     o[i] = cam->c[i] + x * cam->e1[i] + y * cam->e2[i] - cam->S * cam->e3[i];
     d[i] = cam->e3[i];
