@@ -148,6 +148,27 @@ def bench_fwd_bwd(ctx, stream):
             "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3), "nominal_samples": int(nominal)}
 
 
+def bench_variants(ctx, h, dims, views_R, W, H, stream):
+    """The same cube and views rendered with a perspective camera (eye at twice
+    the half diagonal from the centre: a 53-degree field of view at the
+    box-diagonal extent) and as a maximum intensity projection."""
+    import torch
+    n = np.array(dims, np.float64)
+    eye = float(np.sqrt(((n - 1) ** 2).sum()))  # 2 x half diagonal
+    out = torch.empty((len(views_R), H, W, 4), device="cuda")
+    res = {}
+    for name, mode, ed in (("perspective", 0, eye), ("mip", vr.VR_MODE_MIP, 0.0)):
+        views = [vr.make_view(R, W, H, eye_dist=ed) for R in views_R]
+        params = vr.make_params(step=0.5, tau=0.99, ess=1, mode=mode)
+        nominal = sum(vr.vr_count_samples(dims, v, 0.5) for v in views)
+        ms = _events_ms(lambda: vr.vr_render(ctx, h, views, params, out, stream), 3, stream)
+        log(f"{name}: {ms / len(views):.3f} ms/frame, {nominal / ms / 1e6:.1f} Gsamples/s")
+        res[name] = {"ms_per_frame": round(ms / len(views), 4), "gsamples_per_s": round(nominal / ms / 1e6, 3),
+                     "nominal_samples_per_frame": int(nominal // len(views))}
+    res["perspective"]["eye_dist"] = round(eye, 2)
+    return res
+
+
 def counter_traffic(config):
     """HBM bytes per march launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
@@ -330,6 +351,7 @@ def main():
     }
 
     if not args.no_extras:
+        result.update(bench_variants(ctx, h, (n1, n2, n3), views_R, W, H, stream))
         result["batched"] = bench_batched(ctx, stream)
         result["fwd_bwd"] = bench_fwd_bwd(ctx, stream)
 

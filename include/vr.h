@@ -65,17 +65,25 @@ typedef struct vr_batch vr_batch;
 
 /*
  * Render request view (paper Sec. 2.2: a render request carries the
- * transformation and projection; this build uses an orthographic projection).
- * Rows of R are the view axes in volume coordinates: e1 = R[0..2] (image x),
- * e2 = R[3..5] (image y), e3 = R[6..8] (ray direction).  Pixel (u,v) has
- * x = ((u+1/2)/W - 1/2) S and y = ((v+1/2)/H - 1/2) S H/W; its ray starts at
- * c + x e1 + y e2 - S e3 (c = box centre) and runs along e3.  R = identity
- * looks along +axis 3 with image x = axis 1 and image y = axis 2.
+ * transformation and the projection, orthographic or perspective; Sec. 3
+ * measures both).  Rows of R are the view axes in volume coordinates:
+ * e1 = R[0..2] (image x), e2 = R[3..5] (image y), e3 = R[6..8] (viewing
+ * direction).  Pixel (u,v) has x = ((u+1/2)/W - 1/2) S and
+ * y = ((v+1/2)/H - 1/2) S H/W (c = box centre).
+ *   Orthographic (eye_dist == 0): the ray starts at c + x e1 + y e2 - S e3 and
+ *   runs along e3.
+ *   Perspective (eye_dist = D > 0): the eye sits at c - D e3; the pixel grid
+ *   lies on the plane through c normal to e3, and the ray of (u,v) starts at
+ *   the eye and runs along the unit vector of x e1 + y e2 + D e3.  D must
+ *   exceed half the box diagonal (the whole box then lies in front of the eye).
+ * In both, samples are the step apart along the ray.  R = identity looks along
+ * +axis 3 with image x = axis 1 and image y = axis 2.
  */
 typedef struct {
-  double R[9];   /* row-major rotation (orthonormal rows expected, not enforced) */
-  int32_t W, H;  /* image size in pixels, each in [1, 16384] */
-  double extent; /* S: image width in voxels; <= 0 selects the box diagonal */
+  double R[9];     /* row-major rotation (orthonormal rows expected, not enforced) */
+  int32_t W, H;    /* image size in pixels, each in [1, 16384] */
+  double extent;   /* S: image width in voxels; <= 0 selects the box diagonal */
+  double eye_dist; /* 0: orthographic; > 0: perspective, eye at this distance from the box centre */
 } vr_view;
 
 enum { VR_ERT_LOCAL = 0 };   /* opacity threshold tested per brick (sort-last, Sec. 2.3/2.5) */

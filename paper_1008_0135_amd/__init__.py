@@ -46,7 +46,8 @@ class VRError(RuntimeError):
 
 
 class vr_view(C.Structure):
-    _fields_ = [("R", C.c_double * 9), ("W", C.c_int32), ("H", C.c_int32), ("extent", C.c_double)]
+    _fields_ = [("R", C.c_double * 9), ("W", C.c_int32), ("H", C.c_int32), ("extent", C.c_double),
+                ("eye_dist", C.c_double)]
 
 
 class vr_params(C.Structure):
@@ -169,12 +170,13 @@ def _ptr(t):
     raise TypeError(type(t))
 
 
-def make_view(R, W, H, extent=0.0) -> vr_view:
+def make_view(R, W, H, extent=0.0, eye_dist=0.0) -> vr_view:
+    """eye_dist 0: orthographic; > 0: perspective with the eye that far from the box centre."""
     v = vr_view()
     flat = [float(x) for row in R for x in row] if hasattr(R[0], "__len__") else [float(x) for x in R]
     for i in range(9):
         v.R[i] = flat[i]
-    v.W, v.H, v.extent = int(W), int(H), float(extent)
+    v.W, v.H, v.extent, v.eye_dist = int(W), int(H), float(extent), float(eye_dist)
     return v
 
 
@@ -367,10 +369,10 @@ def vr_autotune_batch(ctx, reqs, params, cache=None, stream=None):
     return r, h.value
 
 
-def make_request(vol, R, W, H, tf, vmin, vmax, out, extent=0.0):
+def make_request(vol, R, W, H, tf, vmin, vmax, out, extent=0.0, eye_dist=0.0):
     q = vr_request()
     q.vol = vol
-    q.view = make_view(R, W, H, extent)
+    q.view = make_view(R, W, H, extent, eye_dist)
     q.tf = _ptr(tf)
     q.m = int(tf.shape[0])
     q.vmin, q.vmax = float(vmin), float(vmax)

@@ -153,16 +153,23 @@ int reduce_minmax(vr_ctx* ctx, const float* x, int64_t n, hipStream_t s, float o
 static bool finite_view(const vr_view& v) {
   for (int i = 0; i < 9; i++)
     if (!std::isfinite(v.R[i])) return false;
-  return std::isfinite(v.extent);
+  return std::isfinite(v.extent) && std::isfinite(v.eye_dist);
 }
 
-int check_view(const vr_view* v) {
+int check_view(const vr_view* v, const int64_t n[3]) {
   if (!v) return fail(VR_EINVAL, "view is NULL");
   if (v->W < 1 || v->H < 1 || v->W > 16384 || v->H > 16384)
     return fail(VR_EINVAL, "image size %dx%d outside [1, 16384]", v->W, v->H);
   if (!finite_view(*v)) return fail(VR_EINVAL, "view has non-finite entries");
   double e3 = v->R[6] * v->R[6] + v->R[7] * v->R[7] + v->R[8] * v->R[8];
   if (!(e3 > 0.0)) return fail(VR_EINVAL, "view direction (third row of R) is zero");
+  if (v->eye_dist < 0.0) return fail(VR_EINVAL, "eye_dist must be >= 0");
+  if (v->eye_dist > 0.0) {
+    double diag = 0.0;
+    for (int i = 0; i < 3; i++) diag += (double)(n[i] - 1) * (double)(n[i] - 1);
+    if (!(v->eye_dist > 0.5 * std::sqrt(diag)))
+      return fail(VR_EINVAL, "eye_dist %g must exceed half the box diagonal (%g)", v->eye_dist, 0.5 * std::sqrt(diag));
+  }
   return VR_OK;
 }
 
@@ -290,7 +297,7 @@ extern "C" {
 
 const char* vr_last_error(void) { return g_err.c_str(); }
 
-int vr_version(void) { return 1; }
+int vr_version(void) { return 2; }
 
 void vr_params_default(vr_params* p) {
   if (!p) return;
@@ -785,7 +792,7 @@ int vr_plan_view(const int64_t dims[3], const vr_brick_spec* spec, const vr_view
   clear_error();
   if (!dims || !spec || !view || !nb) return fail(VR_EINVAL, "dims, spec, view and nb must be non-NULL");
   VR_TRY(check_dims(dims[0], dims[1], dims[2]));
-  VR_TRY(check_view(view));
+  VR_TRY(check_view(view, dims));
   Partition P;
   std::string err;
   if (spec->mode == VR_BRICK_GRID) {
@@ -809,7 +816,7 @@ int vr_plan_view(const int64_t dims[3], const vr_brick_spec* spec, const vr_view
     }
   if (order) {
     std::vector<int32_t> o;
-    depth_order(P, cam.e3, o);
+    depth_order(P, cam, o);
     std::copy(o.begin(), o.end(), order);
   }
   *nb = have;
@@ -855,7 +862,7 @@ int vr_count_samples(const int64_t dims[3], const vr_view* view, double step, in
   clear_error();
   if (!dims || !view || !nominal) return fail(VR_EINVAL, "dims, view and nominal must be non-NULL");
   VR_TRY(check_dims(dims[0], dims[1], dims[2]));
-  VR_TRY(check_view(view));
+  VR_TRY(check_view(view, dims));
   if (!(step > 0.0)) return fail(VR_EINVAL, "step must be > 0");
   Camera cam;
   make_camera(*view, dims, cam);

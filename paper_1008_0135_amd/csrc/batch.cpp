@@ -85,7 +85,7 @@ int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params
     if (r.vol->bricked) return fail(VR_EINVAL, "request %d: batched requests take unbricked volumes", i);
     if (r.vol->n[0] * r.vol->n[1] * r.vol->n[2] >= ((int64_t)1 << 31))
       return fail(VR_EUNSUPPORTED, "request %d: volume of 2^31 voxels or more", i);
-    VR_TRY(check_view(&r.view));
+    VR_TRY(check_view(&r.view, r.vol->n));
     if (r.m < 2 || r.m > 4096) return fail(VR_EINVAL, "request %d: table size %d outside [2, 4096]", i, r.m);
     if (!std::isfinite(r.vmin) || !std::isfinite(r.vmax) || r.vmax < r.vmin)
       return fail(VR_EINVAL, "request %d: window must be finite with vmax >= vmin", i);

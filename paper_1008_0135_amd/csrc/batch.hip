@@ -55,9 +55,8 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs ba) {
     const int tx = t % rq.tiles_x, ty = t / rq.tiles_x;
     const int u = tx * 8 + (lane & 7), v = ty * 8 + (lane >> 3);
     if (u < rq.cam.W && v < rq.cam.H) {
-      double o[3];
-      pixel_origin(rq.cam, u, v, o);
-      const double* d = rq.cam.e3;
+      double o[3], d[3];
+      pixel_ray(rq.cam, u, v, o, d);
       float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
       double tin;
       int64_t n;

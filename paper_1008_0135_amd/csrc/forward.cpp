@@ -63,7 +63,7 @@ void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params*
     vp.bv.push_back(v);
   }
   std::vector<int32_t> order;
-  depth_order(P, cam.e3, order);
+  depth_order(P, cam, order);
   for (int32_t b : order)
     if (slot[b] >= 0) vp.layers_order.push_back(slot[b]);
   vp.ntiles = tiles;
@@ -202,7 +202,7 @@ int validate_render(vr_ctx* ctx, const vr_volume* vol, const vr_view* views, int
   if (nviews < 1) return fail(VR_EINVAL, "nviews must be >= 1");
   VR_TRY(check_params(p));
   for (int32_t v = 0; v < nviews; v++) {
-    VR_TRY(check_view(&views[v]));
+    VR_TRY(check_view(&views[v], vol->n));
     if (views[v].W != views[0].W || views[v].H != views[0].H)
       return fail(VR_EINVAL, "all views of one call must share W and H");
   }

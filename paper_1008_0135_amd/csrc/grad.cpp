@@ -73,6 +73,7 @@ int ntiles_of(int32_t W, int32_t H, int32_t tw, int32_t th) { return ((W + tw - 
 bool plan_ring_view(const Camera& cam, const vr_params* p, int32_t M, const int64_t n[3], int layer_cap,
                     vr_state::View& rv) {
   if (p->tile != 0 && p->tile != 8) return false;
+  if (cam.persp) return false;  // the ring adjoint assumes parallel rays
   int32_t axis = 0, slot = 0, wpb = 4;
   if (!choose_ring(cam, 4096, M, 24, 12, 2, axis, slot, wpb)) return false;
   const double db = std::fabs(cam.e3[axis]);

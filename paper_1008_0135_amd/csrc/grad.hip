@@ -68,9 +68,8 @@ __global__ __launch_bounds__(256) void k_fwd_save(MarchArgs a, SaveArgs sa) {
   if (!tl.active) return;
   const DevBrick br = a.bricks[0];
   const int pix = tl.v * a.bv[0].w + tl.u;
-  double o[3];
-  pixel_origin(a.cam, tl.u, tl.v, o);
-  const double* d = a.cam.e3;
+  double o[3], d[3];
+  pixel_ray(a.cam, tl.u, tl.v, o, d);
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f;
   int used = 0;
   double tin;
@@ -166,9 +165,8 @@ __global__ __launch_bounds__(256) void k_bwd(MarchArgs a, BwdArgs ba) {
     const DevBrick br = a.bricks[0];
     const int pix = tl.v * a.bv[0].w + tl.u;
     const int used = ba.nused[pix];
-    double o[3];
-    pixel_origin(a.cam, tl.u, tl.v, o);
-    const double* d = a.cam.e3;
+    double o[3], d[3];
+    pixel_ray(a.cam, tl.u, tl.v, o, d);
     double tin;
     int64_t n;
     if (used > 0 && ray_lattice(o, d, a.hi, a.step, tin, n)) {

@@ -406,7 +406,7 @@ int bwd_ring_blocks(const MarchArgs& a, int wpb) {
 hipError_t launch_bwd_ring(const MarchArgs& a, const BwdArgs& ba, int wpb, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4) ||
-      ba.K < 1 || ba.smax < 1 || !ba.ckpt_j)
+      a.cam.persp != 0 || ba.K < 1 || ba.smax < 1 || !ba.ckpt_j)
     return hipErrorInvalidValue;
   const size_t lds = bwd_ring_lds_bytes(a, ba, wpb);
   if (lds > 160 * 1024) return hipErrorInvalidValue;

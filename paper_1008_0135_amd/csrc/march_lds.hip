@@ -355,6 +355,7 @@ __global__ __launch_bounds__(64) void k_march_lds(MarchArgs a) {
 
 hipError_t launch_march_lds(const MarchArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (a.cam.persp || a.mip) return hipErrorInvalidValue;  // parallel rays, emission-absorption only
   const int grid = ((a.ntiles + 7) / 8) * 8;
   // register pipeline depth: 16-byte chunks per lane that carry one slab's box
   const int ch = a.lds_budget <= 2048 ? 8 : (a.lds_budget <= 4096 ? 16 : 32);

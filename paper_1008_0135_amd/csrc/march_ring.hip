@@ -25,6 +25,15 @@
 // the current layer (two to three on typical views).  Four wavefronts share a
 // workgroup only to share the transfer-function table in LDS; after loading it
 // each wavefront runs on its own, with no workgroup barrier.
+//
+// Perspective views (PERSP): the tile's rays leave one eye, so their
+// directions are positive combinations of the four corner directions; when
+// the corner rays all move the same way along b, every ray of the tile meets
+// a plane b = P inside the range the corner rays span there, and the window
+// of layer V is the box of the four corner lines over [V - 1, V + 1] (its size
+// grows with depth: the bound is taken at the tile's first and last layer,
+// where the convex width is largest).  A tile whose corner rays disagree on
+// the direction along b samples from global memory.
 #include <cstring>
 
 #include "ring_common.h"
@@ -43,8 +52,9 @@ constexpr int kSlots = 3;
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
 // MIP: maximum intensity projection (no table, no skipping, no saving).
-template <bool ESS, bool SAVE, bool MIP>
+template <bool ESS, bool SAVE, bool MIP, bool PERSP>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
+  static_assert(!(PERSP && SAVE), "the checkpointing forward is orthographic");
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
   for (int i = threadIdx.x; i < a.M; i += blockDim.x) s_tf[i] = a.tf[i];
@@ -77,9 +87,15 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   const int u = bvw.x0 + min(lx, bvw.w - 1), v = bvw.y0 + min(ly, bvw.h - 1);
 
   // ---- per-lane ray setup (double precision, shared with every march)
-  const double* d = a.cam.e3;
-  double o[3];
-  pixel_origin(a.cam, u, v, o);
+  double o[3], dl[3];
+  const double* d;
+  if constexpr (PERSP) {
+    pixel_ray(a.cam, u, v, o, dl);
+    d = dl;
+  } else {
+    d = a.cam.e3;
+    pixel_origin(a.cam, u, v, o);
+  }
   int cnt = 0;
   float px = 0.f, py = 0.f, pz = 0.f;
   double tin;
@@ -104,7 +120,31 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   const int cloG = by ? br.clo[2] : br.clo[1], chiG = by ? br.chi[2] : br.chi[1];
   const int cloF = br.clo[0], chiF = br.chi[0];
   const double db = by ? d[1] : d[2], dg = by ? d[2] : d[1];
-  const bool up = db > 0.0;
+  // PERSP: corner rays of the tile (lane l holds corner l & 3): their lines
+  // f = Afc + P rfc, g = Agc + P rgc on the planes b = P bound the bundle
+  float Afc = 0.f, Agc = 0.f, rfc = 0.f, rgc = 0.f;
+  bool force_gather = false;
+  bool up;
+  if constexpr (PERSP) {
+    const int cx = bvw.x0 + tx * 8, cy = bvw.y0 + ty * 8;
+    const int ex = min(cx + 7, bvw.x0 + bvw.w - 1), ey = min(cy + 7, bvw.y0 + bvw.h - 1);
+    const int cc = lane & 3;
+    double oc[3], dc[3];
+    pixel_ray(a.cam, (cc & 1) ? ex : cx, (cc & 2) ? ey : cy, oc, dc);
+    const double dcb = by ? dc[1] : dc[2], dcg = by ? dc[2] : dc[1];
+    up = uni(dcb > 0.0 ? 1 : 0) != 0;
+    force_gather = __any(!(fabs(dcb) > 1e-6) || (dcb > 0.0) != up);
+    if (!force_gather) {
+      const double rfd = dc[0] / dcb, rgd = dcg / dcb;
+      const double ob = (by ? oc[1] : oc[2]) - (double)(by ? br.lo[1] : br.lo[2]);
+      Afc = (float)(oc[0] - (double)br.lo[0] - ob * rfd);
+      Agc = (float)((by ? oc[2] : oc[1]) - (double)(by ? br.lo[2] : br.lo[1]) - ob * rgd);
+      rfc = (float)rfd;
+      rgc = (float)rgd;
+    }
+  } else {
+    up = db > 0.0;
+  }
 
   // cell layers (along b) of the lane's first and last samples
   int c_first = up ? 0x7fffffff : -0x7fffffff, c_last = up ? -0x7fffffff : 0x7fffffff;
@@ -122,7 +162,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   float4* dst = a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
   const int pix = ly * bvw.w + lx;  // SAVE: pixel of the whole-volume image
-  if (up ? Lbeg > Lend : Lbeg < Lend) {
+  if (!force_gather && (up ? Lbeg > Lend : Lbeg < Lend)) {
     if (valid) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
     if (SAVE && valid) sa.nused[pix] = 0;
     return;
@@ -139,10 +179,10 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
 
   // ---- window geometry from the tile's corner rays (lanes 0..3)
   // A corner ray meets the plane b = P at f = Af + P rf, g = Ag + P rg.
-  const double rfd = d[0] / db, rgd = dg / db;
+  const double rfd = PERSP ? 0.0 : d[0] / db, rgd = PERSP ? 0.0 : dg / db;
   const float rf = (float)rfd, rg = (float)rgd;
-  float Af, Ag;
-  {
+  float Af = 0.f, Ag = 0.f;
+  if constexpr (!PERSP) {
     const int cx = bvw.x0 + tx * 8, cy = bvw.y0 + ty * 8;
     const int ex = min(cx + 7, bvw.x0 + bvw.w - 1), ey = min(cy + 7, bvw.y0 + bvw.h - 1);
     const int cc = lane & 3;
@@ -155,10 +195,48 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   const float Af_lo = unif(wmin4(Af)), Af_hi = unif(wmax4(Af));
   const float Ag_lo = unif(wmin4(Ag)), Ag_hi = unif(wmax4(Ag));
   const float arf = fabsf(rf), arg = fabsf(rg);
+  // PERSP: the four corner lines as uniform values
+  float cAf[4], crf[4], cAg[4], crg[4];
+  if constexpr (PERSP)
+    for (int c = 0; c < 4; ++c) {
+      cAf[c] = lanef(Afc, c);
+      crf[c] = lanef(rfc, c);
+      cAg[c] = lanef(Agc, c);
+      crg[c] = lanef(rgc, c);
+    }
+  // PERSP: range of the corner lines over the planes [P0, P1] (P0 <= P1)
+  auto crange = [&](const float* A, const float* r, float P0, float P1, float& lo, float& hi) {
+    lo = INFINITY;
+    hi = -INFINITY;
+    for (int c = 0; c < 4; ++c) {
+      const float x0 = fmaf(P0, r[c], A[c]), x1 = fmaf(P1, r[c], A[c]);
+      lo = fminf(lo, fminf(x0, x1));
+      hi = fmaxf(hi, fmaxf(x0, x1));
+    }
+  };
   // window extents: f_hi - f_lo + 1 <= floor(span + 0.1) + 3 for the 0.05 margins
-  const int NF = uni((int)floorf(Af_hi - Af_lo + 2.f * arf + 0.2f) + 3);
+  int NF, NG;
+  if constexpr (PERSP) {
+    if (force_gather) {
+      NF = 1 << 20;
+      NG = 1;
+    } else {
+      // the span over [V - 1, V + 1] is convex in V: largest at the first or
+      // last voxel layer the tile loads
+      const float Va = (float)(up ? Lbeg : Lbeg + 1), Vb = (float)(up ? Lend + 1 : Lend);
+      float l0, h0, l1, h1;
+      crange(cAf, crf, Va - 1.f, Va + 1.f, l0, h0);
+      crange(cAf, crf, Vb - 1.f, Vb + 1.f, l1, h1);
+      NF = uni((int)floorf(fmaxf(h0 - l0, h1 - l1) + 0.2f) + 3);
+      crange(cAg, crg, Va - 1.f, Va + 1.f, l0, h0);
+      crange(cAg, crg, Vb - 1.f, Vb + 1.f, l1, h1);
+      NG = uni((int)floorf(fmaxf(h0 - l0, h1 - l1) + 0.2f) + 3);
+    }
+  } else {
+    NF = uni((int)floorf(Af_hi - Af_lo + 2.f * arf + 0.2f) + 3);
+    NG = uni((int)floorf(Ag_hi - Ag_lo + 2.f * arg + 0.2f) + 3);
+  }
   const int pitch = (NF + 3) & ~3;
-  int NG = uni((int)floorf(Ag_hi - Ag_lo + 2.f * arg + 0.2f) + 3);
   NG = min(NG, chiG + 2 - cloG);
   const int ysl = br.sy, zsl = br.sz;
   const int sB = by ? ysl : zsl, sG = by ? zsl : ysl;
@@ -168,7 +246,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   int j = 0;
   bool done = cnt == 0;
 
-  if (pitch > chiF + 2 - cloF || pitch * NG > slot || pitch > 256 ||
+  if (force_gather || pitch > chiF + 2 - cloF || pitch * NG > slot || pitch > 256 ||
       ((int64_t)(64 / (pitch >> 2)) * sG + pitch) * 4 >= ((int64_t)1 << 32)) {
     // the window does not fit: read the corners from global memory
     int gnext = 0;  // SAVE: next group whose start state is to be stored
@@ -201,9 +279,18 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   // window of voxel layer V (brick-local): rows [g0, g0 + NG), columns [f0, f0 + pitch)
   auto window = [&](int V) {
     Window w;
-    const float Pf = (float)V * rf, Pg = (float)V * rg;
-    const int flo = max((int)floorf(Af_lo + Pf - arf - 0.05f), cloF);
-    const int glo = max((int)floorf(Ag_lo + Pg - arg - 0.05f), cloG);
+    int flo, glo;
+    if constexpr (PERSP) {
+      float lf, hf, lg, hg;
+      crange(cAf, crf, (float)(V - 1), (float)(V + 1), lf, hf);
+      crange(cAg, crg, (float)(V - 1), (float)(V + 1), lg, hg);
+      flo = max((int)floorf(lf - 0.05f), cloF);
+      glo = max((int)floorf(lg - 0.05f), cloG);
+    } else {
+      const float Pf = (float)V * rf, Pg = (float)V * rg;
+      flo = max((int)floorf(Af_lo + Pf - arf - 0.05f), cloF);
+      glo = max((int)floorf(Ag_lo + Pg - arg - 0.05f), cloG);
+    }
     w.f0 = uni(max(cloF, min(flo, chiF + 2 - pitch)));
     w.g0 = uni(max(cloG, min(glo, chiG + 2 - NG)));
     return w;
@@ -296,10 +383,23 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     // add nothing and leave T as it is), the lanes only move their cursors.
     auto step_clear = [&](int c, int c_end) {
       const int P0 = min(c, c_end), P1 = max(c, c_end) + 1;  // planes bounding the step
-      const float lo_f = fminf((float)P0 * rf, (float)P1 * rf), hi_f = fmaxf((float)P0 * rf, (float)P1 * rf);
-      const float lo_g = fminf((float)P0 * rg, (float)P1 * rg), hi_g = fmaxf((float)P0 * rg, (float)P1 * rg);
-      const int f0 = max((int)floorf(Af_lo + lo_f - 0.05f), cloF), f1 = min((int)floorf(Af_hi + hi_f + 0.05f), chiF);
-      const int g0 = max((int)floorf(Ag_lo + lo_g - 0.05f), cloG), g1 = min((int)floorf(Ag_hi + hi_g + 0.05f), chiG);
+      int f0, f1, g0, g1;
+      if constexpr (PERSP) {
+        float lf, hf, lg, hg;
+        crange(cAf, crf, (float)P0, (float)P1, lf, hf);
+        crange(cAg, crg, (float)P0, (float)P1, lg, hg);
+        f0 = max((int)floorf(lf - 0.05f), cloF);
+        f1 = min((int)floorf(hf + 0.05f), chiF);
+        g0 = max((int)floorf(lg - 0.05f), cloG);
+        g1 = min((int)floorf(hg + 0.05f), chiG);
+      } else {
+        const float lo_f = fminf((float)P0 * rf, (float)P1 * rf), hi_f = fmaxf((float)P0 * rf, (float)P1 * rf);
+        const float lo_g = fminf((float)P0 * rg, (float)P1 * rg), hi_g = fmaxf((float)P0 * rg, (float)P1 * rg);
+        f0 = max((int)floorf(Af_lo + lo_f - 0.05f), cloF);
+        f1 = min((int)floorf(Af_hi + hi_f + 0.05f), chiF);
+        g0 = max((int)floorf(Ag_lo + lo_g - 0.05f), cloG);
+        g1 = min((int)floorf(Ag_hi + hi_g + 0.05f), chiG);
+      }
       const int mc = a.mc;
       const int mf0 = (f0 + br.lo[0]) / mc, mf1 = (max(f1, f0) + br.lo[0]) / mc;
       const int mg0 = (g0 + loG) / mc, mg1 = (max(g1, g0) + loG) / mc;
@@ -403,13 +503,17 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   // registers the plain march does not need
   SaveArgs none;
   std::memset(&none, 0, sizeof none);
-  if (a.mip) {
-    if (a.mc > 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_march_ring<false, false, true>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
-  } else if (a.mc > 0) {
-    hipLaunchKernelGGL((k_march_ring<true, false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+  const dim3 g(grid), b(64 * wpb);
+  const size_t lds = ring_lds_bytes(a, wpb);
+  if (a.mip && a.mc > 0) return hipErrorInvalidValue;
+  if (a.cam.persp) {
+    if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true>), g, b, lds, s, a, none);
+    else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, true>), g, b, lds, s, a, none);
+    else hipLaunchKernelGGL((k_march_ring<false, false, false, true>), g, b, lds, s, a, none);
   } else {
-    hipLaunchKernelGGL((k_march_ring<false, false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, none);
+    if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, false>), g, b, lds, s, a, none);
+    else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, false>), g, b, lds, s, a, none);
+    else hipLaunchKernelGGL((k_march_ring<false, false, false, false>), g, b, lds, s, a, none);
   }
   return hipGetLastError();
 }
@@ -417,11 +521,11 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
 hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wpb, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4) ||
-      a.mc != 0 || a.mip != 0 || sa.K < 1 || !sa.ckpt_j)
+      a.mc != 0 || a.mip != 0 || a.cam.persp != 0 || sa.K < 1 || !sa.ckpt_j)
     return hipErrorInvalidValue;
   const int groups = (a.ntiles + wpb - 1) / wpb;
   const int grid = ((groups + 7) / 8) * 8;
-  hipLaunchKernelGGL((k_march_ring<false, true, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, sa);
+  hipLaunchKernelGGL((k_march_ring<false, true, false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, sa);
   return hipGetLastError();
 }
 

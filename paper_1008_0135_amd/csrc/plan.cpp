@@ -118,9 +118,17 @@ Rect brick_rect(const Camera& cam, const Box& b) {
   const double k = (double)cam.W / cam.S;  // pixels per voxel
   for (int c = 0; c < 8; c++) {
     double p[3];
-    for (int i = 0; i < 3; i++) p[i] = (double)(((c >> i) & 1) ? b.hi[i] : b.lo[i]) - cam.c[i];
-    const double x = p[0] * cam.e1[0] + p[1] * cam.e1[1] + p[2] * cam.e1[2];
-    const double y = p[0] * cam.e2[0] + p[1] * cam.e2[1] + p[2] * cam.e2[2];
+    for (int i = 0; i < 3; i++)
+      p[i] = (double)(((c >> i) & 1) ? b.hi[i] : b.lo[i]) - (cam.persp ? cam.eye[i] : cam.c[i]);
+    double x = p[0] * cam.e1[0] + p[1] * cam.e1[1] + p[2] * cam.e1[2];
+    double y = p[0] * cam.e2[0] + p[1] * cam.e2[1] + p[2] * cam.e2[2];
+    if (cam.persp) {
+      // pinhole projection onto the pixel plane at distance D (every corner
+      // lies in front of the eye: D exceeds half the box diagonal)
+      const double z = p[0] * cam.e3[0] + p[1] * cam.e3[1] + p[2] * cam.e3[2];
+      x *= cam.D / z;
+      y *= cam.D / z;
+    }
     const double u = x * k + 0.5 * cam.W - 0.5, v = y * k + 0.5 * cam.H - 0.5;
     umin = std::min(umin, u);
     umax = std::max(umax, u);
@@ -138,23 +146,55 @@ Rect brick_rect(const Camera& cam, const Box& b) {
   return r;
 }
 
-static void kd_order(const Partition& P, int32_t node, const double d[3], std::vector<int32_t>& order) {
+// Near child first: for parallel rays the side the rays come from; for rays
+// from an eye the side that holds the eye (a ray crosses a plane at most once,
+// leaving the eye's side).
+static void kd_order(const Partition& P, int32_t node, const Camera& cam, std::vector<int32_t>& order) {
   const KdNode& nd = P.nodes[node];
   if (nd.leaf >= 0) {
     order.push_back(nd.leaf);
     return;
   }
-  const bool low_first = d[nd.axis] >= 0.0;
-  kd_order(P, low_first ? nd.left : nd.right, d, order);
-  kd_order(P, low_first ? nd.right : nd.left, d, order);
+  const bool low_first = cam.persp ? cam.eye[nd.axis] < (double)nd.plane : cam.e3[nd.axis] >= 0.0;
+  kd_order(P, low_first ? nd.left : nd.right, cam, order);
+  kd_order(P, low_first ? nd.right : nd.left, cam, order);
 }
 
-void depth_order(const Partition& p, const double d[3], std::vector<int32_t>& order) {
+void depth_order(const Partition& p, const Camera& cam, std::vector<int32_t>& order) {
   order.clear();
   if (p.mode == VR_BRICK_LONGEST_AXIS) {
-    kd_order(p, 0, d, order);
+    kd_order(p, 0, cam, order);
     return;
   }
+  if (cam.persp) {
+    // rays from an eye move away from it along every axis, so a ray's slab
+    // distance |k_i - e_i| from the eye's slab e_i never decreases; sorting
+    // by the distances along axes 3, 2, 1 (lexicographically) puts every
+    // brick a ray meets after the ones it met before
+    int32_t e[3];
+    for (int i = 0; i < 3; i++) {
+      const double q = cam.eye[i];
+      const int32_t c = p.gcount[i];
+      if (q < 0.0) e[i] = -1;
+      else if (q >= (double)p.boxes.back().hi[i]) e[i] = c;
+      else e[i] = std::min<int32_t>(c - 1, (int32_t)std::floor(q / (double)p.gsize[i]));
+    }
+    const int32_t* c = p.gcount;
+    std::vector<std::pair<int64_t, int32_t>> key;
+    key.reserve(p.boxes.size());
+    const int64_t m1 = (int64_t)c[0] + 2, m2 = (int64_t)c[1] + 2;
+    for (int32_t k3 = 0; k3 < c[2]; k3++)
+      for (int32_t k2 = 0; k2 < c[1]; k2++)
+        for (int32_t k1 = 0; k1 < c[0]; k1++) {
+          const int64_t d1 = std::abs(k1 - e[0]), d2 = std::abs(k2 - e[1]), d3 = std::abs(k3 - e[2]);
+          key.emplace_back((d3 * m2 + d2) * m1 + d1, (k3 * c[1] + k2) * c[0] + k1);
+        }
+    std::sort(key.begin(), key.end());
+    order.reserve(key.size());
+    for (const auto& kv : key) order.push_back(kv.second);
+    return;
+  }
+  const double* d = cam.e3;
   // grid: visit slabs along axis 3, then 2, then 1, each in the ray's direction;
   // a ray crosses the grid monotonically along every axis, so this lexicographic
   // order puts every brick a ray meets after the ones it met before.
@@ -188,6 +228,7 @@ bool brick_transparent(float bmin, float bmax, const float* tf, int32_t M, doubl
 }
 
 bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int32_t& axis, int32_t& T) {
+  if (cam.persp) return false;  // the slab march assumes parallel rays
   const double p = cam.S / (double)cam.W;  // pixel pitch in voxels
   double best = INFINITY;
   bool found = false;
@@ -240,18 +281,47 @@ int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* wa
 bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves,
                  int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb) {
   const double p = cam.S / (double)cam.W;
+  // ray directions to size the window for: the view direction (parallel
+  // rays), or the rays of the image's corners and centre (perspective; a
+  // tile's footprint also grows with depth, by at most (D + r) / D for the
+  // box's circumradius r)
+  double dirs[5][3];
+  int ndir = 1;
+  double scale = 1.0;
+  for (int i = 0; i < 3; i++) dirs[0][i] = cam.e3[i];
+  if (cam.persp) {
+    const int us[5] = {cam.W / 2, 0, cam.W - 1, 0, cam.W - 1}, vs[5] = {cam.H / 2, 0, 0, cam.H - 1, cam.H - 1};
+    for (int k = 0; k < 5; k++) {
+      double o[3];
+      pixel_ray(cam, us[k], vs[k], o, dirs[k]);
+    }
+    ndir = 5;
+    double r2 = 0.0;
+    for (int i = 0; i < 3; i++) r2 += cam.c[i] * cam.c[i];
+    scale = (cam.D + std::sqrt(r2)) / cam.D;
+  }
   double best = INFINITY;
   bool found = false;
   for (int b = 1; b <= 2; b++) {
     const int g = 3 - b;
-    const double db = cam.e3[b];
+    const double db = dirs[0][b];
     if (std::fabs(db) < 1e-3) continue;
-    const double rf = cam.e3[0] / db, rg = cam.e3[g] / db;
-    const double Wf = p * 7.0 * (std::fabs(cam.e1[0] - cam.e1[b] * rf) + std::fabs(cam.e2[0] - cam.e2[b] * rf));
-    const double Wg = p * 7.0 * (std::fabs(cam.e1[g] - cam.e1[b] * rg) + std::fabs(cam.e2[g] - cam.e2[b] * rg));
-    // the kernel's bound is floor(span + 0.2) + 3 per axis; one more for rounding
-    const double nf = std::floor(Wf + 2.0 * std::fabs(rf) + 0.2) + 4.0;
-    const double ng = std::floor(Wg + 2.0 * std::fabs(rg) + 0.2) + 4.0;
+    double nf = 0.0, ng = 0.0;
+    bool ok = true;
+    for (int k = 0; k < ndir && ok; k++) {
+      const double* d = dirs[k];
+      if (std::fabs(d[b]) < 1e-3 || (d[b] > 0.0) != (db > 0.0)) {
+        ok = false;
+        break;
+      }
+      const double rf = d[0] / d[b], rg = d[g] / d[b];
+      const double Wf = scale * p * 7.0 * (std::fabs(cam.e1[0] - cam.e1[b] * rf) + std::fabs(cam.e2[0] - cam.e2[b] * rf));
+      const double Wg = scale * p * 7.0 * (std::fabs(cam.e1[g] - cam.e1[b] * rg) + std::fabs(cam.e2[g] - cam.e2[b] * rg));
+      // the kernel's bound is floor(span + 0.2) + 3 per axis; one more for rounding
+      nf = std::max(nf, std::floor(Wf + 2.0 * std::fabs(rf) + 0.2) + 4.0);
+      ng = std::max(ng, std::floor(Wg + 2.0 * std::fabs(rg) + 0.2) + 4.0);
+    }
+    if (!ok) continue;
     const double pitch = 4.0 * std::ceil(nf / 4.0);
     const double size = pitch * ng;
     if (size > (double)cap || pitch > 256.0) continue;
@@ -277,10 +347,10 @@ int64_t count_samples(const Camera& cam, const int64_t n[3], double step) {
   int64_t total = 0;
   for (int v = 0; v < cam.H; v++)
     for (int u = 0; u < cam.W; u++) {
-      double o[3], tin;
+      double o[3], d[3], tin;
       int64_t k;
-      pixel_origin(cam, u, v, o);
-      if (ray_lattice(o, cam.e3, hi, step, tin, k)) total += k;
+      pixel_ray(cam, u, v, o, d);
+      if (ray_lattice(o, d, hi, step, tin, k)) total += k;
     }
   return total;
 }

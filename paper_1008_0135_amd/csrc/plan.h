@@ -53,7 +53,7 @@ void stored_box(const Box& b, const int64_t n[3], int64_t slo[3], int64_t shi[3]
 Rect brick_rect(const Camera& cam, const Box& b);
 
 // Front-to-back order of all boxes for ray direction d.
-void depth_order(const Partition& p, const double d[3], std::vector<int32_t>& order);
+void depth_order(const Partition& p, const Camera& cam, std::vector<int32_t>& order);
 
 // True when every sample a brick with stored range [bmin, bmax] can produce
 // has zero opacity: all table alphas in [floor(u(bmin)) - 1, ceil(u(bmax)) + 1]

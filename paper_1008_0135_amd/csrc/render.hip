@@ -70,9 +70,8 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   if (lx >= bvw.w || ly >= bvw.h) return;
   const int u = bvw.x0 + lx, v = bvw.y0 + ly;
 
-  double o[3];
-  pixel_origin(a.cam, u, v, o);
-  const double* d = a.cam.e3;
+  double o[3], d[3];
+  pixel_ray(a.cam, u, v, o, d);
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f, mx = 0.f;
   double tin;
   int64_t n;

@@ -37,6 +37,10 @@ __device__ __forceinline__ gfloat* unip(gfloat* p) {
 __device__ __forceinline__ float unif(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
+// value of v in lane l (uniform)
+__device__ __forceinline__ float lanef(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 
 // Wait until every global->LDS load this wavefront issued has landed (the
 // memory clobber keeps LDS reads from moving above the wait).

@@ -138,7 +138,7 @@ int ensure_device(void** p, size_t* cap, size_t need);
 int upload_tables(vr_ctx* ctx, hipStream_t s, const void* data, size_t bytes, void** dev);
 int reduce_minmax(vr_ctx* ctx, const float* x, int64_t n, hipStream_t s, float out3[3]);
 int volume_range(vr_volume* vol, hipStream_t s);
-int check_view(const vr_view* v);
+int check_view(const vr_view* v, const int64_t n[3]);
 int check_params(const vr_params* p);
 int resolve_window(vr_ctx* ctx, vr_volume* vol, hipStream_t s, double& vmin, double& vmax);
 void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, double vmin, double vmax,

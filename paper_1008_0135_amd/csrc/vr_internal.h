@@ -19,11 +19,14 @@ namespace vr {
 struct Camera {
   double c[3];          // box centre
   double e1[3], e2[3];  // image axes
-  double e3[3];         // ray direction
+  double e3[3];         // viewing direction (the ray direction when orthographic)
   double S;             // image width in voxels
   double Sy;            // image height in voxels = S*H/W
   int32_t W, H;
-  int32_t pad[2];
+  int32_t persp;        // 1: perspective from eye[], 0: orthographic
+  int32_t pad;
+  double D;             // eye distance from c (perspective)
+  double eye[3];        // c - D e3 (perspective)
 };
 
 __host__ __device__ inline void make_camera(const vr_view& v, const int64_t n[3], Camera& cam) {
@@ -39,15 +42,39 @@ __host__ __device__ inline void make_camera(const vr_view& v, const int64_t n[3]
   cam.Sy = cam.S * (double)v.H / (double)v.W;
   cam.W = v.W;
   cam.H = v.H;
-  cam.pad[0] = cam.pad[1] = 0;
+  cam.persp = v.eye_dist > 0.0 ? 1 : 0;
+  cam.pad = 0;
+  cam.D = cam.persp ? v.eye_dist : 0.0;
+  for (int i = 0; i < 3; i++) cam.eye[i] = cam.c[i] - cam.D * cam.e3[i];
 }
 
-// Ray origin of pixel (u, v); the direction is cam.e3.
+// Ray origin of pixel (u, v) of an orthographic camera; the direction is cam.e3.
 __host__ __device__ inline void pixel_origin(const Camera& cam, int u, int v, double o[3]) {
 #pragma clang fp contract(off)
   double x = (((double)u + 0.5) / (double)cam.W - 0.5) * cam.S;
   double y = (((double)v + 0.5) / (double)cam.H - 0.5) * cam.S * (double)cam.H / (double)cam.W;
   for (int i = 0; i < 3; i++) o[i] = cam.c[i] + x * cam.e1[i] + y * cam.e2[i] - cam.S * cam.e3[i];
+}
+
+// Ray of pixel (u, v), either projection: origin o and unit direction d.
+// Perspective: from the eye through the pixel's point on the plane through
+// the box centre normal to e3 (the pixel grid of the orthographic camera).
+__host__ __device__ inline void pixel_ray(const Camera& cam, int u, int v, double o[3], double d[3]) {
+#pragma clang fp contract(off)
+  if (!cam.persp) {
+    pixel_origin(cam, u, v, o);
+    for (int i = 0; i < 3; i++) d[i] = cam.e3[i];
+    return;
+  }
+  double x = (((double)u + 0.5) / (double)cam.W - 0.5) * cam.S;
+  double y = (((double)v + 0.5) / (double)cam.H - 0.5) * cam.S * (double)cam.H / (double)cam.W;
+  double w[3];
+  for (int i = 0; i < 3; i++) {
+    o[i] = cam.eye[i];
+    w[i] = x * cam.e1[i] + y * cam.e2[i] + cam.D * cam.e3[i];
+  }
+  const double len = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  for (int i = 0; i < 3; i++) d[i] = w[i] / len;
 }
 
 // Whole-volume ray/box test (slab method against the closed box [0, hi]) and

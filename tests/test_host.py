@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(vr.exported_symbols())
-    assert vr.vr_version() == 1
+    assert vr.vr_version() == 2
 
 
 def test_params_default():
@@ -110,7 +110,7 @@ def test_stored_ranges_are_ghosted():
         assert d.shi[i] == min(63, d.hi[i] + 1)
 
 
-def _rays(dims, R, W, H, extent=0.0):
+def _rays(dims, R, W, H, extent=0.0, eye_dist=0.0):
     n = np.array(dims, np.float64)
     c = (n - 1) / 2
     S = extent if extent > 0 else math.sqrt(((n - 1) ** 2).sum())
@@ -119,6 +119,11 @@ def _rays(dims, R, W, H, extent=0.0):
     x = ((u + 0.5) / W - 0.5) * S
     y = ((v + 0.5) / H - 0.5) * S * H / W
     R = np.asarray(R)
+    if eye_dist > 0:
+        w = x[None, :, None] * R[0] + y[:, None, None] * R[1] + eye_dist * R[2]
+        d = w / np.linalg.norm(w, axis=-1, keepdims=True)
+        o = np.broadcast_to(c - eye_dist * R[2], d.shape)
+        return o, d
     o = c[None, None] + x[None, :, None] * R[0] + y[:, None, None] * R[1] - S * R[2]
     return o, R[2]
 
@@ -132,16 +137,20 @@ def _slab(o, d, lo, hi):
     return tn.max(-1), tf.min(-1)
 
 
-@pytest.mark.parametrize("kind", ["grid", "kd"])
-def test_rectangles_conservative_and_order_consistent(kind):
+@pytest.mark.parametrize("kind,eye", [("grid", 0.0), ("kd", 0.0), ("grid", 90.0), ("kd", 90.0), ("grid", 260.0),
+                                      ("kd", 260.0)])
+def test_rectangles_conservative_and_order_consistent(kind, eye):
+    """Rectangles hold every pixel whose ray meets the brick; the order sorts
+    every ray's bricks by entry (parallel rays, and rays from an eye at 90 or
+    260 voxels from the centre of a box of half-diagonal 86)."""
     dims = (96, 80, 120)
     spec = vr.grid_spec((32, 32, 48)) if kind == "grid" else vr.kd_spec(6)
     descs = vr.vr_partition(dims, spec)
     for R in synth.random_views(4, 41):
         W, H = 64, 48
-        view = vr.make_view(R, W, H)
+        view = vr.make_view(R, W, H, eye_dist=eye)
         rects, order = vr.vr_plan_view(dims, spec, view)
-        o, d = _rays(dims, R, W, H)
+        o, d = _rays(dims, R, W, H, eye_dist=eye)
         pos = {b: i for i, b in enumerate(order)}
         entries = []
         for b, dsc in enumerate(descs):
@@ -154,8 +163,10 @@ def test_rectangles_conservative_and_order_consistent(kind):
             if len(xs):
                 assert w > 0 and h > 0
                 assert xs.min() >= x0 and xs.max() < x0 + w and ys.min() >= y0 and ys.max() < y0 + h
-                # not wildly larger than needed
-                assert x0 >= xs.min() - 3 and x0 + w <= xs.max() + 4
+                # not wildly larger than needed (where the image does not cut the
+                # projection: the box of a cut hull can exceed the visible part)
+                if x0 > 0 and y0 > 0 and x0 + w < W and y0 + h < H:
+                    assert x0 >= xs.min() - 3 and x0 + w <= xs.max() + 4
             entries.append(np.where(hit, tn, np.inf))
         E = np.stack(entries)  # [nb][H][W]
         # any two bricks a ray meets with distinct entries are ordered by entry
@@ -173,7 +184,17 @@ def test_count_samples_matches_oracle(orc):
     vol = np.zeros((48, 36, 40), np.float32)
     tf = synth.tf_ramp(8)
     for R in synth.random_views(3, 42) + [np.eye(3)]:
-        view = vr.make_view(R, 64, 56)
-        n = vr.vr_count_samples(dims, view, 0.5)
-        res = orc.render(vol, tf, [R], 64, 56, 0.0, 1.0, tau=2.0)
-        assert n == res["nsamples"]
+        for eye in (0.0, 40.0, 150.0):
+            view = vr.make_view(R, 64, 56, eye_dist=eye)
+            n = vr.vr_count_samples(dims, view, 0.5)
+            res = orc.render(vol, tf, [R], 64, 56, 0.0, 1.0, tau=2.0, eye_dist=eye)
+            assert n == res["nsamples"]
+
+
+def test_eye_distance_validation():
+    dims = (40, 36, 48)  # half diagonal 35.19
+    for bad in (-1.0, 20.0, 35.1, float("nan")):
+        with pytest.raises(vr.VRError) as e:
+            vr.vr_count_samples(dims, vr.make_view(np.eye(3), 16, 16, eye_dist=bad), 0.5)
+        assert e.value.code == vr.VR_EINVAL
+    vr.vr_count_samples(dims, vr.make_view(np.eye(3), 16, 16, eye_dist=35.3), 0.5)
