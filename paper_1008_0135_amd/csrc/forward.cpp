@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -160,9 +161,28 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     bool lds = false, ring = false;
     int ring_wpb = 4;
     a.lds_budget = budget;
-    if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8)
-      ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
-                         a.ring_slot, ring_wpb);
+    if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8) {
+      if (cams[v].persp) {
+        std::vector<TileRegion> regs;
+        for (const DevBrickView& b : vp.bv) {
+          TileRegion r;
+          for (int i = 0; i < 3; i++) {
+            r.lo[i] = bricked ? vol->part.boxes[b.brick].lo[i] : 0;
+            r.hi[i] = bricked ? vol->part.boxes[b.brick].hi[i] : vol->n[i] - 1;
+          }
+          r.x0 = b.x0;
+          r.y0 = b.y0;
+          r.w = b.w;
+          r.h = b.h;
+          regs.push_back(r);
+        }
+        a.slab_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
+        ring = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, ring_wpb);
+      } else {
+        ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
+                           a.ring_slot, ring_wpb);
+      }
+    }
     if (!ring && !extras && mode != 1 && !a.mip) {  // (the slab march has no projection mode)
       lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
       // rays nearly parallel to axis 1 need a wider slab box: retry with twice the budget

@@ -113,27 +113,80 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   const float sx = (float)(a.step * d[0]), sy = (float)(a.step * d[1]), sz = (float)(a.step * d[2]);
 
+  // range of four lines x = A[c] + P r[c] over the planes [P0, P1] (P0 <= P1)
+  auto crange = [](const float* A, const float* r, float P0, float P1, float& lo, float& hi) {
+    lo = INFINITY;
+    hi = -INFINITY;
+    for (int c = 0; c < 4; ++c) {
+      const float x0 = fmaf(P0, r[c], A[c]), x1 = fmaf(P1, r[c], A[c]);
+      lo = fminf(lo, fminf(x0, x1));
+      hi = fmaxf(hi, fmaxf(x0, x1));
+    }
+  };
+
   // ---- frame: b = slab axis (axis 2 or 3), g = the other of axes 2/3, f = axis 1
-  const bool by = a.slab_axis == 1;
+  // PERSP: the corner rays of the tile (lane l holds corner l & 3) pick the
+  // axis per tile: of the axes along which all four move the same way, the one
+  // whose window over the brick's layers is smaller (rays from an eye turn
+  // across the image, so no one axis suits every tile)
+  bool by = a.slab_axis == 1;
+  bool force_gather = false;
+  double oc[3] = {0.0, 0.0, 0.0}, dc[3] = {0.0, 0.0, 1.0};
+  if constexpr (PERSP) {
+    const int cx = bvw.x0 + tx * 8, cy = bvw.y0 + ty * 8;
+    const int ex = min(cx + 7, bvw.x0 + bvw.w - 1), ey = min(cy + 7, bvw.y0 + bvw.h - 1);
+    const int cc = lane & 3;
+    pixel_ray(a.cam, (cc & 1) ? ex : cx, (cc & 2) ? ey : cy, oc, dc);
+    int pick = 0;
+    int best = 0x7fffffff;
+    for (int bb = 1; bb <= 2; ++bb) {
+      const double dcb = dc[bb];
+      const bool upb = uni(dcb > 0.0 ? 1 : 0) != 0;
+      if (wany(!(fabs(dcb) > 1e-6) || (dcb > 0.0) != upb)) continue;
+      const int gg = 3 - bb;
+      const double rfd = dc[0] / dcb, rgd = dc[gg] / dcb;
+      const double ob = oc[bb] - (double)br.lo[bb];
+      const float A_f = (float)(oc[0] - (double)br.lo[0] - ob * rfd);
+      const float A_g = (float)(oc[gg] - (double)br.lo[gg] - ob * rgd);
+      float qA[4], qr[4], qB[4], qs[4];
+      for (int c = 0; c < 4; ++c) {
+        qA[c] = lanef(A_f, c);
+        qr[c] = lanef((float)rfd, c);
+        qB[c] = lanef(A_g, c);
+        qs[c] = lanef((float)rgd, c);
+      }
+      const float Va = (float)br.clo[bb], Vb = (float)(br.chi[bb] + 1);
+      float l0, h0, l1, h1;
+      crange(qA, qr, Va - 1.f, Va + 1.f, l0, h0);
+      crange(qA, qr, Vb - 1.f, Vb + 1.f, l1, h1);
+      const float wf = fmaxf(h0 - l0, h1 - l1);
+      crange(qB, qs, Va - 1.f, Va + 1.f, l0, h0);
+      crange(qB, qs, Vb - 1.f, Vb + 1.f, l1, h1);
+      const float wg = fmaxf(h0 - l0, h1 - l1);
+      if (!(wf < 4096.f && wg < 4096.f)) continue;
+      const int nf = (((int)floorf(wf + 0.2f) + 3) + 3) & ~3;
+      const int ng = min((int)floorf(wg + 0.2f) + 3, br.chi[gg] + 2 - br.clo[gg]);
+      const int size = uni(nf * ng);
+      if (size < best) {
+        best = size;
+        pick = bb;
+      }
+    }
+    if (pick == 0) force_gather = true;
+    else by = uni(pick) == 1;
+  }
   const float pb = by ? py : pz, sb = by ? sy : sz;
   const int cloB = by ? br.clo[1] : br.clo[2], chiB = by ? br.chi[1] : br.chi[2];
   const int cloG = by ? br.clo[2] : br.clo[1], chiG = by ? br.chi[2] : br.chi[1];
   const int cloF = br.clo[0], chiF = br.chi[0];
   const double db = by ? d[1] : d[2], dg = by ? d[2] : d[1];
-  // PERSP: corner rays of the tile (lane l holds corner l & 3): their lines
-  // f = Afc + P rfc, g = Agc + P rgc on the planes b = P bound the bundle
+  // PERSP: the corner lines f = Afc + P rfc, g = Agc + P rgc on the planes
+  // b = P bound the bundle
   float Afc = 0.f, Agc = 0.f, rfc = 0.f, rgc = 0.f;
-  bool force_gather = false;
   bool up;
   if constexpr (PERSP) {
-    const int cx = bvw.x0 + tx * 8, cy = bvw.y0 + ty * 8;
-    const int ex = min(cx + 7, bvw.x0 + bvw.w - 1), ey = min(cy + 7, bvw.y0 + bvw.h - 1);
-    const int cc = lane & 3;
-    double oc[3], dc[3];
-    pixel_ray(a.cam, (cc & 1) ? ex : cx, (cc & 2) ? ey : cy, oc, dc);
     const double dcb = by ? dc[1] : dc[2], dcg = by ? dc[2] : dc[1];
     up = uni(dcb > 0.0 ? 1 : 0) != 0;
-    force_gather = __any(!(fabs(dcb) > 1e-6) || (dcb > 0.0) != up);
     if (!force_gather) {
       const double rfd = dc[0] / dcb, rgd = dcg / dcb;
       const double ob = (by ? oc[1] : oc[2]) - (double)(by ? br.lo[1] : br.lo[2]);
@@ -204,16 +257,6 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
       cAg[c] = lanef(Agc, c);
       crg[c] = lanef(rgc, c);
     }
-  // PERSP: range of the corner lines over the planes [P0, P1] (P0 <= P1)
-  auto crange = [&](const float* A, const float* r, float P0, float P1, float& lo, float& hi) {
-    lo = INFINITY;
-    hi = -INFINITY;
-    for (int c = 0; c < 4; ++c) {
-      const float x0 = fmaf(P0, r[c], A[c]), x1 = fmaf(P1, r[c], A[c]);
-      lo = fminf(lo, fminf(x0, x1));
-      hi = fmaxf(hi, fmaxf(x0, x1));
-    }
-  };
   // window extents: f_hi - f_lo + 1 <= floor(span + 0.1) + 3 for the 0.05 margins
   int NF, NG;
   if constexpr (PERSP) {
@@ -311,7 +354,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     gfloat* gb = gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0);
     const unsigned l0 = uni(lds_addr(sdst));
     for (int k = 0; k < nload; ++k)
-      if (lane_on && k * R + rl < NG) lds_dma16(unip(gb + k * gstep), voff, l0 + (unsigned)k * lstep);
+      if (lane_on && k * R + rl < NG) lds_dma16(unip(gb + k * gstep), voff, (unsigned)uni((int)(l0 + (unsigned)k * lstep)));
   };
 
   // voxel layers in marching order: V_k = Lbeg + k (up) or Lbeg + 1 - k (down);

@@ -342,6 +342,85 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
   return found;
 }
 
+// Window floats of the perspective ring march for the 8 x 8 tile with corner
+// pixels (cx, cy) .. (ex, ey) over box r, on the better of axes 2 and 3 (the
+// kernel's choice, bounded over the box's layers); infinity when neither suits.
+static double persp_tile_window(const Camera& cam, const TileRegion& r, int cx, int cy, int ex, int ey) {
+  double oc[3], dc[4][3];
+  for (int k = 0; k < 4; k++) pixel_ray(cam, (k & 1) ? ex : cx, (k & 2) ? ey : cy, oc, dc[k]);
+  double best = INFINITY;
+  for (int b = 1; b <= 2; b++) {
+    const int g = 3 - b;
+    bool ok = true;
+    for (int k = 0; k < 4 && ok; k++)
+      ok = std::fabs(dc[k][b]) > 1e-6 && (dc[k][b] > 0.0) == (dc[0][b] > 0.0);
+    if (!ok) continue;
+    const double Va = (double)r.lo[b] - 1.0, Vb = (double)r.hi[b] + 1.0;
+    double wf = 0.0, wg = 0.0;
+    for (double V : {Va, Vb}) {
+      double lf = INFINITY, hf = -INFINITY, lg = INFINITY, hg = -INFINITY;
+      for (int k = 0; k < 4; k++) {
+        const double rf = dc[k][0] / dc[k][b], rg = dc[k][g] / dc[k][b];
+        for (double P : {V - 1.0, V + 1.0}) {
+          const double f = oc[0] + (P - oc[b]) * rf, q = oc[g] + (P - oc[b]) * rg;
+          lf = std::min(lf, f);
+          hf = std::max(hf, f);
+          lg = std::min(lg, q);
+          hg = std::max(hg, q);
+        }
+      }
+      wf = std::max(wf, hf - lf);
+      wg = std::max(wg, hg - lg);
+    }
+    if (!(wf < 4096.0 && wg < 4096.0)) continue;
+    const double pitch = 4.0 * std::ceil((std::floor(wf + 0.2) + 3.0) / 4.0);
+    const double ng = std::min(std::floor(wg + 0.2) + 3.0, (double)(r.hi[g] - r.lo[g]) + 4.0);
+    best = std::min(best, pitch * ng);
+  }
+  return best;
+}
+
+bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
+                       int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb) {
+  std::vector<std::pair<double, double>> est;  // (window of the region's worst sampled tile, tiles)
+  double total = 0.0;
+  for (const TileRegion& r : regs) {
+    if (r.w <= 0 || r.h <= 0) continue;
+    const int ntx = (r.w + 7) / 8, nty = (r.h + 7) / 8;
+    const int sx[5] = {0, ntx - 1, 0, ntx - 1, ntx / 2}, sy[5] = {0, 0, nty - 1, nty - 1, nty / 2};
+    double worst = 0.0;
+    for (int k = 0; k < 5; k++) {
+      const int cx = r.x0 + 8 * sx[k], cy = r.y0 + 8 * sy[k];
+      const int ex = std::min(cx + 7, r.x0 + r.w - 1), ey = std::min(cy + 7, r.y0 + r.h - 1);
+      worst = std::max(worst, persp_tile_window(cam, r, cx, cy, ex, ey));
+    }
+    est.emplace_back(worst, (double)ntx * nty);
+    total += (double)ntx * nty;
+  }
+  if (est.empty()) return false;
+  std::sort(est.begin(), est.end());
+  double acc = 0.0, need = INFINITY;
+  for (const auto& e : est) {
+    acc += e.second;
+    if (acc >= 0.95 * total) {
+      need = e.first;
+      break;
+    }
+  }
+  if (!(need <= (double)cap)) {
+    // windows past the cap read global memory; worthwhile only for a minority
+    double fit = 0.0;
+    for (const auto& e : est)
+      if (e.first <= (double)cap) fit += e.second;
+    if (fit < 0.5 * total) return false;
+    need = (double)cap;
+  }
+  slot = (int32_t)(4.0 * std::ceil(need / 4.0));
+  int32_t waves = 0;
+  wpb = ring_waves_per_block(slot, M, max_waves, &waves);
+  return waves >= min_waves;
+}
+
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step) {
   const double hi[3] = {(double)(n[0] - 1), (double)(n[1] - 1), (double)(n[2] - 1)};
   int64_t total = 0;

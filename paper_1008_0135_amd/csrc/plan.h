@@ -85,6 +85,18 @@ int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* wa
 bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves,
                  int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb);
 
+// Perspective ring march: the window of a tile depends on its rays' directions
+// and depth, and the kernel picks the slab axis per tile.  From a few sample
+// tiles of every rendered region (box + pixel rectangle) the host sizes the
+// slot to hold the windows of about 95 % of the tiles (the rest read global
+// memory).  False when too few tiles would fit.
+struct TileRegion {
+  int64_t lo[3], hi[3];
+  int32_t x0, y0, w, h;
+};
+bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
+                       int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb);
+
 // Sum over pixels of the whole-volume lattice count (no ERT, no skipping).
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step);
 

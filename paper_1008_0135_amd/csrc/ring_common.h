@@ -37,6 +37,8 @@ __device__ __forceinline__ gfloat* unip(gfloat* p) {
 __device__ __forceinline__ float unif(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
+// wave vote known to the compiler as uniform
+__device__ __forceinline__ bool wany(bool p) { return uni(__any(p) ? 1 : 0) != 0; }
 // value of v in lane l (uniform)
 __device__ __forceinline__ float lanef(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
