@@ -151,15 +151,17 @@ def bench_fwd_bwd(ctx, stream):
 def bench_variants(ctx, h, dims, views_R, W, H, stream):
     """The same cube and views rendered with a perspective camera (eye at twice
     the half diagonal from the centre: a 53-degree field of view at the
-    box-diagonal extent) and as a maximum intensity projection."""
+    box-diagonal extent), as a maximum intensity projection, and with the
+    opacity test over the whole ray (bricks in front-to-back waves)."""
     import torch
     n = np.array(dims, np.float64)
     eye = float(np.sqrt(((n - 1) ** 2).sum()))  # 2 x half diagonal
     out = torch.empty((len(views_R), H, W, 4), device="cuda")
     res = {}
-    for name, mode, ed in (("perspective", 0, eye), ("mip", vr.VR_MODE_MIP, 0.0)):
+    for name, mode, ed, scope in (("perspective", 0, eye, 0), ("mip", vr.VR_MODE_MIP, 0.0, 0),
+                                  ("global_ert", 0, 0.0, vr.VR_ERT_GLOBAL)):
         views = [vr.make_view(R, W, H, eye_dist=ed) for R in views_R]
-        params = vr.make_params(step=0.5, tau=0.99, ess=1, mode=mode)
+        params = vr.make_params(step=0.5, tau=0.99, ess=1, mode=mode, ert_scope=scope)
         nominal = sum(vr.vr_count_samples(dims, v, 0.5) for v in views)
         ms = _events_ms(lambda: vr.vr_render(ctx, h, views, params, out, stream), 3, stream)
         log(f"{name}: {ms / len(views):.3f} ms/frame, {nominal / ms / 1e6:.1f} Gsamples/s")

@@ -86,7 +86,16 @@ typedef struct {
   double eye_dist; /* 0: orthographic; > 0: perspective, eye at this distance from the box centre */
 } vr_view;
 
-enum { VR_ERT_LOCAL = 0 };   /* opacity threshold tested per brick (sort-last, Sec. 2.3/2.5) */
+/* Early termination scope (Sec. 2.4; the sort-last split of Sec. 2.3/2.5):
+ * VR_ERT_LOCAL: each brick accumulates from T = 1 and stops on its own (the
+ *   paper's independent GPUs); brick images are then over-composited.
+ * VR_ERT_GLOBAL: one opacity test over the whole ray: bricks are marched in
+ *   front-to-back waves (no ray meets two bricks of one wave) straight into
+ *   the frame, every ray continuing from the colour and transmittance the
+ *   bricks in front left; the image equals the unbricked render.  No brick
+ *   images exist (vr_render_bricks rejects it); unbricked volumes and
+ *   VR_MODE_MIP are unaffected by the scope. */
+enum { VR_ERT_LOCAL = 0, VR_ERT_GLOBAL = 1 };
 /* VR_MODE_DVR: emission-absorption accumulated front to back, sub-volume
  * images over-composited in depth order.  VR_MODE_MIP: maximum intensity
  * projection (paper Sec. 2.4: the kernel's output is the maximum scalar value
@@ -104,7 +113,7 @@ typedef struct {
   double tau;        /* stop a ray after the sample where 1 - T >= tau; tau >= 1 disables */
   int32_t ess;       /* 1: empty-space skipping: skip bricks, and slabs of macrocells (when the
                         volume has them), whose transfer-function opacity is 0 over their range */
-  int32_t ert_scope; /* VR_ERT_LOCAL */
+  int32_t ert_scope; /* VR_ERT_LOCAL or VR_ERT_GLOBAL */
   int32_t mode;      /* VR_MODE_DVR or VR_MODE_MIP */
   int32_t ckpt_K;    /* adjoint: transmittance checkpoint interval in samples (>= 1; 32 typical) */
   int32_t tile;      /* pixel tile edge of one wavefront: 0 = autotuned/default (8) */
@@ -279,7 +288,8 @@ typedef struct {
  * *nimg is the capacity of imgs and order; on output the number of images.
  * order receives the front-to-back order as indices into imgs.  Image memory
  * is library arena storage valid until the next render call on this context.
- * Errors: VR_EINVAL, VR_ESTATE (not bricked, no transfer function), VR_ENOMEM, VR_EHIP.
+ * Errors: VR_EINVAL, VR_ESTATE (not bricked, no transfer function), VR_EUNSUPPORTED
+ * (VR_ERT_GLOBAL), VR_ENOMEM, VR_EHIP.
  */
 int vr_render_bricks(vr_ctx *ctx, const vr_volume *vol, const vr_view *view, const vr_params *p,
                      vr_brick_image *imgs, int32_t *nimg, int32_t *order, uintptr_t stream);
@@ -374,15 +384,17 @@ int vr_autotune_batch(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_p
 
 /* ------------------------------------------------------------------ host-only helpers */
 /*
- * Rendering rectangles and depth order for a brick partition of a volume of
- * size dims and one view (paper Sec. 2.4: the rectangle bounds the projection
- * of the brick; it never changes the image).  No GPU use.  rects: [nb][4]
- * (x0, y0, w, h; w = 0 for an empty rectangle), order: [nb] brick indices
- * front to back.  *nb is the capacity on input, the brick count on output.
- * Errors: VR_EINVAL.
+ * Rendering rectangles, depth order and front-to-back waves for a brick
+ * partition of a volume of size dims and one view (paper Sec. 2.4: the
+ * rectangle bounds the projection of the brick; it never changes the image).
+ * No GPU use.  rects: [nb][4] (x0, y0, w, h; w = 0 for an empty rectangle),
+ * order: [nb] brick indices front to back, waves: [nb] wave of each brick
+ * under VR_ERT_GLOBAL (no ray meets two bricks of one wave; every ray meets
+ * its bricks in increasing wave order).  Each output may be NULL.  *nb is the
+ * capacity on input, the brick count on output.  Errors: VR_EINVAL.
  */
 int vr_plan_view(const int64_t dims[3], const vr_brick_spec *spec, const vr_view *view, int32_t *nb,
-                 int32_t *rects, int32_t *order);
+                 int32_t *rects, int32_t *order, int32_t *waves);
 
 /*
  * The partition vr_volume_brick would make for a volume of size dims, without

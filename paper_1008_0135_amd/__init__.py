@@ -33,6 +33,8 @@ _NAMES = {0: "VR_OK", -1: "VR_EINVAL", -2: "VR_ENOMEM", -3: "VR_EHIP", -4: "VR_E
 
 VR_MODE_DVR = 0
 VR_MODE_MIP = 1
+VR_ERT_LOCAL = 0
+VR_ERT_GLOBAL = 1
 VR_BRICK_GRID = 0
 VR_BRICK_LONGEST_AXIS = 1
 VR_STAGE_SETUP, VR_STAGE_MARCH, VR_STAGE_COMPOSITE, VR_STAGE_BACKWARD, VR_STAGE_BATCH = range(5)
@@ -113,7 +115,7 @@ _SIGS = {
     "vr_batch_destroy": (_I, [_P]),
     "vr_autotune": (_I, [_P, _P, _P, _P, _P, _U]),
     "vr_autotune_batch": (_I, [_P, _P, _I32, _P, _P, _P, _U]),
-    "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P]),
+    "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "vr_count_samples": (_I, [_P, _P, _D, _P]),
     "vr_partition": (_I, [_P, _P, _P, _P]),
 }
@@ -180,12 +182,14 @@ def make_view(R, W, H, extent=0.0, eye_dist=0.0) -> vr_view:
     return v
 
 
-def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0, mode=0) -> vr_params:
-    """mode: VR_MODE_DVR (emission-absorption) or VR_MODE_MIP (maximum intensity projection)."""
+def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0, mode=0, ert_scope=0) -> vr_params:
+    """mode: VR_MODE_DVR (emission-absorption) or VR_MODE_MIP (maximum intensity projection);
+    ert_scope: VR_ERT_LOCAL (per brick) or VR_ERT_GLOBAL (over the whole ray)."""
     p = vr_params()
     lib().vr_params_default(C.byref(p))
     p.step, p.tau, p.ess, p.ckpt_K, p.tile = float(step), float(tau), int(ess), int(ckpt_K), int(tile)
     p.mode = int(mode)
+    p.ert_scope = int(ert_scope)
     return p
 
 
@@ -380,14 +384,17 @@ def make_request(vol, R, W, H, tf, vmin, vmax, out, extent=0.0, eye_dist=0.0):
     return q
 
 
-def vr_plan_view(dims, spec, view, capacity=65536):
+def vr_plan_view(dims, spec, view, capacity=65536, waves=False):
+    """Returns (rects, order), or (rects, order, waves) with waves=True."""
     d = (C.c_int64 * 3)(*[int(x) for x in dims])
     rects = (C.c_int32 * (4 * capacity))()
     order = (C.c_int32 * capacity)()
+    wv = (C.c_int32 * capacity)() if waves else None
     nb = C.c_int32(capacity)
-    _check(lib().vr_plan_view(d, C.byref(spec), C.byref(view), C.byref(nb), rects, order), "vr_plan_view")
+    _check(lib().vr_plan_view(d, C.byref(spec), C.byref(view), C.byref(nb), rects, order, wv), "vr_plan_view")
     n = nb.value
-    return [tuple(rects[4 * i:4 * i + 4]) for i in range(n)], [order[i] for i in range(n)]
+    out = [tuple(rects[4 * i:4 * i + 4]) for i in range(n)], [order[i] for i in range(n)]
+    return out + ([wv[i] for i in range(n)],) if waves else out
 
 
 def vr_partition(dims, spec):

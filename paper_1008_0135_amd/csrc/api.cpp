@@ -83,6 +83,27 @@ int stage_begin(vr_ctx* ctx, int stage, hipStream_t s) {
   return VR_OK;
 }
 
+int aux_fork(vr_ctx* ctx, hipStream_t s) {
+  if (!ctx->aux_fork_ev) {
+    for (int i = 0; i < vr_ctx::kAux; i++) {
+      VR_HIP(hipStreamCreateWithFlags(&ctx->aux[i], hipStreamNonBlocking));
+      VR_HIP(hipEventCreateWithFlags(&ctx->aux_join_ev[i], hipEventDisableTiming));
+    }
+    VR_HIP(hipEventCreateWithFlags(&ctx->aux_fork_ev, hipEventDisableTiming));
+  }
+  VR_HIP(hipEventRecord(ctx->aux_fork_ev, s));
+  for (int i = 0; i < vr_ctx::kAux; i++) VR_HIP(hipStreamWaitEvent(ctx->aux[i], ctx->aux_fork_ev, 0));
+  return VR_OK;
+}
+
+int aux_join(vr_ctx* ctx, hipStream_t s) {
+  for (int i = 0; i < vr_ctx::kAux; i++) {
+    VR_HIP(hipEventRecord(ctx->aux_join_ev[i], ctx->aux[i]));
+    VR_HIP(hipStreamWaitEvent(s, ctx->aux_join_ev[i], 0));
+  }
+  return VR_OK;
+}
+
 int stage_end(vr_ctx* ctx, hipStream_t s) {
   if (!ctx->prof) return VR_OK;
   VR_HIP(hipEventRecord(ctx->timed.back().b, s));
@@ -177,7 +198,7 @@ int check_params(const vr_params* p) {
   if (!p) return fail(VR_EINVAL, "params is NULL");
   if (!(p->step > 0.0) || !std::isfinite(p->step)) return fail(VR_EINVAL, "step must be > 0");
   if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(VR_EINVAL, "tau must be > 0 (>= 1 disables)");
-  if (p->ert_scope != VR_ERT_LOCAL) return fail(VR_EUNSUPPORTED, "only VR_ERT_LOCAL is implemented");
+  if (p->ert_scope != VR_ERT_LOCAL && p->ert_scope != VR_ERT_GLOBAL) return fail(VR_EINVAL, "unknown ert_scope %d", p->ert_scope);
   if (p->mode != VR_MODE_DVR && p->mode != VR_MODE_MIP) return fail(VR_EINVAL, "unknown mode %d", p->mode);
   if (p->ckpt_K < 1) return fail(VR_EINVAL, "ckpt_K must be >= 1");
   if (p->tile != 0 && p->tile != 4 && p->tile != 8 && p->tile != 16)
@@ -369,6 +390,11 @@ int vr_destroy(vr_ctx* ctx) {
   }
   for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
   if (ctx->done) (void)hipEventDestroy(ctx->done);
+  for (int i = 0; i < vr_ctx::kAux; i++) {
+    if (ctx->aux[i]) (void)hipStreamDestroy(ctx->aux[i]);
+    if (ctx->aux_join_ev[i]) (void)hipEventDestroy(ctx->aux_join_ev[i]);
+  }
+  if (ctx->aux_fork_ev) (void)hipEventDestroy(ctx->aux_fork_ev);
   delete ctx;
   return VR_OK;
 }
@@ -788,7 +814,7 @@ int vr_tf_set(vr_ctx* ctx, const float* rgba, int32_t m, double vmin, double vma
 
 // ---------------------------------------------------------------- host-only helpers
 int vr_plan_view(const int64_t dims[3], const vr_brick_spec* spec, const vr_view* view, int32_t* nb, int32_t* rects,
-                 int32_t* order) {
+                 int32_t* order, int32_t* waves) {
   clear_error();
   if (!dims || !spec || !view || !nb) return fail(VR_EINVAL, "dims, spec, view and nb must be non-NULL");
   VR_TRY(check_dims(dims[0], dims[1], dims[2]));
@@ -803,7 +829,7 @@ int vr_plan_view(const int64_t dims[3], const vr_brick_spec* spec, const vr_view
     return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
   }
   const int32_t have = (int32_t)P.boxes.size();
-  if ((rects || order) && *nb < have) return fail(VR_EINVAL, "capacity %d below brick count %d", *nb, have);
+  if ((rects || order || waves) && *nb < have) return fail(VR_EINVAL, "capacity %d below brick count %d", *nb, have);
   Camera cam;
   make_camera(*view, dims, cam);
   if (rects)
@@ -818,6 +844,11 @@ int vr_plan_view(const int64_t dims[3], const vr_brick_spec* spec, const vr_view
     std::vector<int32_t> o;
     depth_order(P, cam, o);
     std::copy(o.begin(), o.end(), order);
+  }
+  if (waves) {
+    std::vector<int32_t> w;
+    brick_waves(P, cam, w);
+    std::copy(w.begin(), w.end(), waves);
   }
   *nb = have;
   return VR_OK;

@@ -32,7 +32,7 @@ constexpr int32_t kRingMinWaves = 2;
 // transparent brick), launch order (brick index order, which keeps
 // neighbouring bricks together), arena offsets and the front-to-back layers.
 void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params* p, int32_t tile_w,
-                       const float* tf, int32_t M, double vmin, double vmax, ViewPlan& vp) {
+                       const float* tf, int32_t M, double vmin, double vmax, ViewPlan& vp, bool waves) {
   const Partition& P = vol->part;
   const int32_t nb = (int32_t)P.boxes.size();
   const int32_t tile_h = 64 / tile_w;
@@ -69,6 +69,31 @@ void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params*
     if (slot[b] >= 0) vp.layers_order.push_back(slot[b]);
   vp.ntiles = tiles;
   vp.pixels = pix;
+  vp.wave_begin.clear();
+  vp.wave_tiles.clear();
+  if (waves) {
+    std::vector<int32_t> wave;
+    const int32_t nw = brick_waves(P, cam, wave);
+    std::vector<DevBrickView> by_wave;
+    by_wave.reserve(vp.bv.size());
+    for (int32_t w = 0; w < nw; w++) {
+      const int32_t first = (int32_t)by_wave.size();
+      int32_t t = 0;
+      for (const DevBrickView& b : vp.bv)
+        if (wave[b.brick] == w) {
+          DevBrickView c = b;
+          c.tile_begin = t;
+          t += c.tiles_x * ((c.h + tile_h - 1) / tile_h);
+          by_wave.push_back(c);
+        }
+      if (t == 0) continue;
+      vp.wave_begin.push_back(first);
+      vp.wave_tiles.push_back(t);
+    }
+    vp.wave_begin.push_back((int32_t)by_wave.size());
+    vp.bv.swap(by_wave);
+    vp.layers_order.clear();  // no brick images to composite
+  }
 }
 
 int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p,
@@ -86,6 +111,9 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   fill_march_common(base, vol, &pt, vmin, vmax, ctx->d_tf, ctx->tf_m);
   if (!extras) VR_TRY(prepare_macrocells(ctx, vol, p, vmin, vmax, base, s));
   const int32_t tw = base.tile_w, th = base.tile_h;
+  // opacity tested over the whole ray: bricks marched in front-to-back waves
+  // straight into the frame, each ray carrying its state from brick to brick
+  const bool global = bricked && out && !extras && !base.mip && p->ert_scope == VR_ERT_GLOBAL;
 
   std::vector<ViewPlan> plans((size_t)nviews);
   std::vector<Camera> cams((size_t)nviews);
@@ -94,8 +122,8 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     make_camera(views[v], vol->n, cams[v]);
     ViewPlan& vp = plans[v];
     if (bricked) {
-      plan_bricked_view(vol, cams[v], p, tw, ctx->h_tf.data(), ctx->tf_m, vmin, vmax, vp);
-      arena_pix = std::max(arena_pix, vp.pixels);
+      plan_bricked_view(vol, cams[v], p, tw, ctx->h_tf.data(), ctx->tf_m, vmin, vmax, vp, global);
+      if (!global) arena_pix = std::max(arena_pix, vp.pixels);
     } else {
       DevBrickView b;
       std::memset(&b, 0, sizeof b);
@@ -143,6 +171,13 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   VR_TRY(stage_end(ctx, s));
   unsigned char* dt = reinterpret_cast<unsigned char*>(dtab);
 
+  // views with the opacity test over whole rays write disjoint frames and use
+  // no shared arena: their wave sequences run side by side on the side streams
+  // (small front and back waves of one view leave most of the chip idle)
+  if (global) {
+    VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
+    VR_TRY(aux_fork(ctx, s));
+  }
   for (int32_t v = 0; v < nviews; v++) {
     const ViewPlan& vp = plans[v];
     MarchArgs a = base;
@@ -191,6 +226,24 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         a.lds_budget = 8192;
       }
     }
+    if (global) {
+      // waves in order, each continuing the rays the previous left in the frame
+      float4* frame = reinterpret_cast<float4*>(out) + (int64_t)v * W * H;
+      hipStream_t vs = ctx->aux[v % vr_ctx::kAux];
+      lds = false;  // the slab march does not carry state
+      a.carry = 1;
+      a.img = frame;
+      VR_HIP(launch_carry(frame, (int64_t)W * H, false, vs));
+      const DevBrickView* wbv = a.bv;
+      for (size_t w = 0; w + 1 < vp.wave_begin.size(); w++) {
+        a.bv = wbv + vp.wave_begin[w];
+        a.nbv = vp.wave_begin[w + 1] - vp.wave_begin[w];
+        a.ntiles = vp.wave_tiles[w];
+        VR_HIP(ring ? launch_march_ring(a, ring_wpb, vs) : launch_march(a, vs));
+      }
+      VR_HIP(launch_carry(frame, (int64_t)W * H, true, vs));
+      continue;
+    }
     VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
     VR_HIP(extras ? extras->launch(a, s)
                   : (ring ? launch_march_ring(a, ring_wpb, s) : (lds ? launch_march_lds(a, s) : launch_march(a, s))));
@@ -208,6 +261,10 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       VR_HIP(launch_composite(c, s));
       VR_TRY(stage_end(ctx, s));
     }
+  }
+  if (global) {
+    VR_TRY(aux_join(ctx, s));
+    VR_TRY(stage_end(ctx, s));
   }
   if (extras) {
     extras->vmin = vmin;
@@ -258,6 +315,9 @@ int vr_render_bricks(vr_ctx* ctx, const vr_volume* cvol, const vr_view* view, co
   VR_TRY(validate_render(ctx, cvol, view, 1, p));
   if (!imgs || !nimg || !order) return fail(VR_EINVAL, "imgs, nimg and order must be non-NULL");
   if (!cvol->bricked) return fail(VR_ESTATE, "volume is not bricked (vr_volume_brick)");
+  if (p->ert_scope == VR_ERT_GLOBAL)
+    return fail(VR_EUNSUPPORTED, "per-brick images exist only with VR_ERT_LOCAL (global termination carries rays "
+                                 "across bricks)");
   vr_volume* vol = const_cast<vr_volume*>(cvol);
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;

@@ -13,6 +13,10 @@ struct ViewPlan {
   std::vector<int32_t> layers_order;  // indices into bv, front to back
   int32_t ntiles = 0;
   int64_t pixels = 0;                 // brick-image pixels of this view
+  // opacity tested over the whole ray: bv grouped into front-to-back waves,
+  // wave w = bv[wave_begin[w] .. wave_begin[w + 1]) with tile_begin counted
+  // from the wave's first brick and wave_tiles[w] tiles
+  std::vector<int32_t> wave_begin, wave_tiles;
 };
 
 // Hook that replaces the march launch (the differentiable forward saves
@@ -25,7 +29,7 @@ struct ForwardExtras {
 };
 
 void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params* p, int32_t tile_w, const float* tf,
-                       int32_t M, double vmin, double vmax, ViewPlan& vp);
+                       int32_t M, double vmin, double vmax, ViewPlan& vp, bool waves = false);
 int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p, float* out,
                    hipStream_t s, ForwardExtras* extras);
 int validate_render(vr_ctx* ctx, const vr_volume* vol, const vr_view* views, int32_t nviews, const vr_params* p);

@@ -26,6 +26,11 @@
 // workgroup only to share the transfer-function table in LDS; after loading it
 // each wavefront runs on its own, with no workgroup barrier.
 //
+// Carried state (a.carry, opacity tested over the whole ray): the image is the
+// output frame holding each ray's (C, T) from the bricks in front of this
+// one; a ray starts from it (and not at all once 1 - T >= tau) and leaves its
+// new state there.
+//
 // Perspective views (PERSP): the tile's rays leave one eye, so their
 // directions are positive combinations of the four corner directions; when
 // the corner rays all move the same way along b, every ray of the tile meets
@@ -98,9 +103,14 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   int cnt = 0;
   float px = 0.f, py = 0.f, pz = 0.f;
+  float4* const dst =
+      a.carry ? a.img + (int64_t)v * a.cam.W + u : a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
+  float4 carried = make_float4(0.f, 0.f, 0.f, 1.f);
+  if (a.carry && valid) carried = *dst;
+  const bool live = !a.carry || 1.f - carried.w < a.tau;
   double tin;
   int64_t n;
-  if (valid && ray_lattice(o, d, a.hi, a.step, tin, n)) {
+  if (valid && live && ray_lattice(o, d, a.hi, a.step, tin, n)) {
     int64_t k0, k1;
     brick_krange(o, d, tin, a.step, n, br.lo, br.hi, br.closed, k0, k1);
     if (k1 > k0) {
@@ -213,10 +223,9 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     Lbeg = uni(wave_imax(c_first));
     Lend = uni(wave_imin(c_last));
   }
-  float4* dst = a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
   const int pix = ly * bvw.w + lx;  // SAVE: pixel of the whole-volume image
   if (!force_gather && (up ? Lbeg > Lend : Lbeg < Lend)) {
-    if (valid) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid && !a.carry) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
     if (SAVE && valid) sa.nused[pix] = 0;
     return;
   }
@@ -285,7 +294,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   const int sB = by ? ysl : zsl, sG = by ? zsl : ysl;
   gfloat* gbase = (gfloat*)br.base;
 
-  float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f, mx = 0.f;
+  float Cr = carried.x, Cg = carried.y, Cb = carried.z, T = carried.w, mx = 0.f;
   int j = 0;
   bool done = cnt == 0;
 
@@ -315,7 +324,12 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
       while (gnext < ngrp_tile) save_group(gnext++, T, j);
       if (valid) sa.nused[pix] = j;
     }
-    if (valid) *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, 1.f - T);
+    // carried state: only rays with samples here write (another brick of the
+    // wave whose rectangle holds the pixel may update it)
+    if (valid && cnt > 0)
+      *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, a.carry ? T : 1.f - T);
+    else if (valid && !a.carry)
+      *dst = make_float4(0.f, 0.f, 0.f, 0.f);
     return;
   }
 
@@ -527,7 +541,8 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   wait_loads();  // no load may still target LDS when the wavefront ends
   if (SAVE && valid) sa.nused[pix] = j;
-  if (valid) *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, 1.f - T);
+  if (valid && (cnt > 0 || !a.carry))
+    *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, a.carry ? T : 1.f - T);
 }
 
 }  // namespace

@@ -146,6 +146,18 @@ Rect brick_rect(const Camera& cam, const Box& b) {
   return r;
 }
 
+// Slab of the eye along each axis of a grid (-1 before the first slab, the
+// slab count past the last): rays from the eye move away from it.
+static void eye_slabs(const Partition& p, const Camera& cam, int32_t e[3]) {
+  for (int i = 0; i < 3; i++) {
+    const double q = cam.eye[i];
+    const int32_t c = p.gcount[i];
+    if (q < 0.0) e[i] = -1;
+    else if (q >= (double)p.boxes.back().hi[i]) e[i] = c;
+    else e[i] = std::min<int32_t>(c - 1, (int32_t)std::floor(q / (double)p.gsize[i]));
+  }
+}
+
 // Near child first: for parallel rays the side the rays come from; for rays
 // from an eye the side that holds the eye (a ray crosses a plane at most once,
 // leaving the eye's side).
@@ -172,13 +184,7 @@ void depth_order(const Partition& p, const Camera& cam, std::vector<int32_t>& or
     // by the distances along axes 3, 2, 1 (lexicographically) puts every
     // brick a ray meets after the ones it met before
     int32_t e[3];
-    for (int i = 0; i < 3; i++) {
-      const double q = cam.eye[i];
-      const int32_t c = p.gcount[i];
-      if (q < 0.0) e[i] = -1;
-      else if (q >= (double)p.boxes.back().hi[i]) e[i] = c;
-      else e[i] = std::min<int32_t>(c - 1, (int32_t)std::floor(q / (double)p.gsize[i]));
-    }
+    eye_slabs(p, cam, e);
     const int32_t* c = p.gcount;
     std::vector<std::pair<int64_t, int32_t>> key;
     key.reserve(p.boxes.size());
@@ -210,6 +216,47 @@ void depth_order(const Partition& p, const Camera& cam, std::vector<int32_t>& or
       }
     }
   }
+}
+
+int32_t brick_waves(const Partition& p, const Camera& cam, std::vector<int32_t>& wave) {
+  const int32_t nb = (int32_t)p.boxes.size();
+  wave.assign((size_t)nb, 0);
+  int32_t nw = 0;
+  if (p.mode == VR_BRICK_GRID) {
+    const int32_t* c = p.gcount;
+    int32_t e[3] = {0, 0, 0};
+    if (cam.persp) eye_slabs(p, cam, e);
+    for (int32_t b = 0; b < nb; b++) {
+      const int32_t k[3] = {b % c[0], (b / c[0]) % c[1], b / (c[0] * c[1])};
+      int32_t w = 0;
+      for (int i = 0; i < 3; i++) {
+        if (cam.persp) w += std::abs(k[i] - e[i]);
+        else w += cam.e3[i] >= 0.0 ? k[i] : c[i] - 1 - k[i];
+      }
+      wave[b] = w;
+      nw = std::max(nw, w + 1);
+    }
+    return nw;
+  }
+  std::vector<int32_t> order;
+  depth_order(p, cam, order);
+  std::vector<Rect> r((size_t)nb);
+  for (int32_t b = 0; b < nb; b++) r[b] = brick_rect(cam, p.boxes[b]);
+  for (size_t i = 0; i < order.size(); i++) {
+    const int32_t b = order[i];
+    int32_t w = 0;
+    if (r[b].w > 0 && r[b].h > 0)
+      for (size_t j = 0; j < i; j++) {
+        const int32_t q = order[j];
+        if (r[q].w == 0 || r[q].h == 0) continue;
+        const bool overlap = r[q].x0 < r[b].x0 + r[b].w && r[b].x0 < r[q].x0 + r[q].w && r[q].y0 < r[b].y0 + r[b].h &&
+                             r[b].y0 < r[q].y0 + r[q].h;
+        if (overlap) w = std::max(w, wave[q] + 1);
+      }
+    wave[b] = w;
+    nw = std::max(nw, w + 1);
+  }
+  return nw;
 }
 
 bool brick_transparent(float bmin, float bmax, const float* tf, int32_t M, double vmin, double vmax) {

@@ -55,6 +55,13 @@ Rect brick_rect(const Camera& cam, const Box& b);
 // Front-to-back order of all boxes for ray direction d.
 void depth_order(const Partition& p, const Camera& cam, std::vector<int32_t>& order);
 
+// Front-to-back waves: wave[b] for every box such that no ray meets two boxes
+// of one wave and every ray meets its boxes in increasing wave order (grid:
+// the sum over axes of the box's slab distance from the rays' start, exact;
+// longest-axis split: one past the largest wave of any earlier box in depth
+// order whose rectangle overlaps).  Returns the number of waves.
+int32_t brick_waves(const Partition& p, const Camera& cam, std::vector<int32_t>& wave);
+
 // True when every sample a brick with stored range [bmin, bmax] can produce
 // has zero opacity: all table alphas in [floor(u(bmin)) - 1, ceil(u(bmax)) + 1]
 // (clipped to [0, M-1]) are zero.  Skipping such a brick is bit-exact.

@@ -72,13 +72,24 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
 
   double o[3], d[3];
   pixel_ray(a.cam, u, v, o, d);
+  float4* const dst = a.carry ? a.img + (int64_t)v * a.cam.W + u : a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
   float Cr = 0.f, Cg = 0.f, Cb = 0.f, T = 1.f, mx = 0.f;
+  if (a.carry) {
+    const float4 s0 = *dst;
+    if (1.f - s0.w >= a.tau) return;  // the ray stopped in a brick in front
+    Cr = s0.x;
+    Cg = s0.y;
+    Cb = s0.z;
+    T = s0.w;
+  }
   double tin;
   int64_t n;
+  bool touched = false;  // the ray has samples in this brick
   if (ray_lattice(o, d, a.hi, a.step, tin, n)) {
     int64_t k0, k1;
     brick_krange(o, d, tin, a.step, n, br.lo, br.hi, br.closed, k0, k1);
     if (k1 > k0) {
+      touched = true;
       const double t0 = tin + ((double)k0 + 0.5) * a.step;
       const float px = (float)(o[0] + t0 * d[0] - (double)br.lo[0]);
       const float py = (float)(o[1] + t0 * d[1] - (double)br.lo[1]);
@@ -102,8 +113,24 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       }
     }
   }
-  a.img[bvw.img_off + (int64_t)ly * bvw.w + lx] =
-      MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, 1.f - T);
+  // carried state: only a ray with samples here owns its pixel in this wave
+  // (another brick of the wave whose rectangle holds the pixel may update it)
+  if (a.carry && !touched) return;
+  *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, a.carry ? T : 1.f - T);
+}
+
+// Carried state over the frame: (C, T) = (0, 1) before the first brick, and
+// (C, 1 - T) once the last has been marched.
+__global__ __launch_bounds__(256) void k_carry_init(float4* img, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) img[i] = make_float4(0.f, 0.f, 0.f, 1.f);
+}
+__global__ __launch_bounds__(256) void k_carry_final(float4* img, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) {
+    const float4 s = img[i];
+    img[i] = make_float4(s.x, s.y, s.z, 1.f - s.w);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
@@ -134,6 +161,14 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
 }
 
 }  // namespace
+
+hipError_t launch_carry(float4* img, int64_t n, bool final, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = (n + 255) / 256;
+  if (final) hipLaunchKernelGGL(k_carry_final, dim3((unsigned)grid), dim3(256), 0, s, img, n);
+  else hipLaunchKernelGGL(k_carry_init, dim3((unsigned)grid), dim3(256), 0, s, img, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_march(const MarchArgs& a, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;

@@ -74,6 +74,12 @@ struct vr_ctx {
   // calls on this context are ordered, whatever stream they use
   hipEvent_t done = nullptr;
   bool done_valid = false;
+  // side streams (default priority) for work of one call that is independent
+  // (the views of a render with the opacity test over whole rays), forked
+  // from and joined back into the caller's stream; created on first use
+  static constexpr int kAux = 4;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t aux_fork_ev = nullptr, aux_join_ev[kAux] = {};
   // stage timers
   bool prof = false;
   struct Timed {
@@ -133,6 +139,9 @@ namespace vr {
 int ctx_begin(vr_ctx* ctx, hipStream_t s);
 int ctx_end(vr_ctx* ctx, hipStream_t s);
 int stage_begin(vr_ctx* ctx, int stage, hipStream_t s);
+// make the side streams wait for the work queued on s so far / s wait for theirs
+int aux_fork(vr_ctx* ctx, hipStream_t s);
+int aux_join(vr_ctx* ctx, hipStream_t s);
 int stage_end(vr_ctx* ctx, hipStream_t s);
 int ensure_device(void** p, size_t* cap, size_t need);
 int upload_tables(vr_ctx* ctx, hipStream_t s, const void* data, size_t bytes, void** dev);

@@ -197,7 +197,8 @@ struct MarchArgs {
   int32_t lds_budget;    // floats of LDS for one slab's voxel box
   int32_t ring_slot;     // ring march: floats per LDS ring slot (one voxel layer's window)
   int32_t mip;           // 1: maximum intensity projection (pixels (M, M, M, M)), 0: emission-absorption
-  int32_t pad2;
+  int32_t carry;         // 1: rays continue from the state (C, T) held in img, the output frame
+                         // (rows of cam.W pixels), and leave theirs there
   const float4* tf;      // [M] RGBA
   const DevBrick* bricks;
   const DevBrickView* bv;
@@ -262,6 +263,8 @@ struct BatchArgs {
 
 // Launchers (defined in the .hip files); all asynchronous on `s`.
 hipError_t launch_march(const MarchArgs& a, hipStream_t s);
+// (C, T) = (0, 1) over a frame of n pixels (final = false), or (C, T) -> (C, 1 - T) (final = true)
+hipError_t launch_carry(float4* img, int64_t n, bool final, hipStream_t s);
 // Ring march (march_ring.hip): 8 x 8 tiles, a.ring_slot floats per window slot,
 // `wpb` wavefronts per workgroup (1, 2 or 4).
 hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s);

@@ -140,16 +140,16 @@ def _slab(o, d, lo, hi):
 @pytest.mark.parametrize("kind,eye", [("grid", 0.0), ("kd", 0.0), ("grid", 90.0), ("kd", 90.0), ("grid", 260.0),
                                       ("kd", 260.0)])
 def test_rectangles_conservative_and_order_consistent(kind, eye):
-    """Rectangles hold every pixel whose ray meets the brick; the order sorts
-    every ray's bricks by entry (parallel rays, and rays from an eye at 90 or
-    260 voxels from the centre of a box of half-diagonal 86)."""
+    """Rectangles hold every pixel whose ray meets the brick; the order and the
+    waves sort every ray's bricks by entry (parallel rays, and rays from an eye
+    at 90 or 260 voxels from the centre of a box of half-diagonal 86)."""
     dims = (96, 80, 120)
     spec = vr.grid_spec((32, 32, 48)) if kind == "grid" else vr.kd_spec(6)
     descs = vr.vr_partition(dims, spec)
     for R in synth.random_views(4, 41):
         W, H = 64, 48
         view = vr.make_view(R, W, H, eye_dist=eye)
-        rects, order = vr.vr_plan_view(dims, spec, view)
+        rects, order, waves = vr.vr_plan_view(dims, spec, view, waves=True)
         o, d = _rays(dims, R, W, H, eye_dist=eye)
         pos = {b: i for i, b in enumerate(order)}
         entries = []
@@ -177,6 +177,7 @@ def test_rectangles_conservative_and_order_consistent(kind, eye):
                 for (t1, b1), (t2, b2) in zip(met, met[1:]):
                     if t2 - t1 > 1e-9:
                         assert pos[b1] < pos[b2]
+                        assert waves[b1] < waves[b2]  # global termination: one brick per ray per wave
 
 
 def test_count_samples_matches_oracle(orc):
