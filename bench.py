@@ -209,6 +209,8 @@ def main():
     ap.add_argument("--macrocell", type=int, default=16,
                     help="macrocell edge for empty-space skipping (0: none; used by tables with zero opacity)")
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--twin", type=int, default=0,
+                    help="1: keep a permuted copy of the cube for views along axis 1 (24 GiB more HBM)")
     ap.add_argument("--oracle-seconds", type=float, default=15.0)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--per-view", action="store_true", help="print each view's march time to stderr")
@@ -248,7 +250,8 @@ def main():
     vmin, vmax = vr.vr_volume_minmax(h)
     log(f"uploaded + min/max in {time.time() - t0:.1f} s: range [{vmin:.3f}, {vmax:.3f}]")
     t0 = time.time()
-    vr.vr_volume_brick(h, vr.grid_spec(cfg["bricks"], materialize=args.materialize, macrocell=args.macrocell))
+    vr.vr_volume_brick(h, vr.grid_spec(cfg["bricks"], materialize=args.materialize, macrocell=args.macrocell,
+                                       twin=bool(args.twin)))
     bricks = vr.vr_volume_brick_info(h)
     log(f"bricked into {len(bricks)} bricks in {time.time() - t0:.1f} s")
     if args.tf == "ramp":
@@ -333,7 +336,7 @@ def main():
                         f"{cfg['bricks'][0]}^3 bricks, {W}x{H} frames, {nviews} views/step, step 0.5, "
                         f"tau 0.99 local ERT, TF {args.tf}" + (", materialised bricks" if args.materialize else ""),
             "volume": [n1, n2, n3], "bricks": list(cfg["bricks"]), "image": [W, H], "views_per_step": nviews,
-            "tf": args.tf, "tile": args.tile or 8, "macrocell": args.macrocell,
+            "tf": args.tf, "tile": args.tile or 8, "macrocell": args.macrocell, "twin": bool(args.twin),
         },
         "ms_per_frame": round(ms_step / nviews, 4),
         "nominal_samples_per_frame": int(nominal // nviews),

@@ -187,7 +187,11 @@ typedef struct {
   int32_t ghost;       /* ghost layer width: must be 1 */
   int32_t macrocell;   /* macrocell edge in cells for empty-space skipping: 0 = none, else in [2, 1024] */
   int32_t materialize; /* 1: copy each brick and its ghost layer into its own storage */
-  int32_t reserved;
+  int32_t twin;        /* 1: also keep a permuted copy of the volume (axes 1, 2, 3 = axes 2, 3, 1;
+                          one more volume's worth of device memory), bricked with the same
+                          sub-volumes, from which views looking mostly along axis 1 are
+                          rendered (same image up to rounding).  The copy is taken now: a
+                          wrapped volume whose data change needs vr_volume_brick again. */
 } vr_brick_spec;
 
 /*

@@ -59,7 +59,7 @@ class vr_params(C.Structure):
 
 class vr_brick_spec(C.Structure):
     _fields_ = [("mode", C.c_int32), ("nparts", C.c_int32), ("size", C.c_int64 * 3), ("ghost", C.c_int32),
-                ("macrocell", C.c_int32), ("materialize", C.c_int32), ("reserved", C.c_int32)]
+                ("macrocell", C.c_int32), ("materialize", C.c_int32), ("twin", C.c_int32)]
 
 
 class vr_brick_desc(C.Structure):
@@ -193,7 +193,7 @@ def make_params(step=0.5, tau=0.99, ess=1, ckpt_K=32, tile=0, mode=0, ert_scope=
     return p
 
 
-def grid_spec(size, materialize=False, macrocell=0) -> vr_brick_spec:
+def grid_spec(size, materialize=False, macrocell=0, twin=False) -> vr_brick_spec:
     s = vr_brick_spec()
     s.mode = VR_BRICK_GRID
     for i in range(3):
@@ -201,16 +201,18 @@ def grid_spec(size, materialize=False, macrocell=0) -> vr_brick_spec:
     s.ghost = 1
     s.macrocell = int(macrocell)
     s.materialize = int(bool(materialize))
+    s.twin = int(bool(twin))
     return s
 
 
-def kd_spec(nparts, materialize=False, macrocell=0) -> vr_brick_spec:
+def kd_spec(nparts, materialize=False, macrocell=0, twin=False) -> vr_brick_spec:
     s = vr_brick_spec()
     s.mode = VR_BRICK_LONGEST_AXIS
     s.nparts = int(nparts)
     s.ghost = 1
     s.macrocell = int(macrocell)
     s.materialize = int(bool(materialize))
+    s.twin = int(bool(twin))
     return s
 
 

@@ -558,6 +558,7 @@ int vr_volume_destroy(vr_volume* vol) {
   if (vol->d_store) (void)hipFree(vol->d_store);
   if (vol->d_mc_mm) (void)hipFree(vol->d_mc_mm);
   if (vol->d_mc_clear) (void)hipFree(vol->d_mc_clear);
+  if (vol->twin) vr_volume_destroy(vol->twin);
   delete vol;
   return VR_OK;
 }
@@ -583,30 +584,15 @@ int vr_volume_dims(const vr_volume* vol, int64_t n[3]) {
   return VR_OK;
 }
 
-int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream) {
-  clear_error();
-  if (!vol || !spec) return fail(VR_EINVAL, "vol and spec must be non-NULL");
-  if (spec->ghost != 1) return fail(VR_EINVAL, "ghost must be 1");
-  if (spec->macrocell != 0 && (spec->macrocell < 2 || spec->macrocell > 1024))
-    return fail(VR_EINVAL, "macrocell %d outside {0} U [2, 1024]", spec->macrocell);
-  Partition P;
-  std::string err;
-  if (spec->mode == VR_BRICK_GRID) {
-    if (!make_grid(vol->n, spec->size, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
-  } else if (spec->mode == VR_BRICK_LONGEST_AXIS) {
-    if (!make_kd(vol->n, spec->nparts, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
-  } else {
-    return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
-  }
+// Brick records, storage and ranges of partition P for vol (and its
+// macrocells); the caller holds the context's call order.
+static int brick_volume(vr_volume* vol, Partition& P, bool materialize, int32_t macrocell, hipStream_t s) {
   vr_ctx* ctx = vol->ctx;
-  DeviceGuard g(ctx->device);
-  hipStream_t s = (hipStream_t)stream;
-  VR_TRY(ctx_begin(ctx, s));
   const int32_t nb = (int32_t)P.boxes.size();
   const int64_t* n = vol->n;
   // storage: virtual (strided view of the volume) unless asked, or unless a
   // brick's local offsets would not fit 32-bit indices
-  bool mat = spec->materialize != 0;
+  bool mat = materialize;
   std::vector<int64_t> sboxes(6 * (size_t)nb);
   for (int32_t b = 0; b < nb; b++) {
     int64_t slo[3], shi[3];
@@ -716,9 +702,76 @@ int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream)
   vol->bricked = true;
   vol->materialized = mat;
   vol->version++;
-  VR_TRY(build_macrocells(vol, spec->macrocell, s));
-  VR_TRY(ctx_end(ctx, s));
+  return build_macrocells(vol, macrocell, s);
+}
+
+static void destroy_twin(vr_volume* vol) {
+  if (vol->twin) {
+    vr_volume_destroy(vol->twin);
+    vol->twin = nullptr;
+  }
+}
+
+// The permuted copy of vol (axes 1, 2, 3 = vol's axes 2, 3, 1), bricked with
+// the permuted partition of vol.
+static int make_twin(vr_volume* vol, int32_t macrocell, hipStream_t s) {
+  const int64_t* n = vol->n;
+  vr_volume* t = vol->twin;
+  if (!t) {
+    t = new vr_volume;
+    t->ctx = vol->ctx;
+    t->n[0] = n[1];
+    t->n[1] = n[2];
+    t->n[2] = n[0];
+    if (hipMalloc(&t->data, sizeof(float) * (size_t)(n[0] * n[1] * n[2]) + 256) != hipSuccess) {
+      (void)hipGetLastError();
+      delete t;
+      return fail(VR_ENOMEM, "hipMalloc for the permuted copy (%lld floats) failed", (long long)(n[0] * n[1] * n[2]));
+    }
+    t->owned = true;
+    vol->twin = t;
+  }
+  VR_HIP(launch_twin(vol->data, n, t->data, s));
+  t->have_range = vol->have_range;
+  t->vmin = vol->vmin;
+  t->vmax = vol->vmax;
+  t->nonfinite = vol->nonfinite;
+  VR_TRY(make_whole_brick(t));
+  Partition P;
+  permute_partition(vol->part, t->n, P);
+  VR_TRY(brick_volume(t, P, false, macrocell, s));
+  t->version++;
   return VR_OK;
+}
+
+int vr_volume_brick(vr_volume* vol, const vr_brick_spec* spec, uintptr_t stream) {
+  clear_error();
+  if (!vol || !spec) return fail(VR_EINVAL, "vol and spec must be non-NULL");
+  if (spec->ghost != 1) return fail(VR_EINVAL, "ghost must be 1");
+  if (spec->macrocell != 0 && (spec->macrocell < 2 || spec->macrocell > 1024))
+    return fail(VR_EINVAL, "macrocell %d outside {0} U [2, 1024]", spec->macrocell);
+  if (spec->twin != 0 && spec->twin != 1) return fail(VR_EINVAL, "twin must be 0 or 1");
+  Partition P;
+  std::string err;
+  if (spec->mode == VR_BRICK_GRID) {
+    if (!make_grid(vol->n, spec->size, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else if (spec->mode == VR_BRICK_LONGEST_AXIS) {
+    if (!make_kd(vol->n, spec->nparts, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else {
+    return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
+  }
+  vr_ctx* ctx = vol->ctx;
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  VR_TRY(ctx_begin(ctx, s));
+  VR_TRY(brick_volume(vol, P, spec->materialize != 0, spec->macrocell, s));
+  if (spec->twin) {
+    VR_TRY(make_twin(vol, spec->macrocell, s));
+  } else if (vol->twin) {
+    VR_HIP(hipStreamSynchronize(s));
+    destroy_twin(vol);
+  }
+  return ctx_end(ctx, s);
 }
 
 int vr_volume_brick_info(const vr_volume* vol, int32_t* nb, vr_brick_desc* out) {

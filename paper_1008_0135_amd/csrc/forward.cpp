@@ -305,7 +305,36 @@ int vr_render(vr_ctx* ctx, const vr_volume* cvol, const vr_view* views, int32_t 
   hipStream_t s = (hipStream_t)stream;
   if (save) return render_with_state(ctx, vol, views, nviews, p, out, s, save);
   VR_TRY(ctx_begin(ctx, s));
-  VR_TRY(render_forward(ctx, vol, views, nviews, p, out, s, nullptr));
+  if (!vol->twin || !vol->bricked) {
+    VR_TRY(render_forward(ctx, vol, views, nviews, p, out, s, nullptr));
+    return ctx_end(ctx, s);
+  }
+  // views looking mostly along axis 1 (the contiguous one) are rendered from
+  // the permuted copy, whose contiguous axis is axis 2: the same rays in
+  // permuted coordinates (view axes permuted like the volume's)
+  auto along1 = [](const vr_view& v) {
+    return std::fabs(v.R[6]) > std::max(std::fabs(v.R[7]), std::fabs(v.R[8]));
+  };
+  const int64_t frame = (int64_t)views[0].W * views[0].H * 4;
+  for (int32_t v0 = 0; v0 < nviews;) {
+    const bool tw = along1(views[v0]);
+    int32_t v1 = v0 + 1;
+    while (v1 < nviews && along1(views[v1]) == tw) v1++;
+    if (tw) {
+      std::vector<vr_view> pv(views + v0, views + v1);
+      for (vr_view& q : pv)
+        for (int r = 0; r < 3; r++) {
+          const double x = q.R[3 * r], y = q.R[3 * r + 1], z = q.R[3 * r + 2];
+          q.R[3 * r] = y;
+          q.R[3 * r + 1] = z;
+          q.R[3 * r + 2] = x;
+        }
+      VR_TRY(render_forward(ctx, vol->twin, pv.data(), v1 - v0, p, out + v0 * frame, s, nullptr));
+    } else {
+      VR_TRY(render_forward(ctx, vol, views + v0, v1 - v0, p, out + v0 * frame, s, nullptr));
+    }
+    v0 = v1;
+  }
   return ctx_end(ctx, s);
 }
 

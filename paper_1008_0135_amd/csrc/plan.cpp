@@ -106,6 +106,30 @@ bool make_kd(const int64_t n[3], int32_t nparts, Partition& out, std::string& er
   return true;
 }
 
+void permute_partition(const Partition& p, const int64_t n_twin[3], Partition& out) {
+  // axis a of the volume is axis t[a] of the copy
+  static const int t[3] = {2, 0, 1};
+  if (p.mode == VR_BRICK_GRID) {
+    int64_t size[3];
+    for (int a = 0; a < 3; a++) size[t[a]] = p.gsize[a];
+    std::string err;
+    make_grid(n_twin, size, out, err);  // cannot fail: the same counts as p
+    return;
+  }
+  out = Partition();
+  out.mode = p.mode;
+  out.boxes.resize(p.boxes.size());
+  for (size_t b = 0; b < p.boxes.size(); b++)
+    for (int a = 0; a < 3; a++) {
+      out.boxes[b].lo[t[a]] = p.boxes[b].lo[a];
+      out.boxes[b].hi[t[a]] = p.boxes[b].hi[a];
+      out.boxes[b].closed[t[a]] = p.boxes[b].closed[a];
+    }
+  out.nodes = p.nodes;
+  for (KdNode& nd : out.nodes)
+    if (nd.leaf < 0) nd.axis = t[nd.axis];
+}
+
 void stored_box(const Box& b, const int64_t n[3], int64_t slo[3], int64_t shi[3]) {
   for (int i = 0; i < 3; i++) {
     slo[i] = std::max<int64_t>(0, b.lo[i] - 1);

@@ -52,6 +52,11 @@ void stored_box(const Box& b, const int64_t n[3], int64_t slo[3], int64_t shi[3]
 // padded by one pixel, clipped to the image).
 Rect brick_rect(const Camera& cam, const Box& b);
 
+// The partition of the permuted copy whose axes 1, 2, 3 are axes 2, 3, 1 of
+// the partition's volume: the same boxes, axes permuted (grid: in the copy's
+// grid order; longest-axis split: the same tree).
+void permute_partition(const Partition& p, const int64_t n_twin[3], Partition& out);
+
 // Front-to-back order of all boxes for ray direction d.
 void depth_order(const Partition& p, const Camera& cam, std::vector<int32_t>& order);
 

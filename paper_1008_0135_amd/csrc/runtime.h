@@ -132,6 +132,9 @@ struct vr_volume {
   uint64_t mc_tf_version = 0;
   double mc_vmin = 0.0, mc_vmax = 0.0;
   uint64_t version = 0;
+  // permuted copy (axes 1, 2, 3 = this volume's axes 2, 3, 1), bricked with the
+  // permuted partition, for views that look along axis 1 (owned; or null)
+  vr_volume* twin = nullptr;
 };
 
 namespace vr {

@@ -239,6 +239,38 @@ hipError_t launch_brick_minmax_parts(const float* vol, const int64_t n[3], const
   return hipGetLastError();
 }
 
+// Permuted copy for views along axis 1: dst[x][z][y] = src[z][y][x] (the
+// copy's axes 1, 2, 3 are the source's axes 2, 3, 1).  32 x 32 tiles of each
+// (y, x) plane go through LDS so that both the reads (rows along x) and the
+// writes (rows along y) are whole 128-byte lines.
+__global__ __launch_bounds__(256) void k_twin(const float* __restrict__ src, float* __restrict__ dst, int64_t n1,
+                                              int64_t n2, int64_t n3) {
+  __shared__ float tile[32][33];
+  const int64_t ntx = (n1 + 31) / 32, nty = (n2 + 31) / 32, units = ntx * nty * n3;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    const int64_t bx = u % ntx, by = (u / ntx) % nty, z = u / (ntx * nty);
+    const int64_t x0 = bx * 32, y0 = by * 32;
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t y = y0 + r, x = x0 + tx;
+      if (y < n2 && x < n1) tile[r][tx] = src[(z * n2 + y) * n1 + x];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t x = x0 + r, y = y0 + tx;
+      if (x < n1 && y < n2) dst[(x * n3 + z) * n2 + y] = tile[tx][r];
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_twin(const float* src, const int64_t n[3], float* dst, hipStream_t s) {
+  const int64_t units = ((n[0] + 31) / 32) * ((n[1] + 31) / 32) * n[2];
+  const int grid = (int)(units < (1 << 20) ? units : (1 << 20));
+  hipLaunchKernelGGL(k_twin, dim3(grid), dim3(256), 0, s, src, dst, n[0], n[1], n[2]);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
                            const int64_t dn[3], hipStream_t s) {
   const int64_t rows = dn[1] * dn[2];

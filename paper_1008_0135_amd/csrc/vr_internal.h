@@ -293,6 +293,8 @@ hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int blocks, hipStream_t s);
 hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
                            const int64_t dn[3], hipStream_t s);
+// dst[x][z][y] = src[z][y][x] for a volume of dims n (dst holds n[0] n[1] n[2] floats)
+hipError_t launch_twin(const float* src, const int64_t n[3], float* dst, hipStream_t s);
 // Macrocell (min, max) pairs [c3][c2][c1] of edge `mc` over the volume (mc in [2, 1024]).
 hipError_t launch_mc_minmax(const float* vol, const int64_t n[3], int mc, const int64_t c[3], float* out2,
                             hipStream_t s);
