@@ -209,8 +209,8 @@ def main():
     ap.add_argument("--macrocell", type=int, default=16,
                     help="macrocell edge for empty-space skipping (0: none; used by tables with zero opacity)")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--twin", type=int, default=0,
-                    help="1: keep a permuted copy of the cube for views along axis 1 (24 GiB more HBM)")
+    ap.add_argument("--twin", type=int, default=1,
+                    help="1: keep a permuted copy of the cube for views along axis 1 (one more cube of HBM)")
     ap.add_argument("--oracle-seconds", type=float, default=15.0)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--per-view", action="store_true", help="print each view's march time to stderr")

@@ -346,6 +346,10 @@ int vr_create(int device, vr_ctx** out) {
   vr_ctx* ctx = new (std::nothrow) vr_ctx();
   if (!ctx) return fail(VR_ENOMEM, "out of host memory");
   ctx->device = device;
+  if (const char* m = std::getenv("VR_RING_SLOTS")) {
+    const int k = std::atoi(m);
+    if (k == 2 || k == 3) ctx->ring_nslots = k;
+  }
   if (const char* m = std::getenv("VR_BWD_LAYERS")) {
     const int k = std::atoi(m);
     if (k >= 1 && k <= 16) ctx->bwd_layer_cap = k;

@@ -214,8 +214,26 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         a.slab_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
         ring = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, ring_wpb);
       } else {
+        int32_t waves3 = 0;
         ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
-                           a.ring_slot, ring_wpb);
+                           a.ring_slot, ring_wpb, 3, &waves3);
+        a.ring_nslots = 3;
+        // two LDS slots per wavefront (the next layer's loads no longer overlap
+        // the wavefront's own sampling, but more wavefronts fit): taken where
+        // three leave the unit at 8 wavefronts or fewer and two reach 12
+        // (measured on 24 GiB cubes), or when forced; plain march only
+        const bool plain = !a.mip && a.mc == 0;
+        if (ring && plain && ctx->ring_nslots != 3) {
+          int32_t ax2 = 0, slot2 = 0, wpb2 = 4, waves2 = 0;
+          if (choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, ax2, slot2, wpb2, 2,
+                          &waves2) &&
+              (ctx->ring_nslots == 2 || (waves3 <= 8 && waves2 >= 12))) {
+            a.slab_axis = ax2;
+            a.ring_slot = slot2;
+            ring_wpb = wpb2;
+            a.ring_nslots = 2;
+          }
+        }
       }
     }
     if (!ring && !extras && mode != 1 && !a.mip) {  // (the slab march has no projection mode)

@@ -51,15 +51,17 @@ namespace {
 
 using namespace ring;
 
-constexpr int kSlots = 3;
+constexpr int kSlotsMax = 3;
 
 // SAVE (differentiable forward, whole volume): also store, for every group of
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
 // MIP: maximum intensity projection (no table, no skipping, no saving).
-template <bool ESS, bool SAVE, bool MIP, bool PERSP>
+template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   static_assert(!(PERSP && SAVE), "the checkpointing forward is orthographic");
+  static_assert(!TWO || !(ESS || SAVE), "two slots: the plain march");
+  constexpr int kSlots = TWO ? 2 : 3;
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
   for (int i = threadIdx.x; i < a.M; i += blockDim.x) s_tf[i] = a.tf[i];
@@ -384,14 +386,15 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     for (int k = 0; k < nlay; ++k) {
       if (SAVE && k % sa.K == 0) save_group(k / sa.K, T, j);
       wait_loads();  // V_k and V_{k+1} are in LDS
-      // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished)
+      // start V_{k+2} into the slot V_{k-1} used (cell layer c_{k-1} is finished);
+      // with two slots, into the slot of V_k once c_k is finished
       const int s1 = s0 == kSlots - 1 ? 0 : s0 + 1;
       const int s2 = s1 == kSlots - 1 ? 0 : s1 + 1;
       Window w2;
       if (k + 1 < nlay) {
         const int V2 = V0 + (k + 2) * vstep;
         w2 = window(V2);
-        issue(V2, w2, s_ring + s2 * slot);
+        if (!TWO) issue(V2, w2, s_ring + s2 * slot);
       }
       // lower and upper voxel layer of cell layer c_k
       const int c = up ? Lbeg + k : Lbeg - k;
@@ -427,6 +430,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
           for (int g = k / sa.K + 1; g < ngrp_tile; ++g) save_group(g, T, j);
         break;
       }
+      if (TWO && k + 1 < nlay) issue(V0 + (k + 2) * vstep, w2, s_ring + s0 * slot);
       s0 = s1;
       w0 = w1;
       w1 = w2;
@@ -548,7 +552,8 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
 }  // namespace
 
 size_t ring_lds_bytes(const MarchArgs& a, int wpb) {
-  return sizeof(float4) * (size_t)a.M + sizeof(float) * (size_t)wpb * kSlots * (size_t)a.ring_slot;
+  const int ns = a.ring_nslots == 2 ? 2 : kSlotsMax;
+  return sizeof(float4) * (size_t)a.M + sizeof(float) * (size_t)wpb * ns * (size_t)a.ring_slot;
 }
 
 hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
@@ -564,6 +569,7 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   const dim3 g(grid), b(64 * wpb);
   const size_t lds = ring_lds_bytes(a, wpb);
   if (a.mip && a.mc > 0) return hipErrorInvalidValue;
+  if (a.ring_nslots == 2 && (a.mip || a.mc > 0 || a.cam.persp)) return hipErrorInvalidValue;
   if (a.cam.persp) {
     if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true>), g, b, lds, s, a, none);
     else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, true>), g, b, lds, s, a, none);
@@ -571,6 +577,7 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   } else {
     if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, false>), g, b, lds, s, a, none);
     else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, false>), g, b, lds, s, a, none);
+    else if (a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, false, false, true>), g, b, lds, s, a, none);
     else hipLaunchKernelGGL((k_march_ring<false, false, false, false>), g, b, lds, s, a, none);
   }
   return hipGetLastError();
@@ -579,7 +586,7 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
 hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wpb, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4) ||
-      a.mc != 0 || a.mip != 0 || a.cam.persp != 0 || sa.K < 1 || !sa.ckpt_j)
+      a.mc != 0 || a.mip != 0 || a.cam.persp != 0 || a.ring_nslots == 2 || sa.K < 1 || !sa.ckpt_j)
     return hipErrorInvalidValue;
   const int groups = (a.ntiles + wpb - 1) / wpb;
   const int grid = ((groups + 7) / 8) * 8;

@@ -332,11 +332,11 @@ bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int3
   return found;
 }
 
-int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* waves_per_cu) {
+int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* waves_per_cu, int32_t nslots) {
   const int64_t lds = 160 * 1024;
   int best_w = 1, best_waves = -1;
   for (int w : {4, 2, 1}) {
-    const int64_t per_block = 16 * (int64_t)M + 4 * 3 * (int64_t)w * slot;
+    const int64_t per_block = 16 * (int64_t)M + 4 * (int64_t)nslots * w * slot;
     int64_t blocks = lds / per_block;
     if (blocks * w > max_waves) blocks = max_waves / w;
     const int waves = (int)(blocks * w);
@@ -350,7 +350,8 @@ int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* wa
 }
 
 bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves,
-                 int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb) {
+                 int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb, int32_t nslots,
+                 int32_t* waves_per_cu) {
   const double p = cam.S / (double)cam.W;
   // ray directions to size the window for: the view direction (parallel
   // rays), or the rays of the image's corners and centre (perspective; a
@@ -397,7 +398,7 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
     const double size = pitch * ng;
     if (size > (double)cap || pitch > 256.0) continue;
     int32_t waves = 0;
-    const int w = ring_waves_per_block((int32_t)size, M, max_waves, &waves);
+    const int w = ring_waves_per_block((int32_t)size, M, max_waves, &waves, nslots);
     if (waves < min_waves) continue;
     // window floats per sample (one window per layer, 2 / |db| samples per ray
     // and layer), weighted by the occupancy shortfall
@@ -407,6 +408,7 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
       axis = b;
       slot = (int32_t)size;
       wpb = w;
+      if (waves_per_cu) *waves_per_cu = waves;
       found = true;
     }
   }

@@ -85,7 +85,7 @@ bool choose_slab(const Camera& cam, int32_t tw, int32_t th, int32_t budget, int3
 // Wavefronts per workgroup (1, 2 or 4) for a ring launch: the choice that fits
 // the most wavefronts per compute unit into 160 KB of LDS (M-entry table per
 // workgroup, three slots per wavefront), at most `max_waves` per unit.
-int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* waves_per_cu);
+int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* waves_per_cu, int32_t nslots = 3);
 
 // Ring march for one view (8 x 8 tiles).  For each slab axis (as above) the
 // per-layer window bound -- the box of voxels that the samples of one tile
@@ -95,7 +95,8 @@ int ring_waves_per_block(int32_t slot, int32_t M, int32_t max_waves, int32_t* wa
 // weighted by how far occupancy falls below `want_waves`.  Needs a bound of
 // at most `cap` floats and at least `min_waves` wavefronts per unit.
 bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves,
-                 int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb);
+                 int32_t min_waves, int32_t& axis, int32_t& slot, int32_t& wpb, int32_t nslots = 3,
+                 int32_t* waves_per_cu = nullptr);
 
 // Perspective ring march: the window of a tile depends on its rays' directions
 // and depth, and the kernel picks the slab axis per tile.  From a few sample

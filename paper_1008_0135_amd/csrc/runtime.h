@@ -95,6 +95,7 @@ struct vr_ctx {
   int32_t march_mode = 0;
   int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
   int32_t bwd_layer_cap = 4;  // adjoint on the ring layout: cell layers per checkpoint group, at most
+  int32_t ring_nslots = 0;    // forward ring march (plain orthographic): LDS slots per wavefront, 3 or 2; 0 = by occupancy
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
   struct TuneEntry {
     std::string key;

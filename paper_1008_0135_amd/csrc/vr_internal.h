@@ -206,6 +206,8 @@ struct MarchArgs {
   const uint8_t* mc_clear; // per macrocell [m3][m2][m1]: 1 = opacity 0 over its whole range
   int32_t mc;            // macrocell edge in cells; 0 = no macrocell skipping
   int32_t mcn[3];        // macrocells per axis
+  int32_t ring_nslots;   // ring march: LDS slots per wavefront, 3 (one layer in flight while sampling) or 2
+  int32_t pad3;
 };
 
 struct CompArgs {

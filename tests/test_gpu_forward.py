@@ -242,20 +242,25 @@ def test_c2_full_size_strided_rays(ctx):
 
 
 def _ctx_with_march(mode):
+    """A context with one march forced; "ring2" / "ring3": the ring march with
+    two / three LDS slots per wavefront."""
     import os
-    old = os.environ.get("VR_MARCH")
-    os.environ["VR_MARCH"] = mode
+    env = {"VR_MARCH": "ring", "VR_RING_SLOTS": mode[-1]} if mode in ("ring2", "ring3") else {"VR_MARCH": mode}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         return vr.vr_create(0)
     finally:
-        if old is None:
-            del os.environ["VR_MARCH"]
-        else:
-            os.environ["VR_MARCH"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
 def test_marches_identical():
-    """The LDS-slab, ring and gather marches compute the same samples in the same order."""
+    """The LDS-slab, ring (two or three LDS slots per wavefront) and gather
+    marches compute the same samples in the same order."""
     _say("slab / ring / gather marches: bit-identical images")
     dims = (160, 144, 176)
     vol = synth.cube(*dims, seed=27, n_sources=15, sigma_range=(2.0, 5.0))
@@ -265,7 +270,7 @@ def test_marches_identical():
     imgs = {}
     layouts = {"grid": vr.grid_spec((48, 64, 80)), "mat": vr.grid_spec((48, 64, 80), materialize=True),
                "kd": vr.kd_spec(7), "whole": None}
-    for mode in ("gather", "slab", "ring"):
+    for mode in ("gather", "slab", "ring", "ring2", "ring3"):
         _say(f"  march {mode}")
         c = _ctx_with_march(mode)
         h = _upload(c, vol)
@@ -285,7 +290,7 @@ def test_marches_identical():
     for name in layouts:
         for W in (96, 333):
             a = imgs[("gather", name, W)]
-            for mode in ("slab", "ring"):
+            for mode in ("slab", "ring", "ring2", "ring3"):
                 b = imgs[(mode, name, W)]
                 assert np.array_equal(a, b), (mode, name, W, float(np.abs(a - b).max()))
     mn, mx = float(vol.min()), float(vol.max())
