@@ -4,8 +4,13 @@ Default workload: a 2048 x 2048 x 1536 float32 cube (24 GiB; noise + 4800
 elongated sources + emission band), 256^3 bricks with 1-voxel ghosts and
 per-brick ranges, 1024 x 1024 orthographic frames, 16 seeded random views,
 step 0.5 voxel, grey ramp transfer function (alpha = 0.02 t), early
-termination at opacity 0.99 (per brick, sort-last).  One step renders the 16
-views (march + composite per view) through the C ABI.
+termination at opacity 0.99 (per brick, sort-last).  The cube is also kept as
+a permuted copy (axes 2, 3, 1; built before timing) from which the views
+looking mostly along axis 1 are rendered.  One step renders the 16 views
+(march + composite per view) through the C ABI.  Further legs on the same
+cube and views: perspective projection, maximum intensity projection, early
+termination over the whole ray; then a 64-request batched launch and a
+forward + backward pass of the differentiable path.
 
 Prints one JSON line: Gsamples/s (nominal lattice samples per second), ms per
 step and per frame, the march kernel's HBM roofline fraction (algorithmic
@@ -334,7 +339,8 @@ def main():
         "config": {
             "workload": f"{args.config}: {n1}x{n2}x{n3} f32 cube ({n1 * n2 * n3 * 4 / 2**30:.1f} GiB), "
                         f"{cfg['bricks'][0]}^3 bricks, {W}x{H} frames, {nviews} views/step, step 0.5, "
-                        f"tau 0.99 local ERT, TF {args.tf}" + (", materialised bricks" if args.materialize else ""),
+                        f"tau 0.99 local ERT, TF {args.tf}" + (", materialised bricks" if args.materialize else "")
+                        + (", permuted copy for views along axis 1" if args.twin else ""),
             "volume": [n1, n2, n3], "bricks": list(cfg["bricks"]), "image": [W, H], "views_per_step": nviews,
             "tf": args.tf, "tile": args.tile or 8, "macrocell": args.macrocell, "twin": bool(args.twin),
         },
