@@ -176,6 +176,20 @@ def bench_variants(ctx, h, dims, views_R, W, H, stream):
     return res
 
 
+def brick_transparent(bmin, bmax, tf, vmin, vmax):
+    """A brick is skipped when every table entry its value range can reach
+    (one entry of margin each side) has opacity 0."""
+    M = tf.shape[0]
+
+    def u(x):
+        t = (x - vmin) / (vmax - vmin) if vmax > vmin else 0.0
+        return min(1.0, max(0.0, t)) * (M - 1)
+
+    i0 = max(0, int(np.floor(u(bmin))) - 1)
+    i1 = min(M - 1, int(np.ceil(u(bmax))) + 1)
+    return bool((tf[i0:i1 + 1, 3] == 0).all())
+
+
 def counter_traffic(config):
     """HBM bytes per march launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
@@ -276,21 +290,27 @@ def main():
         vr.vr_render(ctx, h, views, params, out, stream)
     torch.cuda.synchronize()
 
-    # march launches: per-view algorithmic bytes (bricks rendered + brick-image writes)
+    # march launches: per-view algorithmic bytes (interior voxels of the bricks
+    # rendered + brick-image writes), from the host plan (the same rectangles and
+    # the same transparent-brick test as the renderer; no kernel runs for it)
     imgs_per_view = []
+    spec = vr.grid_spec(cfg["bricks"])
     for v in views:
-        imgs, _ = vr.vr_render_bricks(ctx, h, v, params, stream=stream)
+        rects, _ = vr.vr_plan_view((n1, n2, n3), spec, v)
         brick_bytes = 0
         img_bytes = 0
-        for im in imgs:
-            d = bricks[im.brick]
+        count = 0
+        for b, (x0, y0, w, hh) in enumerate(rects):
+            d = bricks[b]
+            if w == 0 or hh == 0 or brick_transparent(d.vmin, d.vmax, tf, vmin, vmax):
+                continue
             vox = 1
             for i in range(3):
                 vox *= (d.hi[i] - d.lo[i] + (1 if d.closed[i] else 0))
             brick_bytes += 4 * vox
-            img_bytes += 16 * im.w * im.h
-        imgs_per_view.append((brick_bytes, img_bytes, len(imgs)))
-    torch.cuda.synchronize()
+            img_bytes += 16 * w * hh
+            count += 1
+        imgs_per_view.append((brick_bytes, img_bytes, count))
 
     if args.per_view:
         vr.vr_set_profiling(ctx, True)
