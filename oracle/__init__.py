@@ -49,7 +49,7 @@ class Scene(C.Structure):
         ("vmin", C.c_double), ("vmax", C.c_double), ("step", C.c_double), ("tau", C.c_double),
         ("nboxes", C.c_int), ("boxes", C.c_void_p), ("grid", C.c_int), ("gb", C.c_int64 * 3),
         ("gnb", C.c_int * 3), ("ert_margin", C.c_double), ("geom_margin", C.c_double),
-        ("mode", C.c_int),
+        ("mode", C.c_int), ("mask", C.c_void_p),
     ]
 
 
@@ -136,7 +136,7 @@ def kd_boxes(dims, nparts):
 
 
 # ---------------------------------------------------------------- rendering
-def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode=0):
+def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode=0, mask=None):
     vol = np.ascontiguousarray(vol, dtype=np.float32)
     tf = np.ascontiguousarray(tf, dtype=np.float32).reshape(-1, 4)
     sc = Scene()
@@ -148,6 +148,12 @@ def _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode
     sc.ert_margin, sc.geom_margin = float(ert_margin), float(geom_margin)
     sc.mode = int(mode)
     keep = [vol, tf]
+    if mask is not None:
+        mask = np.ascontiguousarray(mask, dtype=np.float32).reshape(-1)
+        if mask.shape[0] != vol.shape[0]:
+            raise ValueError("mask needs one weight per index along axis 3")
+        sc.mask = mask.ctypes.data
+        keep.append(mask)
     if bricks is not None:
         dims = (vol.shape[2], vol.shape[1], vol.shape[0])
         if isinstance(bricks, dict) and "grid" in bricks:
@@ -181,14 +187,15 @@ def _views(views, W, H, extent, eye_dist=0.0):
 
 
 def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bricks=None,
-           ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR, eye_dist=0.0):
+           ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR, eye_dist=0.0, mask=None):
     """Render full images.  Returns dict(image [nv][H][W][4] f64, tol, flags, nsamples).
 
     mode=MODE_MIP: maximum intensity projection, (M, M, M, M) per pixel with M the
     largest normalised sample value along the ray (the table is not used).
     eye_dist > 0: perspective camera with the eye at distance eye_dist from the box
-    centre (0: orthographic)."""
-    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode)
+    centre (0: orthographic).  mask: optional weight per index along axis 3 (spectral
+    channels), multiplying each sample's opacity (MIP: its normalised value)."""
+    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode, mask)
     vw = _views(views, W, H, extent, eye_dist)
     nv = len(views)
     img = np.zeros((nv, H, W, 4), np.float64)
@@ -205,9 +212,9 @@ def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bri
 
 def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0.5, tau=0.99,
                 extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR,
-                eye_dist=0.0):
+                eye_dist=0.0, mask=None):
     """Render selected rays (view index, pixel u, pixel v).  Returns dict like ``render``."""
-    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode)
+    sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode, mask)
     vw = _views(views, W, H, extent, eye_dist)
     rv = np.ascontiguousarray(ray_view, np.int32)
     ru = np.ascontiguousarray(ray_u, np.int32)

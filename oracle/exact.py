@@ -15,7 +15,8 @@ evaluated without rounding, sample by sample:
 * lattice t_k = t_in + (k + 1/2) step while t_k < t_out;
 * owner sub-volume by searching the ownership boxes;
 * trilinear value as an explicit 8-corner weighted sum;
-* transfer-function lookup, front-to-back emission-absorption, ERT test;
+* transfer-function lookup (opacity times the channel mask interpolated
+  along axis 3, when one is given), front-to-back emission-absorption, ERT test;
 * per-ray ordering of the partial results by their first sample, then the
   over operator (paper Sec. 2.5).
 
@@ -105,7 +106,7 @@ def _sqrt(q: Fr) -> Fr:
 
 
 def render(vol, tf, R, W, H, extent, vmin, vmax, step=0.5, tau=0.99, boxes=None,
-           dvol=None, dtf=None, mip=False, eye_dist=0.0):
+           dvol=None, dtf=None, mip=False, eye_dist=0.0, mask=None):
     """Exact image [H][W][4] as Fractions (or Duals when dvol/dtf give a direction).
 
     mip=True: maximum intensity projection (M, M, M, M), M = max over samples of
@@ -164,6 +165,16 @@ def render(vol, tf, R, W, H, extent, vmin, vmax, step=0.5, tau=0.99, boxes=None,
                     acc = term if acc is None else acc + term
         return acc
 
+    mk = None if mask is None else [_fr(x) for x in mask]
+
+    def mask_at(p):
+        """Channel weight: the mask interpolated along axis 3 with the trilinear weight."""
+        if mk is None:
+            return Fr(1)
+        k = max(0, min(n[2] - 2, math.floor(p[2])))
+        f = p[2] - k
+        return (1 - f) * mk[k] + f * mk[k + 1]
+
     def classify(val):
         vv = val.v if use_dual else val
         if hi_w > lo_w:
@@ -220,7 +231,7 @@ def render(vol, tf, R, W, H, extent, vmin, vmax, step=0.5, tau=0.99, boxes=None,
                     if bx is not None and _owner(p, bx) is None:
                         raise AssertionError("sample inside the volume owned by no box")
                     s_raw = (value_at(p) - lo_w) / (hi_w - lo_w) if hi_w > lo_w else Fr(0)
-                    m = max(m, min(Fr(1), max(Fr(0), s_raw)))
+                    m = max(m, min(Fr(1), max(Fr(0), s_raw)) * mask_at(p))
                     k += 1
                 row.append((m, m, m, m))
                 continue
@@ -242,6 +253,7 @@ def render(vol, tf, R, W, H, extent, vmin, vmax, step=0.5, tau=0.99, boxes=None,
                     chains[key] = ch
                 if not ch[2]:
                     r, g, b, a = classify(value_at(p))
+                    a = a * mask_at(p)
                     Tv = ch[1]
                     ch[0] = [ch[0][0] + Tv * a * r, ch[0][1] + Tv * a * g, ch[0][2] + Tv * a * b]
                     ch[1] = Tv * (1 - a)

@@ -31,6 +31,11 @@
  *     x = ((u+1/2)/W - 1/2) S, y = ((v+1/2)/H - 1/2) S H/W with S the extent
  *     (box diagonal when 0), the ray starts at c + x e1 + y e2 - S e3 and runs
  *     along e3;
+ *   - spectral-channel masking (the user may enable or disable spectral channels,
+ *     Sec. 2.2): an optional weight m[k] in [0, 1] per index k along axis 3 (the
+ *     spectral axis); a sample's opacity (its normalised value under MIP) is
+ *     multiplied by m interpolated linearly along axis 3 with the sample's own
+ *     trilinear weight, (1 - f3) m[i3] + f3 m[i3 + 1];
  *   - perspective camera (the projection a render request may carry, Sec. 2.2;
  *     evaluated in Sec. 3): the eye sits at c - D e3 (D = eye distance, larger
  *     than half the box diagonal so the whole box lies in front of it), the
@@ -94,6 +99,7 @@ typedef struct {
   double ert_margin;   /* opacity window around tau treated as a tie */
   double geom_margin;  /* distance (voxels) treated as a geometric tie */
   int mode;            /* OR_MODE_DVR or OR_MODE_MIP */
+  const float *mask;   /* [n3] channel weights along axis 3, or NULL (all 1) */
 } or_scene;
 
 /*
@@ -194,6 +200,13 @@ static double trilinear(const or_scene *sc, const double p[3], int64_t i0[3], do
         v += w * voxel(sc, i0[0] + dx, i0[1] + dy, i0[2] + dz);
       }
   return v;
+}
+
+/* Channel weight at a sample: the mask interpolated along axis 3 with the
+ * sample's trilinear weight (1 without a mask). */
+static double mask_at(const or_scene *sc, const int64_t i0[3], const double f[3]) {
+  if (!sc->mask) return 1.0;
+  return (1.0 - f[2]) * (double)sc->mask[i0[2]] + f[2] * (double)sc->mask[i0[2] + 1];
 }
 
 /* Transfer-function lookup: value -> non-premultiplied RGBA. */
@@ -333,6 +346,7 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
       double s = sc->vmax > sc->vmin ? (val - sc->vmin) / (sc->vmax - sc->vmin) : 0.0;
       if (s < 0.0) s = 0.0;
       if (s > 1.0) s = 1.0;
+      s *= mask_at(sc, i0, f);
       if (s > m) m = s;
     }
     for (int c = 0; c < 4; c++) out[c] = m;
@@ -364,6 +378,7 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
     int ti;
     double val = trilinear(sc, p, i0, f);
     classify(sc, val, rgba, &ti, &tw, &sraw);
+    rgba[3] *= mask_at(sc, i0, f);
     chain_feed(sc, ch, rgba);
     if (sc->nboxes == 0 && sc->tau < 1.0 && ch->hi_seen) break;
   }
@@ -505,7 +520,7 @@ int or_render_images(const or_scene *sc, const or_view *views, int nviews, doubl
  */
 int or_render_grad(const or_scene *sc, const or_view *view, const double *grad_out, double *grad_tf,
                    double *grad_vol, double *out, int nthreads) {
-  if (!scene_ok(sc) || sc->nboxes != 0) return -1;
+  if (!scene_ok(sc) || sc->nboxes != 0 || sc->mask) return -1;
   set_threads(nthreads);
   camera cam;
   make_camera(sc, view, &cam);
