@@ -257,6 +257,22 @@ int vr_volume_macrocell_info(const vr_volume *vol, int32_t *edge, int64_t count[
 int vr_tf_set(vr_ctx *ctx, const float *rgba, int32_t m, double vmin, double vmax, int src_on_device,
               uintptr_t stream);
 
+/*
+ * Spectral-channel mask (paper Sec. 2.2: the user enables or disables spectral
+ * channels).  `mask` is [n] float32 weights in [0, 1], one per index along
+ * axis 3 (the spectral axis; 0 disables a channel), on the host
+ * (src_on_device = 0) or the device (1, copied on `stream`, then validated on
+ * the host).  Every sample's opacity (under VR_MODE_MIP its normalised value)
+ * is multiplied by the mask interpolated linearly along axis 3 with the
+ * sample's own trilinear weight: (1 - f3) mask[i3] + f3 mask[i3 + 1].  mask =
+ * NULL or n = 0 removes it.  A render with a mask needs n equal to the volume's
+ * axis-3 size (else VR_EINVAL); the adjoint and the batched launch do not take
+ * a mask (VR_EUNSUPPORTED while one is set).
+ * Errors: VR_EINVAL (n < 0, n in {1} or > 2^20, a weight outside [0, 1] or non-finite),
+ * VR_EHIP.
+ */
+int vr_mask_set(vr_ctx *ctx, const float *mask, int32_t n, int src_on_device, uintptr_t stream);
+
 /* ------------------------------------------------------------------ rendering */
 /*
  * Render `nviews` views into out ([nviews][H][W][4] float32, device; all views

@@ -106,6 +106,7 @@ _SIGS = {
     "vr_volume_brick_info": (_I, [_P, _P, _P]),
     "vr_volume_macrocell_info": (_I, [_P, _P, _P, _P]),
     "vr_tf_set": (_I, [_P, _P, _I32, _D, _D, _I, _U]),
+    "vr_mask_set": (_I, [_P, _P, _I32, _I, _U]),
     "vr_render": (_I, [_P, _P, _P, _I32, _P, _P, _U, _P]),
     "vr_render_bricks": (_I, [_P, _P, _P, _P, _P, _P, _P, _U]),
     "vr_composite": (_I, [_P, _P, _I32, _P, _I32, _I32, _P, _U]),
@@ -302,6 +303,19 @@ def vr_volume_macrocell_info(vol):
     _check(lib().vr_volume_macrocell_info(vol, C.byref(edge), cnt, mm.ctypes.data_as(C.c_void_p)),
            "vr_volume_macrocell_info")
     return edge.value, (c1, c2, c3), mm
+
+
+def vr_mask_set(ctx, mask, stream=None):
+    """Spectral-channel weights along axis 3 (numpy or torch, host or device); None removes the mask."""
+    if mask is None:
+        _check(lib().vr_mask_set(ctx, None, 0, 0, _stream(stream)), "vr_mask_set")
+        return
+    if hasattr(mask, "is_cuda") and mask.is_cuda:
+        m = mask.contiguous().float()
+        _check(lib().vr_mask_set(ctx, _ptr(m), int(m.numel()), 1, _stream(stream)), "vr_mask_set")
+        return
+    a = np.ascontiguousarray(mask, dtype=np.float32).reshape(-1)
+    _check(lib().vr_mask_set(ctx, a.ctypes.data_as(C.c_void_p), int(a.size), 0, _stream(stream)), "vr_mask_set")
 
 
 def vr_tf_set(ctx, tf, vmin=0.0, vmax=0.0, stream=None):

@@ -241,6 +241,8 @@ void fill_march_common(MarchArgs& a, const vr_volume* vol, const vr_params* p, d
   a.M = M;
   a.tf = tf;
   a.mip = p->mode == VR_MODE_MIP ? 1 : 0;
+  a.mask_axis = vol->spectral_axis;
+  a.mask = nullptr;  // set by the callers that take a mask
   a.tile_w = p->tile ? p->tile : 8;
   a.tile_h = 64 / a.tile_w;
 }
@@ -385,6 +387,7 @@ int vr_destroy(vr_ctx* ctx) {
   }
   if (ctx->d_tf) (void)hipFree(ctx->d_tf);
   if (ctx->d_tf_nz) (void)hipFree(ctx->d_tf_nz);
+  if (ctx->d_mask) (void)hipFree(ctx->d_mask);
   if (ctx->d_arena) (void)hipFree(ctx->d_arena);
   if (ctx->d_small) (void)hipFree(ctx->d_small);
   if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
@@ -727,6 +730,7 @@ static int make_twin(vr_volume* vol, int32_t macrocell, hipStream_t s) {
     t->n[0] = n[1];
     t->n[1] = n[2];
     t->n[2] = n[0];
+    t->spectral_axis = 1;  // the volume's axis 3 is the copy's axis 2
     if (hipMalloc(&t->data, sizeof(float) * (size_t)(n[0] * n[1] * n[2]) + 256) != hipSuccess) {
       (void)hipGetLastError();
       delete t;
@@ -801,6 +805,45 @@ int vr_volume_macrocell_info(const vr_volume* vol, int32_t* edge, int64_t count[
                      hipMemcpyDeviceToHost));
   }
   return VR_OK;
+}
+
+// ---------------------------------------------------------------- spectral-channel mask
+int vr_mask_set(vr_ctx* ctx, const float* mask, int32_t n, int src_on_device, uintptr_t stream) {
+  clear_error();
+  if (!ctx) return fail(VR_EINVAL, "ctx is NULL");
+  if (!mask || n == 0) {
+    ctx->mask_n = 0;
+    return VR_OK;
+  }
+  if (n < 2 || n > (1 << 20)) return fail(VR_EINVAL, "mask length %d outside [2, 2^20]", n);
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float> h((size_t)n);
+  if (src_on_device) {
+    VR_HIP(hipMemcpyAsync(h.data(), mask, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, s));
+    VR_HIP(hipStreamSynchronize(s));
+  } else {
+    std::memcpy(h.data(), mask, sizeof(float) * (size_t)n);
+  }
+  for (int32_t i = 0; i < n; i++)
+    if (!(h[i] >= 0.f && h[i] <= 1.f)) return fail(VR_EINVAL, "mask[%d] = %g outside [0, 1]", i, (double)h[i]);
+  VR_TRY(ctx_begin(ctx, s));
+  if (n > ctx->mask_cap) {
+    if (ctx->d_mask) VR_HIP(hipFree(ctx->d_mask));
+    ctx->d_mask = nullptr;
+    ctx->mask_cap = 0;
+    if (hipMalloc(&ctx->d_mask, sizeof(float) * (size_t)n) != hipSuccess) {
+      (void)hipGetLastError();
+      ctx->d_mask = nullptr;
+      return fail(VR_ENOMEM, "hipMalloc for the mask failed");
+    }
+    ctx->mask_cap = n;
+  }
+  // synchronous copy: the host vector dies with this call
+  VR_HIP(hipMemcpyAsync(ctx->d_mask, h.data(), sizeof(float) * (size_t)n, hipMemcpyHostToDevice, s));
+  VR_HIP(hipStreamSynchronize(s));
+  ctx->mask_n = n;
+  return ctx_end(ctx, s);
 }
 
 // ---------------------------------------------------------------- transfer function

@@ -78,6 +78,7 @@ static double tile_cost(const vr_volume* v, const vr_view& view, double step) {
 int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, vr_batch** cache,
                  hipStream_t s, int32_t force_blocks) {
   if (p && p->mode != VR_MODE_DVR) return fail(VR_EUNSUPPORTED, "batched rendering implements VR_MODE_DVR only");
+  if (ctx->mask_n > 0) return fail(VR_EUNSUPPORTED, "batched rendering takes no channel mask");
   for (int32_t i = 0; i < n; i++) {
     const vr_request& r = reqs[i];
     if (!r.vol || !r.tf || !r.out) return fail(VR_EINVAL, "request %d: vol, tf and out must be non-NULL", i);

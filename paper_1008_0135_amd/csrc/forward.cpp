@@ -109,6 +109,12 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   vr_params pt = *p;
   pt.tile = tuned_tile;
   fill_march_common(base, vol, &pt, vmin, vmax, ctx->d_tf, ctx->tf_m);
+  if (ctx->mask_n > 0) {
+    if (vol->n[vol->spectral_axis] != ctx->mask_n)
+      return fail(VR_EINVAL, "mask length %d differs from the volume's axis-3 size %lld", ctx->mask_n,
+                  (long long)vol->n[vol->spectral_axis]);
+    base.mask = ctx->d_mask;
+  }
   if (!extras) VR_TRY(prepare_macrocells(ctx, vol, p, vmin, vmax, base, s));
   const int32_t tw = base.tile_w, th = base.tile_h;
   // opacity tested over the whole ray: bricks marched in front-to-back waves
@@ -222,7 +228,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         // the wavefront's own sampling, but more wavefronts fit): taken where
         // three leave the unit at 8 wavefronts or fewer and two reach 12
         // (measured on 24 GiB cubes), or when forced; plain march only
-        const bool plain = !a.mip && a.mc == 0;
+        const bool plain = !a.mip && a.mc == 0 && !a.mask;
         if (ring && plain && ctx->ring_nslots != 3) {
           int32_t ax2 = 0, slot2 = 0, wpb2 = 4, waves2 = 0;
           if (choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, ax2, slot2, wpb2, 2,
@@ -236,7 +242,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         }
       }
     }
-    if (!ring && !extras && mode != 1 && !a.mip) {  // (the slab march has no projection mode)
+    if (!ring && !extras && mode != 1 && !a.mip && !a.mask) {  // (the slab march has no MIP and no mask)
       lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
       // rays nearly parallel to axis 1 need a wider slab box: retry with twice the budget
       if (!lds && budget < 8192 && choose_slab(cams[v], a.tile_w, a.tile_h, 8192, a.slab_axis, a.slab_T)) {

@@ -115,6 +115,7 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
                       float* out, hipStream_t s, vr_state** save) {
   if (vol->bricked) return fail(VR_EUNSUPPORTED, "saving forward state needs an unbricked volume");
   if (p->mode != VR_MODE_DVR) return fail(VR_EUNSUPPORTED, "the adjoint implements VR_MODE_DVR only");
+  if (ctx->mask_n > 0) return fail(VR_EUNSUPPORTED, "the adjoint takes no channel mask (vr_mask_set(ctx, NULL, 0))");
   if (p->ckpt_K > 64) return fail(VR_EINVAL, "ckpt_K must be <= 64");
   const int32_t W = views[0].W, H = views[0].H;
   VR_TRY(ctx_begin(ctx, s));

@@ -57,10 +57,11 @@ constexpr int kSlotsMax = 3;
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
 // MIP: maximum intensity projection (no table, no skipping, no saving).
-template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false>
+template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false, bool MASK = false>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   static_assert(!(PERSP && SAVE), "the checkpointing forward is orthographic");
   static_assert(!TWO || !(ESS || SAVE), "two slots: the plain march");
+  static_assert(!(MASK && (SAVE || TWO)), "the channel mask: three-slot forward marches");
   constexpr int kSlots = TWO ? 2 : 3;
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
@@ -315,10 +316,14 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
       const float val = trilerp(p[0], p[1], p[ysl], p[ysl + 1], p[zsl], p[zsl + 1], p[zsl + ysl], p[zsl + ysl + 1], c);
       ++j;
       if (MIP) {
-        mx = fmaxf(mx, norm_value(val, a.vmin, a.inv_range));
+        float s = norm_value(val, a.vmin, a.inv_range);
+        if constexpr (MASK) s *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], c);
+        mx = fmaxf(mx, s);
         if (j >= cnt || mx >= 1.f) done = true;
       } else {
-        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        Classified k = classify(val, a.vmin, a.inv_range, a.M, s_tf);
+        if constexpr (MASK) k.a *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], c);
+        accumulate(k, Cr, Cg, Cb, T);
         if (j >= cnt || 1.f - T >= a.tau) done = true;
       }
     }
@@ -418,10 +423,14 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
                              : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
         ++j;
         if (MIP) {
-          mx = fmaxf(mx, norm_value(val, a.vmin, a.inv_range));
+          float s = norm_value(val, a.vmin, a.inv_range);
+          if constexpr (MASK) s *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], cl);
+          mx = fmaxf(mx, s);
           if (j >= cnt || mx >= 1.f) done = true;
         } else {
-          accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+          Classified k = classify(val, a.vmin, a.inv_range, a.M, s_tf);
+          if constexpr (MASK) k.a *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], cl);
+          accumulate(k, Cr, Cg, Cb, T);
           if (j >= cnt || 1.f - T >= a.tau) done = true;
         }
       }
@@ -535,7 +544,9 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
         const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
         const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
                              : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
-        accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+        Classified k = classify(val, a.vmin, a.inv_range, a.M, s_tf);
+        if constexpr (MASK) k.a *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], cl);
+        accumulate(k, Cr, Cg, Cb, T);
         ++j;
         if (j >= cnt || 1.f - T >= a.tau) done = true;
       }
@@ -570,6 +581,20 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   const size_t lds = ring_lds_bytes(a, wpb);
   if (a.mip && a.mc > 0) return hipErrorInvalidValue;
   if (a.ring_nslots == 2 && (a.mip || a.mc > 0 || a.cam.persp)) return hipErrorInvalidValue;
+  if (a.mask) {
+    // the channel mask lives in instantiations of its own (three slots)
+    if (a.ring_nslots == 2) return hipErrorInvalidValue;
+    if (a.cam.persp) {
+      if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true, false, true>), g, b, lds, s, a, none);
+      else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, true, false, true>), g, b, lds, s, a, none);
+      else hipLaunchKernelGGL((k_march_ring<false, false, false, true, false, true>), g, b, lds, s, a, none);
+    } else {
+      if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, false, false, true>), g, b, lds, s, a, none);
+      else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, false, false, true>), g, b, lds, s, a, none);
+      else hipLaunchKernelGGL((k_march_ring<false, false, false, false, false, true>), g, b, lds, s, a, none);
+    }
+    return hipGetLastError();
+  }
   if (a.cam.persp) {
     if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true>), g, b, lds, s, a, none);
     else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, true>), g, b, lds, s, a, none);

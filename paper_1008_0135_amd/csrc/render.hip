@@ -41,7 +41,7 @@ __device__ __forceinline__ int xcd_block(int nblk) {
   return (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
 }
 
-template <int TW, bool MIP>
+template <int TW, bool MIP, bool MASK>
 __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   extern __shared__ float4 s_tf[];
   for (int i = threadIdx.x; i < a.M; i += 256) s_tf[i] = a.tf[i];
@@ -104,10 +104,14 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         const f2u a00 = ld_pair(p), a01 = ld_pair(p + ys), a10 = ld_pair(p + zs), a11 = ld_pair(p + zs + ys);
         const float val = trilerp(a00.x, a00.y, a01.x, a01.y, a10.x, a10.y, a11.x, a11.y, c);
         if (MIP) {
-          mx = fmaxf(mx, norm_value(val, a.vmin, a.inv_range));
+          float s = norm_value(val, a.vmin, a.inv_range);
+          if constexpr (MASK) s *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], c);
+          mx = fmaxf(mx, s);
           if (mx >= 1.f) break;
         } else {
-          accumulate(classify(val, a.vmin, a.inv_range, a.M, s_tf), Cr, Cg, Cb, T);
+          Classified k = classify(val, a.vmin, a.inv_range, a.M, s_tf);
+          if constexpr (MASK) k.a *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], c);
+          accumulate(k, Cr, Cg, Cb, T);
           if (1.f - T >= a.tau) break;
         }
       }
@@ -175,21 +179,21 @@ hipError_t launch_march(const MarchArgs& a, hipStream_t s) {
   const int nblk = (a.ntiles + 3) / 4;
   const int grid = ((nblk + 7) / 8) * 8;
   const size_t lds = sizeof(float4) * (size_t)a.M;
-  if (a.mip) {
-    switch (a.tile_w) {
-      case 8: hipLaunchKernelGGL((k_march<8, true>), dim3(grid), dim3(256), lds, s, a); break;
-      case 16: hipLaunchKernelGGL((k_march<16, true>), dim3(grid), dim3(256), lds, s, a); break;
-      case 4: hipLaunchKernelGGL((k_march<4, true>), dim3(grid), dim3(256), lds, s, a); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    switch (a.tile_w) {
-      case 8: hipLaunchKernelGGL((k_march<8, false>), dim3(grid), dim3(256), lds, s, a); break;
-      case 16: hipLaunchKernelGGL((k_march<16, false>), dim3(grid), dim3(256), lds, s, a); break;
-      case 4: hipLaunchKernelGGL((k_march<4, false>), dim3(grid), dim3(256), lds, s, a); break;
-      default: return hipErrorInvalidValue;
-    }
+#define VR_LAUNCH_GATHER(MIPV, MASKV)                                                                        \
+  switch (a.tile_w) {                                                                                     \
+    case 8: hipLaunchKernelGGL((k_march<8, MIPV, MASKV>), dim3(grid), dim3(256), lds, s, a); break;       \
+    case 16: hipLaunchKernelGGL((k_march<16, MIPV, MASKV>), dim3(grid), dim3(256), lds, s, a); break;     \
+    case 4: hipLaunchKernelGGL((k_march<4, MIPV, MASKV>), dim3(grid), dim3(256), lds, s, a); break;       \
+    default: return hipErrorInvalidValue;                                                                 \
   }
+  if (a.mask) {
+    if (a.mip) VR_LAUNCH_GATHER(true, true)
+    else VR_LAUNCH_GATHER(false, true)
+  } else {
+    if (a.mip) VR_LAUNCH_GATHER(true, false)
+    else VR_LAUNCH_GATHER(false, false)
+  }
+#undef VR_LAUNCH_GATHER
   return hipGetLastError();
 }
 

@@ -49,6 +49,9 @@ struct vr_ctx {
   std::vector<float> h_tf;
   double tf_vmin = 0.0, tf_vmax = 0.0;
   bool tf_set = false;
+  // spectral-channel mask: weights along the volume's axis 3 (mask_n = 0: none)
+  float* d_mask = nullptr;
+  int32_t mask_n = 0, mask_cap = 0;
   uint64_t tf_version = 0;
   int32_t* d_tf_nz = nullptr;  // [M + 1] prefix count of entries with opacity != 0
   int32_t tf_nz_cap = 0;
@@ -136,6 +139,7 @@ struct vr_volume {
   // permuted copy (axes 1, 2, 3 = this volume's axes 2, 3, 1), bricked with the
   // permuted partition, for views that look along axis 1 (owned; or null)
   vr_volume* twin = nullptr;
+  int32_t spectral_axis = 2;  // the axis the channel mask runs along (1 in the permuted copy)
 };
 
 namespace vr {

@@ -28,6 +28,7 @@ struct Cell {
 // clamp(floor(q), lo, hi) == floor(clamp(q, lo, hi)) for integer bounds, and the
 // clamp of q is one v_med3_f32; the fraction reuses the floored float.
 __device__ __forceinline__ Cell cell_of(const SamplePos& q, const DevBrick& br) {
+#pragma clang fp contract(off)
   Cell c;
   const float fx = floorf(__builtin_amdgcn_fmed3f(q.x, (float)br.clo[0], (float)br.chi[0]));
   const float fy = floorf(__builtin_amdgcn_fmed3f(q.y, (float)br.clo[1], (float)br.chi[1]));
@@ -60,6 +61,9 @@ struct Classified {
 };
 
 __device__ __forceinline__ Classified classify(float val, float vmin, float inv_range, int M, const float4* s_tf) {
+  // no contraction: every kernel (and every inlining context) must round the
+  // table coordinate and weight alike, or the marches would differ in bits
+#pragma clang fp contract(off)
   Classified k;
   k.sraw = (val - vmin) * inv_range;
   const float s = fminf(fmaxf(k.sraw, 0.f), 1.f);
@@ -77,11 +81,25 @@ __device__ __forceinline__ Classified classify(float val, float vmin, float inv_
 // Normalised value clamped to [0, 1] (the table coordinate before scaling by
 // M - 1): what maximum intensity projection keeps the largest of.
 __device__ __forceinline__ float norm_value(float val, float vmin, float inv_range) {
+#pragma clang fp contract(off)
   return fminf(fmaxf((val - vmin) * inv_range, 0.f), 1.f);
+}
+
+// Channel weight of a sample: the mask interpolated along its axis (2, or 1 in
+// the permuted copy) with the sample's trilinear weight; 1 without a mask.
+// lo: the brick's origin along that axis (cell indices are brick-local).
+__device__ __forceinline__ float channel_weight(const float* mask, int axis, int lo, const Cell& c) {
+#pragma clang fp contract(off)
+  if (!mask) return 1.f;
+  const int i = lo + (axis == 2 ? c.iz : c.iy);
+  const float w = axis == 2 ? c.wz : c.wy;
+  const float m0 = mask[i], m1 = mask[i + 1];
+  return fmaf(w, m1 - m0, m0);
 }
 
 // One front-to-back emission-absorption step: C += T a rgb, T *= (1 - a).
 __device__ __forceinline__ void accumulate(const Classified& k, float& Cr, float& Cg, float& Cb, float& T) {
+#pragma clang fp contract(off)
   const float Ta = T * k.a;
   Cr = fmaf(Ta, k.r, Cr);
   Cg = fmaf(Ta, k.g, Cg);

@@ -207,7 +207,8 @@ struct MarchArgs {
   int32_t mc;            // macrocell edge in cells; 0 = no macrocell skipping
   int32_t mcn[3];        // macrocells per axis
   int32_t ring_nslots;   // ring march: LDS slots per wavefront, 3 (one layer in flight while sampling) or 2
-  int32_t pad3;
+  int32_t mask_axis;     // axis of the channel mask (2, or 1 in the permuted copy)
+  const float* mask;     // channel weights along mask_axis (global indices), or null
 };
 
 struct CompArgs {
