@@ -236,6 +236,37 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
       double R0 = 0.0, R1 = 0.0, R2 = 0.0, Q = 0.0;
       const int ngrp = (nlay + L - 1) / L;
       const int npix = ba.npix;
+      // Consecutive samples of a ray mostly fall in the same table interval and
+      // often in the same cell: their table- and voxel-gradient terms are summed
+      // in registers and added to LDS once per run (far fewer atomics on the
+      // few table entries every lane of the tile hits)
+      int ti = -1;  // table interval of the pending sums
+      float run_tf[8];  // a run is a few samples: float sums lose nothing the tolerance sees
+      auto flush_tf = [&]() {
+        if (ti >= 0) {
+          double* e0 = s_gtf + 4 * ti;
+          for (int q = 0; q < 8; ++q) atomicAdd(e0 + q, (double)run_tf[q]);
+          ti = -1;
+        }
+      };
+      int vl = -1, vu = -1;  // LDS offsets of the pending cell's lower and upper corner rows
+      float va[8];
+      auto flush_vox = [&]() {
+        if (vl >= 0) {
+          float* p = s_grad + vl;
+          float* q = s_grad + vu;
+          if (by) {  // dy selects the layer, dz the row
+            atomicAdd(p, va[0]); atomicAdd(p + 1, va[1]); atomicAdd(q, va[2]); atomicAdd(q + 1, va[3]);
+            atomicAdd(p + pitch, va[4]); atomicAdd(p + pitch + 1, va[5]);
+            atomicAdd(q + pitch, va[6]); atomicAdd(q + pitch + 1, va[7]);
+          } else {   // dz selects the layer, dy the row
+            atomicAdd(p, va[0]); atomicAdd(p + 1, va[1]); atomicAdd(p + pitch, va[2]);
+            atomicAdd(p + pitch + 1, va[3]); atomicAdd(q, va[4]); atomicAdd(q + 1, va[5]);
+            atomicAdd(q + pitch, va[6]); atomicAdd(q + pitch + 1, va[7]);
+          }
+          vl = -1;
+        }
+      };
 
       for (int g = ngrp - 1; g >= 0; --g) {
         const int k0 = g * L, k1 = min(nlay, k0 + L);  // cell layers k0 .. k1 - 1
@@ -315,15 +346,19 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
           R2 = fma(S.a, S.b, om * R2);
           Q = fma(om, Q, S.a);
           const double w1 = S.w, w0 = 1.0 - S.w;
-          double* e0 = s_gtf + 4 * S.i;
-          atomicAdd(e0 + 0, w0 * gr);
-          atomicAdd(e0 + 1, w0 * gg);
-          atomicAdd(e0 + 2, w0 * gb);
-          atomicAdd(e0 + 3, w0 * ga);
-          atomicAdd(e0 + 4, w1 * gr);
-          atomicAdd(e0 + 5, w1 * gg);
-          atomicAdd(e0 + 6, w1 * gb);
-          atomicAdd(e0 + 7, w1 * ga);
+          if (S.i != ti) {
+            flush_tf();
+            ti = S.i;
+            for (int q = 0; q < 8; ++q) run_tf[q] = 0.f;
+          }
+          run_tf[0] += (float)(w0 * gr);
+          run_tf[1] += (float)(w0 * gg);
+          run_tf[2] += (float)(w0 * gb);
+          run_tf[3] += (float)(w0 * ga);
+          run_tf[4] += (float)(w1 * gr);
+          run_tf[5] += (float)(w1 * gg);
+          run_tf[6] += (float)(w1 * gb);
+          run_tf[7] += (float)(w1 * ga);
           if (gvol && S.sraw > 0.0 && S.sraw < 1.0) {
             const float4 t0f = s_tf[S.i], t1f = s_tf[S.i + 1];
             const double du = gr * ((double)t1f.x - (double)t0f.x) + gg * ((double)t1f.y - (double)t0f.y) +
@@ -336,17 +371,13 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
                                    (float)(gv * x1 * y1 * z0), (float)(gv * x0 * y0 * z1), (float)(gv * x1 * y0 * z1),
                                    (float)(gv * x0 * y1 * z1), (float)(gv * x1 * y1 * z1)};
               if (lofs >= 0) {
-                float* p = s_grad + lofs;
-                float* q = s_grad + uofs;
-                if (by) {  // dy selects the layer, dz the row
-                  atomicAdd(p, cw[0]); atomicAdd(p + 1, cw[1]); atomicAdd(q, cw[2]); atomicAdd(q + 1, cw[3]);
-                  atomicAdd(p + pitch, cw[4]); atomicAdd(p + pitch + 1, cw[5]);
-                  atomicAdd(q + pitch, cw[6]); atomicAdd(q + pitch + 1, cw[7]);
-                } else {   // dz selects the layer, dy the row
-                  atomicAdd(p, cw[0]); atomicAdd(p + 1, cw[1]); atomicAdd(p + pitch, cw[2]);
-                  atomicAdd(p + pitch + 1, cw[3]); atomicAdd(q, cw[4]); atomicAdd(q + 1, cw[5]);
-                  atomicAdd(q + pitch, cw[6]); atomicAdd(q + pitch + 1, cw[7]);
+                if (lofs != vl) {
+                  flush_vox();
+                  vl = lofs;
+                  vu = uofs;
+                  for (int q = 0; q < 8; ++q) va[q] = 0.f;
                 }
+                for (int q = 0; q < 8; ++q) va[q] += cw[q];
               } else {
                 float* q = gvol + (c.iz * zsl + c.iy * ysl + c.ix);
                 unsafeAtomicAdd(q, cw[0]);
@@ -361,6 +392,7 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
             }
           }
         }
+        flush_vox();
         // add the group's gradient windows to the volume: rows contiguous along axis 1
         if (inl && gvol) {
           __builtin_amdgcn_wave_barrier();
@@ -383,6 +415,7 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       }
+      flush_tf();
     }
   }
   __syncthreads();
