@@ -348,6 +348,16 @@ int vr_create(int device, vr_ctx** out) {
   vr_ctx* ctx = new (std::nothrow) vr_ctx();
   if (!ctx) return fail(VR_ENOMEM, "out of host memory");
   ctx->device = device;
+  if (const char* m = std::getenv("VR_TILE_ORDER")) {
+    if (!std::strcmp(m, "row")) ctx->tile_order = 0;
+    if (!std::strcmp(m, "col")) ctx->tile_order = 1;
+    int bw = 0, bh = 0;
+    if (std::sscanf(m, "blk%dx%d", &bw, &bh) == 2 && bw >= 1 && bh >= 1 && bw * bh <= 64) {
+      ctx->tile_order = 2;
+      ctx->tile_bw = bw;
+      ctx->tile_bh = bh;
+    }
+  }
   if (const char* m = std::getenv("VR_RING_SLOTS")) {
     const int k = std::atoi(m);
     if (k == 2 || k == 3) ctx->ring_nslots = k;

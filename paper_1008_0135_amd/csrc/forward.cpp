@@ -242,6 +242,11 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         }
       }
     }
+    if (ring) {
+      a.tile_order = ctx->tile_order;
+      a.tile_bw = ctx->tile_bw;
+      a.tile_bh = ctx->tile_bh;
+    }
     if (!ring && !extras && mode != 1 && !a.mip && !a.mask) {  // (the slab march has no MIP and no mask)
       lds = choose_slab(cams[v], a.tile_w, a.tile_h, budget, a.slab_axis, a.slab_T);
       // rays nearly parallel to axis 1 need a wider slab box: retry with twice the budget

@@ -88,8 +88,47 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   const DevBrickView bvw = a.bv[lo];
   const DevBrick br = a.bricks[bvw.brick];
+  // tile numbering inside the brick's rectangle.  Tiles started together run
+  // at about the same layer; the L2 keeps a line only a few microseconds, so
+  // lines two windows share (the partial 128-byte ends of rows, the halo
+  // rows) are fetched once only when the two tiles are close in this order.
+  // Blocks of tiles put neighbours on both image axes close, whichever way
+  // the view turns the image against the storage axes.
   const int t = tile - bvw.tile_begin;
-  const int tx = t % bvw.tiles_x, ty = t / bvw.tiles_x;
+  int tx, ty;
+  if (a.tile_order == 1) {
+    const int th = (bvw.h + 7) >> 3;
+    tx = t / th;
+    ty = t - tx * th;
+  } else if (a.tile_order == 2) {
+    // blocks of bw x bh tiles in row order (tiles in a block in row order),
+    // then the tiles right of the last whole block column, then those below
+    // the last whole block row
+    const int tw = bvw.tiles_x, th = (bvw.h + 7) >> 3, bw = a.tile_bw, bh = a.tile_bh;
+    const int fw = tw / bw, fh = th / bh, nfull = fw * fh * bw * bh;
+    if (t < nfull) {
+      const int q = t / (bw * bh), r = t - q * (bw * bh), qy = q / fw;
+      const int ry = r / bw;
+      tx = (q - qy * fw) * bw + (r - ry * bw);
+      ty = qy * bh + ry;
+    } else {
+      int r = t - nfull;
+      const int rw = tw - fw * bw;
+      if (r < rw * th) {
+        ty = r / rw;
+        tx = fw * bw + (r - ty * rw);
+      } else {
+        r -= rw * th;
+        const int lw = fw * bw;
+        const int ry = r / lw;
+        tx = r - ry * lw;
+        ty = fh * bh + ry;
+      }
+    }
+  } else {
+    ty = t / bvw.tiles_x;
+    tx = t - ty * bvw.tiles_x;
+  }
   const int lx = tx * 8 + (lane & 7), ly = ty * 8 + (lane >> 3);
   const bool valid = lx < bvw.w && ly < bvw.h;
   const int u = bvw.x0 + min(lx, bvw.w - 1), v = bvw.y0 + min(ly, bvw.h - 1);

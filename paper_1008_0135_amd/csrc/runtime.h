@@ -98,6 +98,9 @@ struct vr_ctx {
   int32_t march_mode = 0;
   int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
   int32_t bwd_layer_cap = 4;  // adjoint on the ring layout: cell layers per checkpoint group, at most
+  // ring march: tiles of a brick numbered along rows (0), down columns (1) or in
+  // blocks of tile_bw x tile_bh tiles (2)
+  int32_t tile_order = 2, tile_bw = 2, tile_bh = 4;
   int32_t ring_nslots = 0;    // forward ring march (plain orthographic): LDS slots per wavefront, 3 or 2; 0 = by occupancy
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
   struct TuneEntry {

@@ -209,6 +209,9 @@ struct MarchArgs {
   int32_t ring_nslots;   // ring march: LDS slots per wavefront, 3 (one layer in flight while sampling) or 2
   int32_t mask_axis;     // axis of the channel mask (2, or 1 in the permuted copy)
   const float* mask;     // channel weights along mask_axis (global indices), or null
+  int32_t tile_order;    // ring march: tiles of a brick numbered along rows (0), down columns (1),
+                         // or in blocks of tile_bw x tile_bh tiles (2)
+  int32_t tile_bw, tile_bh;
 };
 
 struct CompArgs {

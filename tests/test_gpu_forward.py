@@ -245,7 +245,12 @@ def _ctx_with_march(mode):
     """A context with one march forced; "ring2" / "ring3": the ring march with
     two / three LDS slots per wavefront."""
     import os
-    env = {"VR_MARCH": "ring", "VR_RING_SLOTS": mode[-1]} if mode in ("ring2", "ring3") else {"VR_MARCH": mode}
+    if mode in ("ring2", "ring3"):
+        env = {"VR_MARCH": "ring", "VR_RING_SLOTS": mode[-1]}
+    elif mode.startswith("ring:"):  # the ring march with tiles numbered in another order
+        env = {"VR_MARCH": "ring", "VR_TILE_ORDER": mode[5:]}
+    else:
+        env = {"VR_MARCH": mode}
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -296,3 +301,36 @@ def test_marches_identical():
     mn, mx = float(vol.min()), float(vol.max())
     ref = oracle.render(vol, tf, views, 96, 96, mn, mx, tau=0.99, bricks={"grid": (48, 64, 80)})
     parity(imgs[("ring", "grid", 96)], ref, label="ring march")
+
+
+def test_tile_orders_identical():
+    """The numbering of the ring march's tiles (rows, columns, blocks of any
+    size) changes only which wavefront runs when: the same bits for
+    orthographic and perspective views, emission-absorption and MIP."""
+    _say("ring march: tile orders give bit-identical images")
+    dims = (150, 130, 170)
+    vol = synth.cube(*dims, seed=29, n_sources=12, sigma_range=(2.0, 5.0))
+    tf = synth.tf_colour(256)
+    tf[:, 3] = np.minimum(1.0, tf[:, 3] * 6)
+    views = synth.random_views(4, 30)
+    imgs = {}
+    for order in ("row", "col", "blk2x4", "blk3x5", "blk1x1", "blk8x8"):
+        c = _ctx_with_march("ring:" + order)
+        h = _upload(c, vol)
+        vr.vr_tf_set(c, tf)
+        vr.vr_volume_brick(h, vr.grid_spec((48, 40, 64)))
+        for eye in (0.0, 260.0):
+            for mode in (vr.VR_MODE_DVR, vr.VR_MODE_MIP):
+                out = torch.full((len(views), 211, 237, 4), -7.0, device="cuda")
+                vr.vr_render(c, h, [vr.make_view(R, 237, 211, eye_dist=eye) for R in views],
+                             vr.make_params(tau=0.99, mode=mode), out)
+                torch.cuda.synchronize()
+                imgs[(order, eye, mode)] = out.cpu().numpy()
+        vr.vr_volume_destroy(h)
+        vr.vr_destroy(c)
+    for key, img in imgs.items():
+        ref = imgs[("row",) + key[1:]]
+        assert np.array_equal(img, ref), key
+    mn, mx = float(vol.min()), float(vol.max())
+    ref = oracle.render(vol, tf, views[:2], 237, 211, mn, mx, tau=0.99, bricks={"grid": (48, 40, 64)})
+    parity(imgs[("blk2x4", 0.0, vr.VR_MODE_DVR)][:2], ref, label="ring march, 2 x 4 tile blocks")
