@@ -225,15 +225,18 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
                            a.ring_slot, ring_wpb, 3, &waves3);
         a.ring_nslots = 3;
         // two LDS slots per wavefront (the next layer's loads no longer overlap
-        // the wavefront's own sampling, but more wavefronts fit): taken where
-        // three leave the unit at 8 wavefronts or fewer and two reach 12
-        // (measured on 24 GiB cubes), or when forced; plain march only
-        const bool plain = !a.mip && a.mc == 0 && !a.mask;
+        // the wavefront's own sampling, but more wavefronts fit): taken
+        // whenever they fit more wavefronts on a compute unit than three (on
+        // 24 GiB cubes the march follows the wavefront count, not the
+        // lookahead: 12 -> 16 wavefronts took one view from 12.1 to 9.3 ms, a
+        // fourth slot at fewer wavefronts cost 35 %), or when forced; plain
+        // march and maximum intensity projection only
+        const bool plain = a.mc == 0 && !a.mask;
         if (ring && plain && ctx->ring_nslots != 3) {
           int32_t ax2 = 0, slot2 = 0, wpb2 = 4, waves2 = 0;
           if (choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, ax2, slot2, wpb2, 2,
                           &waves2) &&
-              (ctx->ring_nslots == 2 || (waves3 <= 8 && waves2 >= 12))) {
+              (ctx->ring_nslots == 2 || waves2 > waves3)) {
             a.slab_axis = ax2;
             a.ring_slot = slot2;
             ring_wpb = wpb2;
