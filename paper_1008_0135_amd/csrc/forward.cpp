@@ -219,6 +219,17 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         }
         a.slab_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
         ring = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, ring_wpb);
+        a.ring_nslots = 3;
+        // two slots wherever they fit more wavefronts (as for parallel rays)
+        if (ring && a.mc == 0 && !a.mask && ctx->ring_nslots != 3) {
+          int32_t waves3 = 0, waves2 = 0;
+          ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves3, 3);
+          const int32_t wpb2 = ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves2, 2);
+          if (ctx->ring_nslots == 2 || waves2 > waves3) {
+            ring_wpb = wpb2;
+            a.ring_nslots = 2;
+          }
+        }
       } else {
         int32_t waves3 = 0;
         ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,

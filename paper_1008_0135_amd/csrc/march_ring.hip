@@ -619,7 +619,7 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   const dim3 g(grid), b(64 * wpb);
   const size_t lds = ring_lds_bytes(a, wpb);
   if (a.mip && a.mc > 0) return hipErrorInvalidValue;
-  if (a.ring_nslots == 2 && (a.mc > 0 || a.cam.persp)) return hipErrorInvalidValue;
+  if (a.ring_nslots == 2 && a.mc > 0) return hipErrorInvalidValue;
   if (a.mask) {
     // the channel mask lives in instantiations of its own (three slots)
     if (a.ring_nslots == 2) return hipErrorInvalidValue;
@@ -635,8 +635,10 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
     return hipGetLastError();
   }
   if (a.cam.persp) {
-    if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true>), g, b, lds, s, a, none);
+    if (a.mip && a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, true, true, true>), g, b, lds, s, a, none);
+    else if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true>), g, b, lds, s, a, none);
     else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, true>), g, b, lds, s, a, none);
+    else if (a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, false, true, true>), g, b, lds, s, a, none);
     else hipLaunchKernelGGL((k_march_ring<false, false, false, true>), g, b, lds, s, a, none);
   } else {
     if (a.mip && a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, true, false, true>), g, b, lds, s, a, none);

@@ -305,8 +305,9 @@ def test_marches_identical():
 
 def test_tile_orders_identical():
     """The numbering of the ring march's tiles (rows, columns, blocks of any
-    size) changes only which wavefront runs when: the same bits for
-    orthographic and perspective views, emission-absorption and MIP."""
+    size), and two or three LDS slots per wavefront, change only which
+    wavefront runs when and what it holds: the same bits for orthographic and
+    perspective views, emission-absorption and MIP."""
     _say("ring march: tile orders give bit-identical images")
     dims = (150, 130, 170)
     vol = synth.cube(*dims, seed=29, n_sources=12, sigma_range=(2.0, 5.0))
@@ -314,8 +315,9 @@ def test_tile_orders_identical():
     tf[:, 3] = np.minimum(1.0, tf[:, 3] * 6)
     views = synth.random_views(4, 30)
     imgs = {}
-    for order in ("row", "col", "blk2x4", "blk3x5", "blk1x1", "blk8x8"):
-        c = _ctx_with_march("ring:" + order)
+    for order in ("row", "col", "blk2x4", "blk3x5", "blk1x1", "blk8x8", "slots2", "slots3"):
+        # slots2 / slots3: two / three LDS slots per wavefront forced
+        c = _ctx_with_march("ring" + order[-1] if order.startswith("slots") else "ring:" + order)
         h = _upload(c, vol)
         vr.vr_tf_set(c, tf)
         vr.vr_volume_brick(h, vr.grid_spec((48, 40, 64)))
