@@ -260,8 +260,11 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
   int nblocks_max = std::max(bwd_blocks(a0), 1);
   for (const auto& rv : st->vs)
     if (rv.ring) nblocks_max = std::max(nblocks_max, bwd_ring_blocks(a0, rv.bwd_wpb));
-  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes, sizeof(double) * 4 * (size_t)M * (size_t)nblocks_max));
+  // per-workgroup table partials, then the reduction's slices
+  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes,
+                       sizeof(double) * 4 * (size_t)M * ((size_t)nblocks_max + (size_t)tf_reduce_slices())));
   double* part = reinterpret_cast<double*>(ctx->d_scratch);
+  double* slices = part + 4 * (size_t)M * (size_t)nblocks_max;
   for (int32_t v = 0; v < st->nviews; v++) {
     const vr_state::View& rv = st->vs[v];
     MarchArgs a = base;
@@ -294,7 +297,7 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
       VR_HIP(launch_bwd(a, ba, s));
       nblocks = bwd_blocks(a0);
     }
-    VR_HIP(launch_tf_reduce(part, nblocks, M * 4, grad_tf, s));
+    VR_HIP(launch_tf_reduce(part, nblocks, M * 4, grad_tf, slices, s));
     VR_TRY(stage_end(ctx, s));
   }
   return ctx_end(ctx, s);

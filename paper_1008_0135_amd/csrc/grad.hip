@@ -243,12 +243,24 @@ __global__ __launch_bounds__(256) void k_bwd(MarchArgs a, BwdArgs ba) {
   for (int i = threadIdx.x; i < a.M * 4; i += 256) part[i] = s_gtf[i];
 }
 
-// grad_tf[e] (+)= sum over blocks of the partials, accumulated in double.
-__global__ __launch_bounds__(256) void k_tf_reduce(const double* part, int nblocks, int n, float* grad_tf) {
+// grad_tf[e] (+)= sum over blocks of the partials, accumulated in double, in
+// two passes with a fixed order (the same bits on every run): slice s sums
+// blocks s, s + kSlices, ...; then each entry sums its slices in order.
+constexpr int kSlices = 64;
+
+__global__ __launch_bounds__(256) void k_tf_slices(const double* part, int nblocks, int n, double* sl) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= n) return;
   double acc = 0.0;
-  for (int b = 0; b < nblocks; b++) acc += part[(int64_t)b * n + e];
+  for (int b = (int)blockIdx.y; b < nblocks; b += kSlices) acc += part[(int64_t)b * n + e];
+  sl[(int64_t)blockIdx.y * n + e] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_tf_reduce(const double* sl, int n, float* grad_tf) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  double acc = 0.0;
+  for (int s = 0; s < kSlices; s++) acc += sl[(int64_t)s * n + e];
   grad_tf[e] = (float)((double)grad_tf[e] + acc);
 }
 
@@ -278,8 +290,11 @@ hipError_t launch_bwd(const MarchArgs& a, const BwdArgs& ba, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tf_reduce(const double* part, int nblocks, int n, float* grad_tf, hipStream_t s) {
-  hipLaunchKernelGGL(k_tf_reduce, dim3((n + 255) / 256), dim3(256), 0, s, part, nblocks, n, grad_tf);
+int tf_reduce_slices() { return kSlices; }
+
+hipError_t launch_tf_reduce(const double* part, int nblocks, int n, float* grad_tf, double* slices, hipStream_t s) {
+  hipLaunchKernelGGL(k_tf_slices, dim3((n + 255) / 256, kSlices), dim3(256), 0, s, part, nblocks, n, slices);
+  hipLaunchKernelGGL(k_tf_reduce, dim3((n + 255) / 256), dim3(256), 0, s, slices, n, grad_tf);
   return hipGetLastError();
 }
 

@@ -294,7 +294,9 @@ hipError_t launch_brick_minmax_parts(const float* vol, const int64_t n[3], const
 hipError_t launch_fwd_save(const MarchArgs& a, const SaveArgs& sa, hipStream_t s);
 hipError_t launch_bwd(const MarchArgs& a, const BwdArgs& ba, hipStream_t s);
 int bwd_blocks(const MarchArgs& a);
-hipError_t launch_tf_reduce(const double* part, int nblocks, int n, float* grad_tf, hipStream_t s);
+// slices: tf_reduce_slices() x n doubles of scratch
+int tf_reduce_slices();
+hipError_t launch_tf_reduce(const double* part, int nblocks, int n, float* grad_tf, double* slices, hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
 hipError_t launch_batch(const BatchArgs& a, int blocks, hipStream_t s);
 hipError_t launch_copy_box(const float* src, const int64_t sn[3], const int64_t so[3], float* dst,
