@@ -268,16 +268,26 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
         }
       };
 
+      // Voxel layer V_m lives in slot m % (L + 1) for every group, so the layer
+      // two consecutive groups share (V_{k0} of a group, V_{k1} of the one
+      // before it, which is taken next) keeps its voxel window and its gradient
+      // window: it is neither reloaded nor cleared there, and flushed once,
+      // with both groups' terms, by the group taken later.
+      auto pslot = [&](int m) { return m % (L + 1); };
       for (int g = ngrp - 1; g >= 0; --g) {
         const int k0 = g * L, k1 = min(nlay, k0 + L);  // cell layers k0 .. k1 - 1
         const int nv = k1 - k0 + 1;                     // voxel layers V_{k0} .. V_{k1}
+        const bool shared_top = g + 1 < ngrp;           // V_{k1} kept from group g + 1
         if (inl) {
           for (int i = 0; i < nv; ++i) {
             const Window w = window(V0 + (k0 + i) * vstep);
-            issue(V0 + (k0 + i) * vstep, w, s_vox + i * slot);
-            if (lane == 0) s_boff[i] = i * slot - w.g0 * pitch - w.f0;
+            const int ps = pslot(k0 + i);
+            if (!(shared_top && i == nv - 1)) {
+              issue(V0 + (k0 + i) * vstep, w, s_vox + ps * slot);
+              for (int e = lane; e < slot; e += 64) s_grad[ps * slot + e] = 0.f;
+            }
+            if (lane == 0) s_boff[i] = ps * slot - w.g0 * pitch - w.f0;
           }
-          for (int e = lane; e < nv * slot; e += 64) s_grad[e] = 0.f;
           wait_loads();  // also orders the clears and offsets above
         }
         // this ray's samples in the group: [js, je), at most `used`
@@ -398,10 +408,10 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
           const float inv_pitch = 1.0f / (float)pitch;
-          for (int i = 0; i < nv; ++i) {
+          for (int i = g > 0 ? 1 : 0; i < nv; ++i) {  // V_{k0} goes on into group g - 1
             const Window w = window(V0 + (k0 + i) * vstep);
             float* gl = gvol + ((int64_t)(V0 + (k0 + i) * vstep) * sB + (int64_t)w.g0 * sG + w.f0);
-            const float* sg = s_grad + i * slot;
+            const float* sg = s_grad + pslot(k0 + i) * slot;
             for (int e = lane; e < NG * pitch; e += 64) {
               const float val = sg[e];
               if (val != 0.f) {
