@@ -421,7 +421,7 @@ def main():
             done_samples += int(ref["nsamples"].sum())
             g = got[vv, yy.ravel(), xx.ravel()].astype(np.float64)
             ok = (ref["flags"] & oracle.FLAG_GEOM) == 0
-            e = (np.abs(g - ref["image"]) - ref["tol"])[ok]
+            e = oracle.match_error(g, ref)[ok]
             worst = max(worst, float(e.max()) if e.size else 0.0)
             if spent >= args.oracle_seconds:
                 break

@@ -20,8 +20,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-FLAG_ERT = 1
-FLAG_GEOM = 2
+FLAG_ERT = 1   # early-termination tie: several images are valid (listed in "ties")
+FLAG_GEOM = 2  # a sample count or owner decided within rounding of a face
+
+MAXC = 64  # most valid images listed per ray
 
 
 def build(force: bool = True) -> str:
@@ -66,15 +68,22 @@ def lib():
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build(force=True)
         L = C.CDLL(_LIB)
-        P = C.c_void_p
-        L.or_render_rays.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, P, C.c_int]
-        L.or_render_images.argtypes = [P, P, C.c_int, P, P, P, P, C.c_int]
-        L.or_render_grad.argtypes = [P, P, P, P, P, P, C.c_int]
-        L.or_minmax.argtypes = [P, C.c_int64, P, P, P, C.c_int]
-        L.or_box_minmax.argtypes = [P, P, P, P, P, P]
-        L.or_composite.argtypes = [P, C.c_int, C.c_int64, P]
+        _bind(L)
         _lib = L
     return _lib
+
+
+def _bind(L):
+    """Declare the argument types of the oracle library's entry points."""
+    P = C.c_void_p
+    L.or_render_rays.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, C.c_int]
+    L.or_render_candidates.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, C.c_int, P, P, C.c_int]
+    L.or_render_images.argtypes = [P, P, C.c_int, P, P, P, C.c_int]
+    L.or_render_grad.argtypes = [P, P, P, P, P, P, C.c_int]
+    L.or_minmax.argtypes = [P, C.c_int64, P, P, P, C.c_int]
+    L.or_box_minmax.argtypes = [P, P, P, P, P, P]
+    L.or_composite.argtypes = [P, C.c_int, C.c_int64, P]
+    return L
 
 
 def _ptr(a):
@@ -186,9 +195,27 @@ def _views(views, W, H, extent, eye_dist=0.0):
     return arr
 
 
+def _ties(sc, vw, nv, rv, ru, rr, nthreads):
+    """Every valid image of the given rays (early-termination ties)."""
+    n = rv.shape[0]
+    cand = np.zeros((n, MAXC, 4), np.float64)
+    ncand = np.zeros(n, np.int32)
+    if n:
+        rc = lib().or_render_candidates(C.byref(sc), vw, nv, _ptr(rv), _ptr(ru), _ptr(rr), n, None, None, None,
+                                        MAXC, _ptr(cand), _ptr(ncand), int(nthreads))
+        if rc != 0:
+            raise ValueError("oracle candidates: bad input")
+    return cand, ncand
+
+
 def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bricks=None,
            ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR, eye_dist=0.0, mask=None):
-    """Render full images.  Returns dict(image [nv][H][W][4] f64, tol, flags, nsamples).
+    """Render full images.  Returns dict(image [nv][H][W][4] f64, flags [nv][H][W], nsamples, ties).
+
+    ties = dict(index, cand, ncand): for each pixel flagged FLAG_ERT (flat index
+    into ``flags``), every valid image (cand[i][:ncand[i]], RGBA) -- one per
+    combination of the stopping samples that lie within ``ert_margin`` of tau
+    in opacity; ncand = -1 when there are more than MAXC.
 
     mode=MODE_MIP: maximum intensity projection, (M, M, M, M) per pixel with M the
     largest normalised sample value along the ray (the table is not used).
@@ -199,21 +226,24 @@ def render(vol, tf, views, W, H, vmin, vmax, step=0.5, tau=0.99, extent=0.0, bri
     vw = _views(views, W, H, extent, eye_dist)
     nv = len(views)
     img = np.zeros((nv, H, W, 4), np.float64)
-    tol = np.zeros_like(img)
     flags = np.zeros((nv, H, W), np.uint8)
     tot = C.c_int64(0)
-    rc = lib().or_render_images(C.byref(sc), vw, nv, _ptr(img), _ptr(tol), _ptr(flags),
-                                C.byref(tot), int(nthreads))
+    rc = lib().or_render_images(C.byref(sc), vw, nv, _ptr(img), _ptr(flags), C.byref(tot), int(nthreads))
     if rc != 0:
         raise ValueError("oracle render: bad input")
+    idx = np.flatnonzero((flags & FLAG_ERT) != 0)
+    vi, yy, xx = np.unravel_index(idx, flags.shape)
+    cand, ncand = _ties(sc, vw, nv, np.ascontiguousarray(vi, np.int32), np.ascontiguousarray(xx, np.int32),
+                        np.ascontiguousarray(yy, np.int32), nthreads)
     del keep
-    return dict(image=img, tol=tol, flags=flags, nsamples=int(tot.value))
+    return dict(image=img, flags=flags, nsamples=int(tot.value), ties=dict(index=idx, cand=cand, ncand=ncand))
 
 
 def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0.5, tau=0.99,
                 extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR,
                 eye_dist=0.0, mask=None):
-    """Render selected rays (view index, pixel u, pixel v).  Returns dict like ``render``."""
+    """Render selected rays (view index, pixel u, pixel v).  Returns dict like ``render``
+    (``nsamples`` per ray, ``ties.index`` into the ray list)."""
     sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode, mask)
     vw = _views(views, W, H, extent, eye_dist)
     rv = np.ascontiguousarray(ray_view, np.int32)
@@ -221,15 +251,33 @@ def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0
     rr = np.ascontiguousarray(ray_v, np.int32)
     n = rv.shape[0]
     img = np.zeros((n, 4), np.float64)
-    tol = np.zeros_like(img)
     flags = np.zeros(n, np.uint8)
     ns = np.zeros(n, np.int64)
     rc = lib().or_render_rays(C.byref(sc), vw, len(views), _ptr(rv), _ptr(ru), _ptr(rr), n,
-                              _ptr(img), _ptr(tol), _ptr(flags), _ptr(ns), int(nthreads))
+                              _ptr(img), _ptr(flags), _ptr(ns), int(nthreads))
     if rc != 0:
         raise ValueError("oracle render_rays: bad input")
+    idx = np.flatnonzero((flags & FLAG_ERT) != 0)
+    cand, ncand = _ties(sc, vw, len(views), rv[idx].copy(), ru[idx].copy(), rr[idx].copy(), nthreads)
     del keep
-    return dict(image=img, tol=tol, flags=flags, nsamples=ns)
+    return dict(image=img, flags=flags, nsamples=ns, ties=dict(index=idx, cand=cand, ncand=ncand))
+
+
+def match_error(got, ref):
+    """Per-pixel error of ``got`` ([..., 4], same layout as ref["image"]) against
+    the oracle: the largest channel difference from the oracle image, or, for a
+    pixel with several valid images (FLAG_ERT), from the closest of them (inf
+    when they were too many to list).  Returns an array shaped like ``flags``."""
+    g = np.asarray(got, np.float64).reshape(-1, 4)
+    err = np.abs(g - ref["image"].reshape(-1, 4)).max(axis=1)
+    t = ref["ties"]
+    if t["index"].size:
+        gi = g[t["index"]][:, None, :]
+        e = np.abs(gi - t["cand"]).max(axis=2)  # [n][MAXC]
+        valid = np.arange(MAXC)[None, :] < t["ncand"][:, None]
+        best = np.where(valid, e, np.inf).min(axis=1)
+        err[t["index"]] = best
+    return err.reshape(ref["flags"].shape)
 
 
 def render_grad(vol, tf, view, W, H, grad_out, vmin, vmax, step=0.5, tau=2.0, extent=0.0,

@@ -58,8 +58,9 @@
  *
  * Where several results are correct (an opacity that lands within rounding
  * distance of tau, a sample within rounding distance of a face), the oracle
- * reports a per-pixel widening of the tolerance (ERT) or a flag (geometry)
- * so that a caller can accept any of the valid answers.
+ * flags the pixel; for early-termination ties it lists every valid image (one
+ * per combination of valid stopping samples) so that a caller can accept a
+ * result that matches one of them.
  */
 #include <math.h>
 #include <stdint.h>
@@ -69,7 +70,7 @@
 #include <omp.h>
 #endif
 
-#define OR_FLAG_ERT 1  /* tolerance widened: opacity near tau */
+#define OR_FLAG_ERT 1  /* several stops are valid: opacity within rounding of tau */
 #define OR_FLAG_GEOM 2 /* sample count or ownership decided within rounding of a face */
 
 typedef struct {
@@ -226,45 +227,75 @@ static void classify(const or_scene *sc, double v, double rgba[4], int *ti, doub
   *tw = w;
 }
 
-/* One accumulation chain (the whole ray, or one sub-volume's share of it). */
+/* One accumulation chain (the whole ray, or one sub-volume's share of it).
+ *
+ * With early termination on, an FP32 renderer may stop a chain at any sample
+ * whose FP64 opacity lies within ert_margin of tau: at the first sample with
+ * A >= tau - margin at the earliest, at the first with A >= tau + margin at the
+ * latest.  Every stop in that range is a correct result.  The chain keeps the
+ * state (C, T) after each of those samples (continuing past the FP64 stop) so
+ * that a caller can list every valid image. */
+#define OR_MAXST 48
 typedef struct {
-  double C[3], T; /* accumulated colour and transmittance (stops at ERT) */
-  double Tt;      /* transmittance continued past the stop (tie window only) */
-  int stopped, lo_seen, hi_seen, used;
-  double span[4]; /* contributions of samples whose inclusion is a tie */
+  double C[3], T;   /* accumulated colour and transmittance (stops at ERT) */
+  double Ct[3], Tt; /* continued past the stop (tie window only) */
+  int stopped, lo_seen, hi_seen, used, nst, overflow;
+  double stC[OR_MAXST][3], stT[OR_MAXST]; /* states after each sample of the tie window */
   double tfirst;
 } chain;
 
 static void chain_reset(chain *ch) {
-  memset(ch, 0, sizeof(*ch));
+  for (int c = 0; c < 3; c++) ch->C[c] = ch->Ct[c] = 0.0;
   ch->T = 1.0;
   ch->Tt = 1.0;
+  ch->stopped = ch->lo_seen = ch->hi_seen = ch->used = ch->nst = ch->overflow = 0;
+  ch->tfirst = 0.0;
 }
 
 /* Feed one sample.  Returns 0 once nothing more can change the chain's outputs. */
 static int chain_feed(const or_scene *sc, chain *ch, const double rgba[4]) {
   int ert = sc->tau < 1.0;
+  double a = rgba[3];
   if (!ert) {
-    double a = rgba[3];
     for (int c = 0; c < 3; c++) ch->C[c] += ch->T * a * rgba[c];
     ch->T *= (1.0 - a);
     return 1;
   }
   if (ch->hi_seen) return 0;
-  double a = rgba[3];
-  double contrib[4] = {ch->Tt * a * rgba[0], ch->Tt * a * rgba[1], ch->Tt * a * rgba[2], ch->Tt * a};
   if (!ch->stopped) {
     for (int c = 0; c < 3; c++) ch->C[c] += ch->T * a * rgba[c];
     ch->T *= (1.0 - a);
+    if (1.0 - ch->T >= sc->tau) ch->stopped = 1;
   }
-  if (ch->lo_seen)
-    for (int c = 0; c < 4; c++) ch->span[c] += contrib[c];
+  for (int c = 0; c < 3; c++) ch->Ct[c] += ch->Tt * a * rgba[c];
   ch->Tt *= (1.0 - a);
   double A = 1.0 - ch->Tt;
-  if (!ch->stopped && 1.0 - ch->T >= sc->tau) ch->stopped = 1;
   if (A >= sc->tau - sc->ert_margin) ch->lo_seen = 1;
+  if (ch->lo_seen) {
+    if (ch->nst < OR_MAXST) {
+      for (int c = 0; c < 3; c++) ch->stC[ch->nst][c] = ch->Ct[c];
+      ch->stT[ch->nst] = ch->Tt;
+      ch->nst++;
+    } else {
+      ch->overflow = 1;
+    }
+  }
   if (A >= sc->tau + sc->ert_margin) ch->hi_seen = 1;
   return !ch->hi_seen;
+}
+
+/* Number of valid stops of a chain (1 when its stop is not a tie). */
+static int chain_nstates(const chain *ch) { return ch->nst >= 2 ? ch->nst : 1; }
+
+/* State j of a chain's valid stops: colour and transmittance. */
+static void chain_state(const chain *ch, int j, double C[3], double *T) {
+  if (ch->nst >= 2) {
+    for (int c = 0; c < 3; c++) C[c] = ch->stC[j][c];
+    *T = ch->stT[j];
+  } else {
+    for (int c = 0; c < 3; c++) C[c] = ch->C[c];
+    *T = ch->T;
+  }
 }
 
 /* Owner of a sample: index into sc->boxes, or -1. */
@@ -310,9 +341,43 @@ typedef struct {
   int ntouched;
 } ray_scratch;
 
-/* Render one ray.  out[4] = (C, A); tol[4] = extra tolerance; returns flags. */
+/*
+ * Every valid image of one ray when early termination makes several correct:
+ * the over-composite, in depth order, of one valid stop per chain, for every
+ * combination of the chains' valid stops.  Writes at most maxc candidates
+ * (RGBA each) and returns their number, or -1 when there are more than maxc
+ * (or a chain's tie window held more samples than it keeps).
+ */
+static int ray_candidates(const ray_scratch *rs, double *cand, int maxc) {
+  int64_t total = 1;
+  for (int a = 0; a < rs->ntouched; a++) {
+    const chain *ch = &rs->chains[rs->touched[a]];
+    if (ch->overflow) return -1;
+    total *= chain_nstates(ch);
+    if (total > maxc) return -1;
+  }
+  for (int64_t q = 0; q < total; q++) {
+    int64_t rest = q;
+    double C[3] = {0, 0, 0}, A = 0.0;
+    for (int a = 0; a < rs->ntouched; a++) {
+      const chain *ch = &rs->chains[rs->touched[a]];
+      int ns = chain_nstates(ch);
+      double Cb[3], Tb;
+      chain_state(ch, (int)(rest % ns), Cb, &Tb);
+      rest /= ns;
+      for (int c = 0; c < 3; c++) C[c] = C[c] + (1.0 - A) * Cb[c];
+      A = A + (1.0 - A) * (1.0 - Tb);
+    }
+    for (int c = 0; c < 3; c++) cand[4 * q + c] = C[c];
+    cand[4 * q + 3] = A;
+  }
+  return (int)total;
+}
+
+/* Render one ray.  out[4] = (C, A); returns flags.  With cand != NULL, also
+ * lists the ray's valid images (see ray_candidates) and their count in *ncand. */
 static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratch *rs, double out[4],
-                 double tol[4], int64_t *nsamp) {
+                 int64_t *nsamp, double *cand, int maxc, int *ncand) {
   double o[3], d[3], lo[3], hi[3];
   int flags = 0, gtie = 0;
   pixel_ray(cam, u, v, o, d);
@@ -320,8 +385,9 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
     lo[i] = 0.0;
     hi[i] = (double)(sc->n[i] - 1);
   }
-  for (int c = 0; c < 4; c++) out[c] = tol[c] = 0.0;
+  for (int c = 0; c < 4; c++) out[c] = 0.0;
   *nsamp = 0;
+  if (ncand) *ncand = 0;
   double tin, tout;
   int hit = slab(o, d, lo, hi, &tin, &tout, &gtie, sc->geom_margin);
   if (!hit) return gtie ? OR_FLAG_GEOM : 0;
@@ -394,21 +460,21 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
   double C[3] = {0, 0, 0}, A = 0.0;
   for (int a = 0; a < rs->ntouched; a++) {
     chain *ch = &rs->chains[rs->touched[a]];
-    double Ab = 1.0 - ch->T, Tf = 1.0 - A;
-    if (ch->lo_seen) {
-      flags |= OR_FLAG_ERT;
-      for (int c = 0; c < 3; c++) tol[c] += Tf * (ch->span[c] + ch->span[3]);
-      tol[3] += Tf * ch->span[3];
-    }
+    if (chain_nstates(ch) > 1 || ch->overflow) flags |= OR_FLAG_ERT;
     for (int c = 0; c < 3; c++) C[c] = C[c] + (1.0 - A) * ch->C[c];
-    A = A + (1.0 - A) * Ab;
-    ch->used = 0;
+    A = A + (1.0 - A) * (1.0 - ch->T);
   }
   for (int c = 0; c < 3; c++) out[c] = C[c];
   out[3] = A;
+  if (cand && ncand) *ncand = ray_candidates(rs, cand, maxc);
+  for (int a = 0; a < rs->ntouched; a++) rs->chains[rs->touched[a]].used = 0;
   if (gtie) flags |= OR_FLAG_GEOM;
   return flags;
 }
+
+int or_render_candidates(const or_scene *sc, const or_view *views, int nviews, const int32_t *ray_view,
+                         const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, uint8_t *flags,
+                         int64_t *nsamp, int maxc, double *cand, int32_t *ncand, int nthreads);
 
 static int scene_ok(const or_scene *sc) {
   if (!sc || !sc->vol || !sc->tf || sc->M < 2 || sc->step <= 0.0) return 0;
@@ -427,14 +493,27 @@ static void set_threads(int nthreads) {
 
 /*
  * Render a list of rays.  ray_view/ray_u/ray_v select (view, pixel).  Outputs
- * per ray: rgba[4] (premultiplied colour, opacity), tol[4] (extra tolerance
- * for tie windows), flags, nsamp (lattice samples inside the volume box).
- * Any output pointer may be NULL.  Returns 0 on success, -1 on bad input.
+ * per ray: rgba[4] (premultiplied colour, opacity), flags, nsamp (lattice
+ * samples inside the volume box).  Any output pointer may be NULL.  Returns 0
+ * on success, -1 on bad input.
  */
 int or_render_rays(const or_scene *sc, const or_view *views, int nviews, const int32_t *ray_view,
-                   const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, double *tol,
-                   uint8_t *flags, int64_t *nsamp, int nthreads) {
-  if (!scene_ok(sc) || nviews < 1) return -1;
+                   const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, uint8_t *flags,
+                   int64_t *nsamp, int nthreads) {
+  return or_render_candidates(sc, views, nviews, ray_view, ray_u, ray_v, nrays, rgba, flags, nsamp, 0, NULL,
+                              NULL, nthreads);
+}
+
+/*
+ * As or_render_rays, and with cand != NULL also every valid image of each ray
+ * (early-termination ties): cand is [nrays][maxc][4], ncand[r] the number
+ * written for ray r (1 without a tie, 0 for a ray that misses or an MIP ray,
+ * -1 when there are more than maxc).
+ */
+int or_render_candidates(const or_scene *sc, const or_view *views, int nviews, const int32_t *ray_view,
+                         const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, uint8_t *flags,
+                         int64_t *nsamp, int maxc, double *cand, int32_t *ncand, int nthreads) {
+  if (!scene_ok(sc) || nviews < 1 || (cand && (maxc < 1 || !ncand))) return -1;
   set_threads(nthreads);
   camera *cams = (camera *)malloc(sizeof(camera) * (size_t)nviews);
   for (int i = 0; i < nviews; i++) make_camera(sc, &views[i], &cams[i]);
@@ -452,13 +531,15 @@ int or_render_rays(const or_scene *sc, const or_view *views, int nviews, const i
         err = 1;
         continue;
       }
-      double o4[4], t4[4];
+      double o4[4];
       int64_t ns;
-      int fl = trace(sc, &cams[vi], ray_u[r], ray_v[r], &rs, o4, t4, &ns);
+      int nc = 0;
+      int fl = trace(sc, &cams[vi], ray_u[r], ray_v[r], &rs, o4, &ns, cand ? cand + 4 * (int64_t)maxc * r : NULL,
+                     maxc, &nc);
       if (rgba) memcpy(rgba + 4 * r, o4, sizeof(o4));
-      if (tol) memcpy(tol + 4 * r, t4, sizeof(t4));
       if (flags) flags[r] = (uint8_t)fl;
       if (nsamp) nsamp[r] = ns;
+      if (cand) ncand[r] = nc;
     }
     free(rs.chains);
     free(rs.touched);
@@ -467,9 +548,9 @@ int or_render_rays(const or_scene *sc, const or_view *views, int nviews, const i
   return err ? -1 : 0;
 }
 
-/* Render full images: out/tol are [nviews][H][W][4] doubles, flags [nviews][H][W]. */
-int or_render_images(const or_scene *sc, const or_view *views, int nviews, double *rgba, double *tol,
-                     uint8_t *flags, int64_t *nsamp_total, int nthreads) {
+/* Render full images: rgba is [nviews][H][W][4] doubles, flags [nviews][H][W]. */
+int or_render_images(const or_scene *sc, const or_view *views, int nviews, double *rgba, uint8_t *flags,
+                     int64_t *nsamp_total, int nthreads) {
   if (!scene_ok(sc) || nviews < 1) return -1;
   set_threads(nthreads);
   int nch = sc->nboxes > 0 ? sc->nboxes : 1;
@@ -486,11 +567,10 @@ int or_render_images(const or_scene *sc, const or_view *views, int nviews, doubl
 #pragma omp for schedule(dynamic, 16)
       for (int64_t q = 0; q < npix; q++) {
         int u = (int)(q % cam.W), v = (int)(q / cam.W);
-        double o4[4], t4[4];
+        double o4[4];
         int64_t ns;
-        int fl = trace(sc, &cam, u, v, &rs, o4, t4, &ns);
+        int fl = trace(sc, &cam, u, v, &rs, o4, &ns, NULL, 0, NULL);
         if (rgba) memcpy(rgba + 4 * (off + q), o4, sizeof(o4));
-        if (tol) memcpy(tol + 4 * (off + q), t4, sizeof(t4));
         if (flags) flags[off + q] = (uint8_t)fl;
         vtotal += ns;
       }
