@@ -271,7 +271,8 @@ static int chain_feed(const or_scene *sc, chain *ch, const double rgba[4]) {
   ch->Tt *= (1.0 - a);
   double A = 1.0 - ch->Tt;
   if (A >= sc->tau - sc->ert_margin) ch->lo_seen = 1;
-  if (ch->lo_seen) {
+  /* a sample of zero opacity repeats the previous state: listed once */
+  if (ch->lo_seen && (ch->nst == 0 || a > 0.0)) {
     if (ch->nst < OR_MAXST) {
       for (int c = 0; c < 3; c++) ch->stC[ch->nst][c] = ch->Ct[c];
       ch->stT[ch->nst] = ch->Tt;

@@ -28,7 +28,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 
 __all__ = [
-    "cube", "CONFIGS", "config_cube", "rot_axis", "c1_views", "random_views",
+    "cube", "CONFIGS", "config_cube", "config_sources", "rot_axis", "c1_views", "random_views",
     "random_rotation", "tf_ramp", "tf_colour", "tf_noise_suppress", "tf_random",
     "tf_perturbed", "batch_requests", "threads",
 ]
@@ -146,6 +146,14 @@ CONFIGS = {
     "C5": dict(dims=(256, 256, 512), seed=1005, n_sources=25, band=True, image=(512, 512),
                view_seed=2005, nviews=8, tf_seed=3005),
 }
+
+
+def config_sources(name: str) -> list:
+    """The compact sources of a named cube: (amplitude, centre (x1, x2, x3), sigmas)."""
+    c = CONFIGS[name]
+    n1, n2, n3 = c["dims"]
+    srng = np.random.Generator(np.random.PCG64([c["seed"], 0x5EED]))
+    return _source_params(srng, c["n_sources"], (n3, n2, n1), c.get("sigma_range", (2.0, 6.0)), c.get("margin"))
 
 
 def config_cube(name: str, nthreads: int | None = None, out=None) -> np.ndarray:

@@ -160,3 +160,47 @@ def test_autotune_keeps_images(ctx):
     vr.vr_batch_destroy(cache)
     for v in vols + [h]:
         vr.vr_volume_destroy(v)
+
+
+def test_c4_full_batch_parity(ctx):
+    """The benchmark's batch at full size: 64 requests, volumes U[32, 256] per axis,
+    images U[64, 512], random views and tables, after the batch autotuner.  Every
+    request is checked against the FP64 oracle on strided rays (every 8th row and
+    column) and against its own plain render bit for bit."""
+    descs = synth.batch_requests(seed=synth.CONFIGS["C4"]["seed"], nreq=synth.CONFIGS["C4"]["nreq"])
+    _say(f"C4 batch: generating {len(descs)} volumes")
+    vols, arrays, reqs, outs, wins = [], [], [], [], []
+    for d in descs:
+        n1, n2, n3 = d["dims"]
+        a = synth.cube(n1, n2, n3, seed=d["seed"], n_sources=d["n_sources"])
+        arrays.append(a)
+        vols.append(vr.vr_volume_create(ctx, a, (n1, n2, n3)))
+        W, H = d["image"]
+        t = torch.from_numpy(d["tf"]).cuda()
+        o = torch.full((H, W, 4), -1.0, device="cuda")
+        mn, mx = float(a.min()), float(a.max())
+        outs.append((o, t))
+        wins.append((mn, mx))
+        reqs.append(vr.make_request(vols[-1], d["view"], W, H, t, mn, mx, o))
+    params = vr.make_params(step=0.5, tau=0.99, ess=0)
+    _say("C4 batch: autotune + render")
+    r, cache = vr.vr_autotune_batch(ctx, reqs, params)
+    cache = vr.vr_render_batch(ctx, reqs, params, cache)
+    torch.cuda.synchronize()
+    got = [o.cpu().numpy() for o, _ in outs]
+    worst = 0.0
+    for i, d in enumerate(descs):
+        W, H = d["image"]
+        mn, mx = wins[i]
+        ref = _plain(ctx, vols[i], d["view"], W, H, d["tf"], mn, mx, params)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[i], ref.cpu().numpy()[0]), f"request {i}: batch != plain render"
+        yy, xx = np.meshgrid(np.arange(i % 8, H, 8), np.arange((3 * i) % 8, W, 8), indexing="ij")
+        o = oracle.render_rays(arrays[i], d["tf"], [d["view"]], W, H, np.zeros(yy.size, np.int32), xx.ravel(),
+                               yy.ravel(), mn, mx, tau=0.99)
+        s = parity(got[i][yy.ravel(), xx.ravel()], o, label=f"C4 request {i} {d['dims']} {W}x{H}")
+        worst = max(worst, s["worst"])
+    _say(f"C4 batch: 64 requests match the oracle (worst {worst:.3g}) and their plain renders")
+    vr.vr_batch_destroy(cache)
+    for v in vols:
+        vr.vr_volume_destroy(v)

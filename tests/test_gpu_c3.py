@@ -59,7 +59,7 @@ def _rays(nv):
     return vv, np.tile(x, nv), np.tile(y, nv)
 
 
-def _check(sc, tf, params, label, eye=0.0, mode=0, bricks=True, mask=None, window=None):
+def _check(sc, tf, params, label, eye=0.0, mode=0, bricks=True, mask=None, window=None, lit=0):
     ctx, h, views = sc["ctx"], sc["h"], sc["views"]
     mn, mx = window if window else (sc["mn"], sc["mx"])
     vr.vr_tf_set(ctx, tf, mn, mx)
@@ -70,10 +70,28 @@ def _check(sc, tf, params, label, eye=0.0, mode=0, bricks=True, mask=None, windo
     got = out.cpu().numpy()
     vr.vr_mask_set(ctx, None)
     vv, xx, yy = _rays(len(views))
+    if lit:
+        # also the pixels under the brightest compact sources (a table that is
+        # transparent below several sigma leaves few strided rays lit): source
+        # centres from the generator, projected with the orthographic camera
+        srcs = sorted(synth.config_sources("C3"), key=lambda t: -t[0])[:lit]
+        cen = np.array([c for _, c, _ in srcs], np.float64)
+        mid = (np.array(DIMS, np.float64) - 1) / 2
+        S = float(np.sqrt(((np.array(DIMS, np.float64) - 1) ** 2).sum()))
+        for v, R in enumerate(views):
+            u = np.floor(((cen - mid) @ R[0] / S + 0.5) * W).astype(int)
+            w = np.floor(((cen - mid) @ R[1] / (S * H / W) + 0.5) * H).astype(int)
+            ok = (u >= 0) & (u < W) & (w >= 0) & (w < H)
+            vv = np.concatenate([vv, np.full(int(ok.sum()), v)])
+            xx = np.concatenate([xx, u[ok]])
+            yy = np.concatenate([yy, w[ok]])
     _say(f"C3 {label}: oracle on {vv.size} rays")
     ref = oracle.render_rays(sc["vol"], tf, views, W, H, vv, xx, yy, mn, mx, tau=0.99, mode=mode, eye_dist=eye,
                              bricks={"grid": C["bricks"]} if bricks else None, mask=mask)
     s = parity(got[vv, yy, xx], ref, label=f"C3 {label}")
+    if lit:
+        s["lit"] = int((ref["image"][:, 3] > 0).sum())
+        assert s["lit"] >= 200, s
     _say(f"  {s}")
     assert np.isfinite(got).all() and (got >= 0).all() and (got <= 1.0 + 1e-6).all()
 
@@ -92,6 +110,13 @@ def test_c3_perspective_global_mip(scene):
     mn, mx = scene["mn"], scene["mx"]
     _check(scene, tf, vr.make_params(mode=vr.VR_MODE_MIP), "MIP", mode=oracle.MODE_MIP,
            window=(mn, mn + 0.4 * (mx - mn)))
+
+
+def test_c3_noise_suppressing_table(scene):
+    """The second benchmark table: opacity 0 below 6 sigma, 16^3 macrocells, no mask
+    (the plain empty-space-skipping ring march)."""
+    tf = synth.tf_noise_suppress(scene["mn"], scene["mx"], thresh=6.0)
+    _check(scene, tf, vr.make_params(), "noise-suppressing table, macrocell skipping", lit=400)
 
 
 def test_c3_channel_mask(scene):

@@ -17,7 +17,8 @@ sub-volume chains).  These tests rebuild those images independently:
 
 Planted mistakes (a window one margin too wide or too narrow, a composite
 without the front's transmittance, every candidate given the FP64 stop's
-colour) are compiled into copies of the oracle and each must fail a pin.
+colour, transparent samples listed as extra images) are compiled into copies
+of the oracle and each must fail a pin.
 """
 import ctypes
 import os
@@ -75,7 +76,8 @@ def _chain_states(rgba, tau, margin):
         return [(C[-1], T[-1])], (C[-1], T[-1])
     hi = np.nonzero(A >= tau + margin)[0]
     last = int(hi[0]) if hi.size else n - 1
-    states = [(C[j], T[j]) for j in range(int(lo[0]), last + 1)]
+    # a sample of zero opacity leaves the state as it was: one image, listed once
+    states = [(C[j], T[j]) for j in range(int(lo[0]), last + 1) if j == lo[0] or a[j] > 0]
     return states, (C[stop], T[stop])
 
 
@@ -114,17 +116,20 @@ def _column_candidates(vol, tf, vmin, vmax, tau, margin, zcuts=()):
     return out
 
 
-def _column_case(seed, n1=6, n2=5, n3=48):
+def _column_case(seed, n1=6, n2=5, n3=48, zero_low=False):
     rng = _rng(seed)
     vol = rng.normal(0, 1, (n3, n2, n1)).astype(np.float32)
     tf = synth.tf_colour(16)
     tf[:, 3] = np.linspace(0.02, 0.2, 16, dtype=np.float32)
+    if zero_low:  # runs of transparent samples (values in the lower half)
+        tf[:8, 3] = 0.0
+        tf[8:, 3] = np.linspace(0.05, 0.5, 8, dtype=np.float32)
     return vol, tf, float(vol.min()), float(vol.max())
 
 
-def _check_columns(orc, tau, margin, zcuts=(), seed=1):
+def _check_columns(orc, tau, margin, zcuts=(), seed=1, zero_low=False):
     """The oracle's valid images of every column pixel equal the column model's."""
-    vol, tf, vmin, vmax = _column_case(seed)
+    vol, tf, vmin, vmax = _column_case(seed, n1=10, n2=9, zero_low=zero_low) if zero_low else _column_case(seed)
     n3, n2, n1 = vol.shape
     bricks = None
     if zcuts:
@@ -165,6 +170,13 @@ def _check_columns(orc, tau, margin, zcuts=(), seed=1):
 def test_whole_column_candidates(orc, tau, margin):
     """Whole volume: the valid images are exactly stop-at-j for j in the window."""
     assert _check_columns(orc, tau, margin) >= 5
+
+
+def test_transparent_samples_in_window(orc):
+    """Zero-opacity samples inside a tie window repeat the previous image: each valid
+    image is listed once (a window spanning a long transparent run stays listable)."""
+    assert _check_columns(orc, 0.6, 2e-2, zero_low=True) >= 3
+    assert _check_columns(orc, 0.5, 3e-2, (20,), zero_low=True) >= 3
 
 
 @pytest.mark.parametrize("zcuts", [(20,), (10, 31)])
@@ -251,6 +263,9 @@ _MUTANTS = {
     "composite without the front's transmittance": (
         "for (int c = 0; c < 3; c++) C[c] = C[c] + (1.0 - A) * Cb[c];",
         "for (int c = 0; c < 3; c++) C[c] = C[c] + Cb[c];"),
+    "transparent samples listed again": (
+        "if (ch->lo_seen && (ch->nst == 0 || a > 0.0)) {",
+        "if (ch->lo_seen) {"),
     "candidates keep the FP64 stop's colour": (
         "for (int c = 0; c < 3; c++) C[c] = ch->stC[j][c];",
         "for (int c = 0; c < 3; c++) C[c] = ch->C[c];"),
@@ -270,7 +285,7 @@ def test_planted_mistakes_fail(orc, name, tmp_path):
     oracle._lib = oracle._bind(ctypes.CDLL(so))
     try:
         failed = False
-        for args in ((0.9, 3e-3, ()), (0.5, 2e-2, (10, 31))):
+        for args in ((0.9, 3e-3, ()), (0.5, 2e-2, (10, 31)), (0.6, 2e-2, (), 1, True)):
             try:
                 _check_columns(oracle, *args)
             except AssertionError:
