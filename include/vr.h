@@ -394,13 +394,27 @@ int vr_autotune(vr_ctx *ctx, const vr_volume *vol, const vr_view *view, const vr
                 vr_tune_result *out, uintptr_t stream);
 
 /*
- * Time the batched launch of these requests with persistent grids of 2, 4, 8,
- * 16 and 32 wavefronts per compute unit, keep the fastest for later batched
- * calls on this context (and in VR_TUNE_CACHE), and leave *cache holding the
- * graph of the chosen grid.  Synchronises.  Errors: as vr_render_batch.
+ * Autotune the batched launch of these requests (a training-system pattern,
+ * not in the paper).  First the tile shape per size class: requests are
+ * grouped by volume size class (floor(log2 voxels) / 3) and image class
+ * (floor(log2 pixels) / 2); the requests of each class are rendered as a
+ * batch of their own with 8 x 8, 16 x 4, 4 x 16 and 32 x 2 pixel tiles, and
+ * the fastest is kept per class.  Then the persistent grid: 2, 4, 8, 16 and
+ * 32 wavefronts per compute unit over the whole batch with the tuned tiles.
+ * Both choices apply to later batched calls on this context (and are written
+ * to VR_TUNE_CACHE); *cache is left holding the graph of the chosen shapes.
+ * out->tile is the tile chosen for most classes.  Synchronises.
+ * Errors: as vr_render_batch.
  */
 int vr_autotune_batch(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_params *p, vr_batch **cache,
                       vr_tune_result *out, uintptr_t stream);
+
+/*
+ * Tile width (4, 8, 16 or 32 pixels; the tile is 64 pixels) each request of a
+ * batch would run with: the autotuner's choice for its size class, else 8.
+ * tiles: [n] host.  No GPU use.  Errors: VR_EINVAL.
+ */
+int vr_batch_tiles(const vr_ctx *ctx, const vr_request *reqs, int32_t n, int32_t *tiles);
 
 /* ------------------------------------------------------------------ host-only helpers */
 /*

@@ -116,6 +116,7 @@ _SIGS = {
     "vr_batch_destroy": (_I, [_P]),
     "vr_autotune": (_I, [_P, _P, _P, _P, _P, _U]),
     "vr_autotune_batch": (_I, [_P, _P, _I32, _P, _P, _P, _U]),
+    "vr_batch_tiles": (_I, [_P, _P, _I32, _P]),
     "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "vr_count_samples": (_I, [_P, _P, _D, _P]),
     "vr_partition": (_I, [_P, _P, _P, _P]),
@@ -387,6 +388,14 @@ def vr_autotune_batch(ctx, reqs, params, cache=None, stream=None):
     _check(lib().vr_autotune_batch(ctx, arr, len(reqs), C.byref(params), C.byref(h), C.byref(r), _stream(stream)),
            "vr_autotune_batch")
     return r, h.value
+
+
+def vr_batch_tiles(ctx, reqs):
+    """Tile width each request of a batch runs with (tuned per size class, else 8)."""
+    arr = (vr_request * len(reqs))(*reqs)
+    t = (C.c_int32 * max(1, len(reqs)))()
+    _check(lib().vr_batch_tiles(ctx, arr, len(reqs), t), "vr_batch_tiles")
+    return [int(x) for x in t[:len(reqs)]]
 
 
 def make_request(vol, R, W, H, tf, vmin, vmax, out, extent=0.0, eye_dist=0.0):

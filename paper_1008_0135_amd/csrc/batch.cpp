@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <string>
 #include <vector>
 
 #include "runtime.h"
@@ -62,8 +63,8 @@ int batch_blocks(vr_ctx* ctx) {
   return std::max(1, cus * wpc / 4);  // 4 wavefronts per block
 }
 
-// Estimated samples per tile of a request: box volume / (pixel area x step), per pixel.
-static double tile_cost(const vr_volume* v, const vr_view& view, double step) {
+// Estimated samples per pixel of a request: box volume / (pixel area x step), per pixel.
+static double pixel_cost(const vr_volume* v, const vr_view& view, double step) {
   double diag = 0.0, vol = 1.0;
   for (int i = 0; i < 3; i++) {
     diag += (double)(v->n[i] - 1) * (double)(v->n[i] - 1);
@@ -71,12 +72,34 @@ static double tile_cost(const vr_volume* v, const vr_view& view, double step) {
   }
   const double S = view.extent > 0.0 ? view.extent : std::sqrt(diag);
   const double pitch = S / view.W;
-  const double per_pixel = vol / (pitch * pitch * step) / ((double)view.W * view.H);
-  return 64.0 * per_pixel;
+  return vol / (pitch * pitch * step) / ((double)view.W * view.H);
 }
 
-int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, vr_batch** cache,
-                 hipStream_t s, int32_t force_blocks) {
+static int log2_floor(double x) {
+  int c = 0;
+  while (c < 62 && std::ldexp(1.0, c + 1) <= x) c++;
+  return c;
+}
+
+// Size class of a batched request for the autotuner: volume size class
+// (floor(log2 voxels) / 3, i.e. per doubling of every axis) and image class
+// (floor(log2 pixels) / 2, i.e. per doubling of each side).
+std::string batch_key(const vr_volume* v, int32_t W, int32_t H) {
+  char buf[64];
+  snprintf(buf, sizeof buf, "batch/v%d/i%d", log2_floor((double)v->n[0] * v->n[1] * v->n[2]) / 3,
+           log2_floor((double)W * H) / 2);
+  return buf;
+}
+
+// Tile width of a batched request: the autotuner's choice for its size class, else 8.
+int32_t batch_tile(const vr_ctx* ctx, const vr_volume* v, int32_t W, int32_t H) {
+  const std::string key = batch_key(v, W, H);
+  for (const auto& e : ctx->tune)
+    if (e.key == key) return e.tile;
+  return 8;
+}
+
+int check_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p) {
   if (p && p->mode != VR_MODE_DVR) return fail(VR_EUNSUPPORTED, "batched rendering implements VR_MODE_DVR only");
   if (ctx->mask_n > 0) return fail(VR_EUNSUPPORTED, "batched rendering takes no channel mask");
   for (int32_t i = 0; i < n; i++) {
@@ -91,34 +114,41 @@ int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params
     if (!std::isfinite(r.vmin) || !std::isfinite(r.vmax) || r.vmax < r.vmin)
       return fail(VR_EINVAL, "request %d: window must be finite with vmax >= vmin", i);
   }
-  vr_batch* b = *cache;
-  if (b && b->ctx != ctx) return fail(VR_EINVAL, "batch cache belongs to another context");
-  const int32_t blocks = force_blocks > 0 ? force_blocks : batch_blocks(ctx);
-  // shape key
-  bool match = b && (int32_t)b->vols.size() == n && b->step == p->step && b->tau == (float)(p->tau >= 1.0 ? 2.0 : p->tau) &&
-               b->blocks == blocks;
-  for (int32_t i = 0; match && i < n; i++)
-    match = b->vols[i] == reqs[i].vol && b->W[i] == reqs[i].view.W && b->H[i] == reqs[i].view.H && b->M[i] == reqs[i].m;
-  // request windows that default to the volume range need the range first
+  return VR_OK;
+}
+
+// Descriptor table of a batch: requests in longest-first order (estimated
+// samples per tile), each with its tile shape, and the work-item count.
+// tiles: per-request tile width (4, 8, 16 or 32), or null for the tuned ones.
+// Requests whose window defaults to the volume range need that range: with
+// may_reduce = false they fail (VR_ESTATE) instead of computing it.
+int plan_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, const int32_t* tiles,
+               bool may_reduce, hipStream_t s, std::vector<BatchReq>& desc, int32_t& items, int32_t& maxM) {
   std::vector<double> vmin((size_t)n), vmax((size_t)n);
+  std::vector<int32_t> tw((size_t)n);
   for (int32_t i = 0; i < n; i++) {
     vmin[i] = reqs[i].vmin;
     vmax[i] = reqs[i].vmax;
     if (vmin[i] == 0.0 && vmax[i] == 0.0) {
       vr_volume* v = const_cast<vr_volume*>(reqs[i].vol);
+      if (!v->have_range && !may_reduce)
+        return fail(VR_ESTATE, "request %d: the volume's range is not known yet; give the window", i);
       VR_TRY(volume_range(v, s));
       vmin[i] = v->vmin;
       vmax[i] = v->vmax;
     }
+    tw[i] = tiles ? tiles[i] : batch_tile(ctx, reqs[i].vol, reqs[i].view.W, reqs[i].view.H);
+    if (tw[i] != 4 && tw[i] != 8 && tw[i] != 16 && tw[i] != 32)
+      return fail(VR_EINVAL, "request %d: tile width %d not 4, 8, 16 or 32", i, tw[i]);
   }
-  // longest-first order of requests (by estimated samples per tile)
   std::vector<int32_t> order((size_t)n);
   std::iota(order.begin(), order.end(), 0);
   std::vector<double> cost((size_t)n);
-  for (int32_t i = 0; i < n; i++) cost[i] = tile_cost(reqs[i].vol, reqs[i].view, p->step);
+  for (int32_t i = 0; i < n; i++) cost[i] = 64.0 * pixel_cost(reqs[i].vol, reqs[i].view, p->step);
   std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
-  std::vector<BatchReq> desc((size_t)n);
-  int32_t items = 0, maxM = 2;
+  desc.assign((size_t)n, BatchReq());
+  items = 0;
+  maxM = 2;
   for (int32_t k = 0; k < n; k++) {
     const int32_t i = order[k];
     const vr_request& r = reqs[i];
@@ -132,12 +162,33 @@ int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params
     d.tf = reinterpret_cast<const float4*>(r.tf);
     d.out = reinterpret_cast<float4*>(r.out);
     d.M = r.m;
-    d.tiles_x = (r.view.W + 7) / 8;
-    d.ntiles = d.tiles_x * ((r.view.H + 7) / 8);
+    int sh = 0;
+    while ((1 << sh) < tw[i]) sh++;
+    d.tile_shift = sh;
+    d.tiles_x = (r.view.W + tw[i] - 1) / tw[i];
+    const int32_t th = 64 / tw[i];
+    d.ntiles = d.tiles_x * ((r.view.H + th - 1) / th);
     d.item_begin = items;
     items += d.ntiles;
     maxM = std::max(maxM, r.m);
   }
+  return VR_OK;
+}
+
+int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, vr_batch** cache,
+                 hipStream_t s, int32_t force_blocks, const int32_t* tiles) {
+  VR_TRY(check_batch(ctx, reqs, n, p));
+  vr_batch* b = *cache;
+  if (b && b->ctx != ctx) return fail(VR_EINVAL, "batch cache belongs to another context");
+  const int32_t blocks = force_blocks > 0 ? force_blocks : batch_blocks(ctx);
+  // shape key
+  bool match = b && (int32_t)b->vols.size() == n && b->step == p->step && b->tau == (float)(p->tau >= 1.0 ? 2.0 : p->tau) &&
+               b->blocks == blocks;
+  for (int32_t i = 0; match && i < n; i++)
+    match = b->vols[i] == reqs[i].vol && b->W[i] == reqs[i].view.W && b->H[i] == reqs[i].view.H && b->M[i] == reqs[i].m;
+  std::vector<BatchReq> desc;
+  int32_t items = 0, maxM = 2;
+  VR_TRY(plan_batch(ctx, reqs, n, p, tiles, true, s, desc, items, maxM));
   if (b && match && (b->total_items != items || b->max_M != maxM)) match = false;
   if (!match) {
     if (!b) {
@@ -221,7 +272,7 @@ int vr_render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_par
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
   VR_TRY(ctx_begin(ctx, s));
-  VR_TRY(render_batch(ctx, reqs, n, p, cache, s, 0));
+  VR_TRY(render_batch(ctx, reqs, n, p, cache, s, 0, nullptr));
   return ctx_end(ctx, s);
 }
 

@@ -2,10 +2,12 @@
 // persistent launch (gfx950).
 //
 // Each request is a whole (unbricked) volume with its own view, transfer
-// function, window and output image.  Work items are (request, 8x8 pixel
-// tile) pairs numbered in the host's order (requests with the most samples
-// per tile first, so the longest items start first).  A grid sized to the
-// device pulls items from one atomic counter, one item per wavefront per
+// function, window and output image.  Work items are (request, pixel tile)
+// pairs numbered in the host's order (requests with the most samples per tile
+// first, so the longest items start first); a request's tile is 64 pixels,
+// 4 x 16, 8 x 8, 16 x 4 or 32 x 2, as the autotuner chose for its size
+// class.  A grid sized to the device pulls items from one atomic counter, one
+// item per wavefront per
 // pull, until the queue is empty: every wavefront reaches the exit test after
 // each item, so the grid drains by itself.  A wavefront keeps the table of
 // the request it is working on in its own LDS slot and reloads it only when
@@ -53,7 +55,8 @@ __global__ __launch_bounds__(256) void k_batch(BatchArgs ba) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     const int t = (int)item - rq.item_begin;
     const int tx = t % rq.tiles_x, ty = t / rq.tiles_x;
-    const int u = tx * 8 + (lane & 7), v = ty * 8 + (lane >> 3);
+    const int sh = rq.tile_shift;
+    const int u = (tx << sh) + (lane & ((1 << sh) - 1)), v = ty * (64 >> sh) + (lane >> sh);
     if (u < rq.cam.W && v < rq.cam.H) {
       double o[3], d[3];
       pixel_ray(rq.cam, u, v, o, d);

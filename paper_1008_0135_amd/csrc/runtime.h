@@ -173,6 +173,12 @@ void tuned_shape(const vr_ctx* ctx, const vr_volume* vol, int32_t W, int32_t H, 
 std::string tune_key(const vr_volume* vol, int32_t W, int32_t H, int32_t mode);
 void tune_load(vr_ctx* ctx);
 int render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, vr_batch** cache, hipStream_t s,
-                 int32_t force_blocks);
+                 int32_t force_blocks, const int32_t* tiles);
+int check_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p);
+int plan_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, const int32_t* tiles,
+               bool may_reduce, hipStream_t s, std::vector<BatchReq>& desc, int32_t& items, int32_t& maxM);
+std::string batch_key(const vr_volume* v, int32_t W, int32_t H);
+int32_t batch_tile(const vr_ctx* ctx, const vr_volume* v, int32_t W, int32_t H);
+int batch_blocks(vr_ctx* ctx);
 
 }  // namespace vr

@@ -3,6 +3,7 @@
 // in the context, optionally persisted to the file named by VR_TUNE_CACHE.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -56,6 +57,10 @@ void tune_load(vr_ctx* ctx) {
   while (std::fscanf(f, "%255s %d %d %d %lf", key, &tile, &budget, &mode, &ms) == 5) {
     if (std::strcmp(key, "batch/waves_per_cu") == 0) {
       ctx->tune_waves_per_cu = tile;
+      continue;
+    }
+    if (std::strncmp(key, "batch/", 6) == 0) {
+      if (tile == 4 || tile == 8 || tile == 16 || tile == 32) ctx->tune.push_back(vr_ctx::TuneEntry{key, tile, 0, 1, ms});
       continue;
     }
     if ((tile == 4 || tile == 8 || tile == 16) && budget >= 256 && budget <= 32768 && mode >= 0 && mode <= 3)
@@ -169,12 +174,56 @@ int vr_autotune_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_p
   clear_error();
   if (!ctx || !reqs || !cache || !out || n < 1) return fail(VR_EINVAL, "ctx, reqs, cache and out must be non-NULL");
   VR_TRY(check_params(p));
+  VR_TRY(check_batch(ctx, reqs, n, p));
   DeviceGuard g(ctx->device);
   hipStream_t s = (hipStream_t)stream;
   int cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
+  // 1. tile shape per size class: the requests of one class rendered as a
+  //    batch of their own with each candidate tile (same grid as the default)
+  std::vector<std::string> keys((size_t)n);
+  for (int32_t i = 0; i < n; i++) keys[i] = batch_key(reqs[i].vol, reqs[i].view.W, reqs[i].view.H);
+  std::vector<std::string> classes;
+  for (const std::string& k : keys)
+    if (std::find(classes.begin(), classes.end(), k) == classes.end()) classes.push_back(k);
+  int32_t ntile_wins[4] = {0, 0, 0, 0};
+  for (const std::string& key : classes) {
+    std::vector<vr_request> sub;
+    for (int32_t i = 0; i < n; i++)
+      if (keys[i] == key) sub.push_back(reqs[i]);
+    const int32_t m = (int32_t)sub.size();
+    const int32_t tcand[] = {8, 16, 4, 32};
+    double best = INFINITY;
+    int32_t pick = 8;
+    vr_batch* tmp = nullptr;
+    int rc = VR_OK;
+    for (int32_t t : tcand) {
+      std::vector<int32_t> tiles((size_t)m, t);
+      double ms = 0.0;
+      rc = time_ms(s, 3, [&]() {
+        VR_TRY(ctx_begin(ctx, s));
+        VR_TRY(render_batch(ctx, sub.data(), m, p, &tmp, s, 0, tiles.data()));
+        return ctx_end(ctx, s);
+      }, ms);
+      if (rc != VR_OK) break;
+      if (ms < best) {
+        best = ms;
+        pick = t;
+      }
+    }
+    (void)vr_batch_destroy(tmp);
+    if (rc != VR_OK) return rc;
+    for (size_t i = 0; i < ctx->tune.size(); i++)
+      if (ctx->tune[i].key == key) {
+        ctx->tune.erase(ctx->tune.begin() + (long)i);
+        break;
+      }
+    ctx->tune.push_back(vr_ctx::TuneEntry{key, pick, 0, 1, best});
+    ntile_wins[pick == 4 ? 0 : pick == 8 ? 1 : pick == 16 ? 2 : 3]++;
+  }
+  // 2. persistent-grid occupancy for the whole batch with the tuned tiles
   const int32_t cands[] = {8, 2, 4, 16, 32};
   double best = INFINITY, dflt = INFINITY;
   int32_t pick = 8;
@@ -182,7 +231,7 @@ int vr_autotune_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_p
     double ms = 0.0;
     VR_TRY(time_ms(s, 3, [&]() {
       VR_TRY(ctx_begin(ctx, s));
-      VR_TRY(render_batch(ctx, reqs, n, p, cache, s, std::max(1, cus * wpc / 4)));
+      VR_TRY(render_batch(ctx, reqs, n, p, cache, s, std::max(1, cus * wpc / 4), nullptr));
       return ctx_end(ctx, s);
     }, ms));
     if (wpc == 8) dflt = ms;
@@ -193,16 +242,34 @@ int vr_autotune_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_p
   }
   ctx->tune_waves_per_cu = pick;
   tune_save(ctx);
-  // leave the cache holding the graph of the chosen grid
+  // leave the cache holding the graph of the chosen grid and tiles
   VR_TRY(ctx_begin(ctx, s));
-  VR_TRY(render_batch(ctx, reqs, n, p, cache, s, 0));
+  VR_TRY(render_batch(ctx, reqs, n, p, cache, s, 0, nullptr));
   VR_TRY(ctx_end(ctx, s));
-  out->tile = 8;
+  // the most frequent tile choice over the classes
+  int32_t most = 1;
+  for (int32_t k = 0; k < 4; k++)
+    if (ntile_wins[k] > ntile_wins[most]) most = k;
+  out->tile = 4 << most;
   out->waves_per_cu = pick;
   out->ms = best;
   out->ms_default = dflt;
   out->lds_budget = 0;
   out->march_mode = 1;
+  return VR_OK;
+}
+
+/*
+ * Tile width each request of a batch runs with (the tuned choice of its size
+ * class, else 8): tiles[i] for reqs[i].
+ */
+int vr_batch_tiles(const vr_ctx* ctx, const vr_request* reqs, int32_t n, int32_t* tiles) {
+  clear_error();
+  if (!ctx || !reqs || !tiles || n < 0) return fail(VR_EINVAL, "ctx, reqs and tiles must be non-NULL");
+  for (int32_t i = 0; i < n; i++) {
+    if (!reqs[i].vol) return fail(VR_EINVAL, "request %d has no volume", i);
+    tiles[i] = batch_tile(ctx, reqs[i].vol, reqs[i].view.W, reqs[i].view.H);
+  }
   return VR_OK;
 }
 

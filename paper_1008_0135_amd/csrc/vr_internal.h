@@ -256,6 +256,8 @@ struct BatchReq {
   const float4* tf;
   float4* out;
   int32_t M, tiles_x, ntiles, item_begin;
+  int32_t tile_shift;    // tile width 2^tile_shift pixels (4, 8, 16 or 32), height 64 / width
+  int32_t pad_[3];
 };
 
 struct BatchArgs {

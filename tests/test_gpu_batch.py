@@ -204,3 +204,46 @@ def test_c4_full_batch_parity(ctx):
     vr.vr_batch_destroy(cache)
     for v in vols:
         vr.vr_volume_destroy(v)
+
+
+@pytest.mark.parametrize("tile", [4, 16, 32])
+def test_batch_tile_shapes_from_tune_cache(tile, tmp_path, monkeypatch):
+    """Every tile shape the batch autotuner can choose (read back from a
+    VR_TUNE_CACHE file, one entry per size class) gives the plain renders' bits."""
+    _say(f"batch tile {tile} x {64 // tile} from the tune cache")
+    descs = _requests(77, 10, dim_range=(24, 96), img_range=(17, 150))
+    path = tmp_path / "tune.txt"
+    # one entry per size class present (volume class floor(log2 voxels) / 3,
+    # image class floor(log2 pixels) / 2, as the library documents)
+    keys = set()
+    for d in descs:
+        n1, n2, n3 = d["dims"]
+        W, H = d["image"]
+        keys.add(f"batch/v{int(np.floor(np.log2(n1 * n2 * n3))) // 3}/i{int(np.floor(np.log2(W * H))) // 2}")
+    path.write_text("".join(f"{k} {tile} 0 1 0.1\n" for k in sorted(keys)))
+    monkeypatch.setenv("VR_TUNE_CACHE", str(path))
+    c = vr.vr_create(0)
+    try:
+        vols, arrays = _volumes(c, descs)
+        params = vr.make_params(tau=0.99)
+        reqs, outs = [], []
+        for i, d in enumerate(descs):
+            W, H = d["image"]
+            t = torch.from_numpy(d["tf"]).cuda()
+            o = torch.full((H, W, 4), -2.0, device="cuda")
+            outs.append((o, t))
+            reqs.append(vr.make_request(vols[i], d["view"], W, H, t, 0.0, 0.0, o))
+        assert vr.vr_batch_tiles(c, reqs) == [tile] * len(reqs)
+        cache = vr.vr_render_batch(c, reqs, params, None)
+        torch.cuda.synchronize()
+        for i, d in enumerate(descs):
+            W, H = d["image"]
+            mn, mx = float(arrays[i].min()), float(arrays[i].max())
+            ref = _plain(c, vols[i], d["view"], W, H, d["tf"], mn, mx, params)
+            torch.cuda.synchronize()
+            assert np.array_equal(outs[i][0].cpu().numpy(), ref.cpu().numpy()[0]), (tile, i)
+        vr.vr_batch_destroy(cache)
+        for v in vols:
+            vr.vr_volume_destroy(v)
+    finally:
+        vr.vr_destroy(c)
