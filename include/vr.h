@@ -370,6 +370,25 @@ int vr_render_batch(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_par
                     uintptr_t stream);
 int vr_batch_destroy(vr_batch *b);
 
+/*
+ * Allocation-free variant of vr_render_batch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The same persistent kernel and the same
+ * images, launched directly (no graph); its descriptor table and work counter
+ * live in a fixed device array of the library (at most 512 requests, about 160 KiB
+ * per device, held by each device the library runs on until the process
+ * ends); the descriptors travel through pinned staging made by vr_create.
+ * The call allocates nothing.  Windows must be given, or the volume's range
+ * already known (vr_volume_create computes it).  Every call on one device
+ * shares that device's array: calls on one context are ordered, but calls
+ * through different contexts of one device must not overlap in time (they
+ * would race on the array).  Errors: VR_EINVAL (n outside [1, 512], bad
+ * request), VR_ESTATE (a volume range not known yet), VR_EUNSUPPORTED
+ * (p->mode other than VR_MODE_DVR, a channel mask set), VR_EHIP.
+ */
+int vr_render_batch_noalloc(vr_ctx *ctx, const vr_request *reqs, int32_t n, const vr_params *p,
+                            uintptr_t stream);
+
 /* ------------------------------------------------------------------ autotuning */
 typedef struct {
   int32_t tile;          /* chosen wavefront tile edge (pixels) */

@@ -117,6 +117,7 @@ _SIGS = {
     "vr_autotune": (_I, [_P, _P, _P, _P, _P, _U]),
     "vr_autotune_batch": (_I, [_P, _P, _I32, _P, _P, _P, _U]),
     "vr_batch_tiles": (_I, [_P, _P, _I32, _P]),
+    "vr_render_batch_noalloc": (_I, [_P, _P, _I32, _P, _U]),
     "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "vr_count_samples": (_I, [_P, _P, _D, _P]),
     "vr_partition": (_I, [_P, _P, _P, _P]),
@@ -388,6 +389,13 @@ def vr_autotune_batch(ctx, reqs, params, cache=None, stream=None):
     _check(lib().vr_autotune_batch(ctx, arr, len(reqs), C.byref(params), C.byref(h), C.byref(r), _stream(stream)),
            "vr_autotune_batch")
     return r, h.value
+
+
+def vr_render_batch_noalloc(ctx, reqs, params, stream=None):
+    """Batched render that allocates nothing (library-held device scratch)."""
+    arr = (vr_request * len(reqs))(*reqs)
+    _check(lib().vr_render_batch_noalloc(ctx, arr, len(reqs), C.byref(params), _stream(stream)),
+           "vr_render_batch_noalloc")
 
 
 def vr_batch_tiles(ctx, reqs):

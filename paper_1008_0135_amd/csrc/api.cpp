@@ -382,6 +382,18 @@ int vr_create(int device, vr_ctx** out) {
       vr_destroy(ctx);
       return fail(VR_EHIP, "hipEventCreate failed");
     }
+  // set-up of the allocation-free batched path: the device's scratch address,
+  // a pinned staging buffer for its descriptors and the event of their copy
+  if (int rc = noalloc_init(device); rc != VR_OK) {
+    vr_destroy(ctx);
+    return rc;
+  }
+  if (hipHostMalloc(&ctx->na_host, kNoAllocBytes, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->na_copied, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    vr_destroy(ctx);
+    return fail(VR_ENOMEM, "pinned staging for the allocation-free batch failed");
+  }
   *out = ctx;
   return VR_OK;
 }
@@ -412,6 +424,8 @@ int vr_destroy(vr_ctx* ctx) {
     if (ctx->aux_join_ev[i]) (void)hipEventDestroy(ctx->aux_join_ev[i]);
   }
   if (ctx->aux_fork_ev) (void)hipEventDestroy(ctx->aux_fork_ev);
+  if (ctx->na_host) (void)hipHostFree(ctx->na_host);
+  if (ctx->na_copied) (void)hipEventDestroy(ctx->na_copied);
   delete ctx;
   return VR_OK;
 }

@@ -276,6 +276,42 @@ int vr_render_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_par
   return ctx_end(ctx, s);
 }
 
+int vr_render_batch_noalloc(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* p, uintptr_t stream) {
+  clear_error();
+  if (!ctx || !reqs || n < 1) return fail(VR_EINVAL, "ctx and reqs must be non-NULL, n >= 1");
+  if (n > kNoAllocMaxReq)
+    return fail(VR_EINVAL, "%d requests exceed the allocation-free batch's limit of %d", n, kNoAllocMaxReq);
+  VR_TRY(check_params(p));
+  VR_TRY(check_batch(ctx, reqs, n, p));
+  DeviceGuard g(ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* dev = static_cast<unsigned char*>(noalloc_scratch(ctx->device));
+  if (!dev || !ctx->na_host) return fail(VR_ESTATE, "allocation-free batch not set up on device %d", ctx->device);
+  std::vector<BatchReq> desc;
+  int32_t items = 0, maxM = 2;
+  VR_TRY(plan_batch(ctx, reqs, n, p, nullptr, false, s, desc, items, maxM));
+  VR_TRY(ctx_begin(ctx, s));
+  // the previous call's copy out of the pinned staging must be done before it is overwritten
+  if (ctx->na_pending) VR_HIP(hipEventSynchronize(ctx->na_copied));
+  const size_t bytes = sizeof(BatchReq) * (size_t)n;
+  std::memcpy(ctx->na_host, desc.data(), bytes);
+  VR_HIP(hipMemcpyAsync(dev, ctx->na_host, bytes, hipMemcpyHostToDevice, s));
+  VR_HIP(hipEventRecord(ctx->na_copied, s));
+  ctx->na_pending = true;
+  BatchArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.reqs = reinterpret_cast<const BatchReq*>(dev);
+  a.counter = reinterpret_cast<unsigned int*>(dev + sizeof(BatchReq) * (size_t)kNoAllocMaxReq);
+  a.nreq = n;
+  a.total_items = items;
+  a.max_M = maxM;
+  a.step = p->step;
+  a.tau = (float)(p->tau >= 1.0 ? 2.0 : p->tau);
+  // the work counter is cleared by a kernel of the launch sequence (no memset)
+  VR_HIP(launch_batch(a, batch_blocks(ctx), s));
+  return ctx_end(ctx, s);
+}
+
 int vr_batch_destroy(vr_batch* b) {
   if (!b) return VR_OK;
   DeviceGuard g(b->ctx->device);

@@ -13,10 +13,45 @@
 // the request it is working on in its own LDS slot and reloads it only when
 // the next item belongs to another request.  The per-sample arithmetic is the
 // one of every other march (sample.h).
+#include <mutex>
+
+#include "runtime.h"
 #include "sample.h"
 #include "vr_internal.h"
 
 namespace vr {
+
+// Device scratch of the allocation-free batched entry point
+// (vr_render_batch_noalloc): the descriptor table of at most
+// kNoAllocMaxReq requests, then the work counter.  Each device holds its own
+// copy for the life of the process; host code reaches it only through the
+// address hipGetSymbolAddress returns for that device.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(VR_EUNSUPPORTED, "device %d beyond %d", device, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return VR_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(VR_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device, hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = p;
+  return VR_OK;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 namespace {
 

@@ -110,6 +110,11 @@ struct vr_ctx {
   };
   std::vector<TuneEntry> tune;
   int32_t tune_waves_per_cu = 0;  // persistent-grid occupancy of the batched path (0 = default 8)
+  // allocation-free batched path: pinned staging for its descriptor table
+  // (made at creation) and the event of the last copy out of it
+  void* na_host = nullptr;
+  hipEvent_t na_copied = nullptr;
+  bool na_pending = false;
 };
 
 struct vr_volume {
@@ -180,5 +185,9 @@ int plan_batch(vr_ctx* ctx, const vr_request* reqs, int32_t n, const vr_params* 
 std::string batch_key(const vr_volume* v, int32_t W, int32_t H);
 int32_t batch_tile(const vr_ctx* ctx, const vr_volume* v, int32_t W, int32_t H);
 int batch_blocks(vr_ctx* ctx);
+// Allocation-free batched path: look up the device's scratch address once
+// (device current; called by vr_create), and return it (null before init).
+int noalloc_init(int device);
+void* noalloc_scratch(int device);
 
 }  // namespace vr

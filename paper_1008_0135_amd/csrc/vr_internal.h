@@ -260,6 +260,12 @@ struct BatchReq {
   int32_t pad_[3];
 };
 
+// Allocation-free batched entry point: its device scratch holds the
+// descriptor table of at most kNoAllocMaxReq requests, then the work counter.
+constexpr int kNoAllocMaxReq = 512;
+constexpr size_t kNoAllocBytes = sizeof(BatchReq) * kNoAllocMaxReq + 256;
+constexpr int kMaxDevices = 64;
+
 struct BatchArgs {
   const BatchReq* reqs;
   unsigned int* counter;  // next work item
