@@ -76,8 +76,8 @@ def lib():
 def _bind(L):
     """Declare the argument types of the oracle library's entry points."""
     P = C.c_void_p
-    L.or_render_rays.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, C.c_int]
-    L.or_render_candidates.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, C.c_int, P, P, C.c_int]
+    L.or_render_rays.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, P, C.c_int]
+    L.or_render_candidates.argtypes = [P, P, C.c_int, P, P, P, C.c_int64, P, P, P, P, C.c_int, P, P, C.c_int]
     L.or_render_images.argtypes = [P, P, C.c_int, P, P, P, C.c_int]
     L.or_render_grad.argtypes = [P, P, P, P, P, P, C.c_int]
     L.or_minmax.argtypes = [P, C.c_int64, P, P, P, C.c_int]
@@ -202,7 +202,7 @@ def _ties(sc, vw, nv, rv, ru, rr, nthreads):
     ncand = np.zeros(n, np.int32)
     if n:
         rc = lib().or_render_candidates(C.byref(sc), vw, nv, _ptr(rv), _ptr(ru), _ptr(rr), n, None, None, None,
-                                        MAXC, _ptr(cand), _ptr(ncand), int(nthreads))
+                                        None, MAXC, _ptr(cand), _ptr(ncand), int(nthreads))
         if rc != 0:
             raise ValueError("oracle candidates: bad input")
     return cand, ncand
@@ -243,7 +243,8 @@ def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0
                 extent=0.0, bricks=None, ert_margin=1e-5, geom_margin=1e-9, nthreads=0, mode=MODE_DVR,
                 eye_dist=0.0, mask=None):
     """Render selected rays (view index, pixel u, pixel v).  Returns dict like ``render``
-    (``nsamples`` per ray, ``ties.index`` into the ray list)."""
+    (``nsamples`` per ray, ``ties.index`` into the ray list) plus ``neval``: samples
+    evaluated per ray (each sub-volume's samples up to its own stop)."""
     sc, keep = _scene(vol, tf, vmin, vmax, step, tau, bricks, ert_margin, geom_margin, mode, mask)
     vw = _views(views, W, H, extent, eye_dist)
     rv = np.ascontiguousarray(ray_view, np.int32)
@@ -253,14 +254,15 @@ def render_rays(vol, tf, views, W, H, ray_view, ray_u, ray_v, vmin, vmax, step=0
     img = np.zeros((n, 4), np.float64)
     flags = np.zeros(n, np.uint8)
     ns = np.zeros(n, np.int64)
+    ne = np.zeros(n, np.int64)
     rc = lib().or_render_rays(C.byref(sc), vw, len(views), _ptr(rv), _ptr(ru), _ptr(rr), n,
-                              _ptr(img), _ptr(flags), _ptr(ns), int(nthreads))
+                              _ptr(img), _ptr(flags), _ptr(ns), _ptr(ne), int(nthreads))
     if rc != 0:
         raise ValueError("oracle render_rays: bad input")
     idx = np.flatnonzero((flags & FLAG_ERT) != 0)
     cand, ncand = _ties(sc, vw, len(views), rv[idx].copy(), ru[idx].copy(), rr[idx].copy(), nthreads)
     del keep
-    return dict(image=img, flags=flags, nsamples=ns, ties=dict(index=idx, cand=cand, ncand=ncand))
+    return dict(image=img, flags=flags, nsamples=ns, neval=ne, ties=dict(index=idx, cand=cand, ncand=ncand))
 
 
 def match_error(got, ref):

@@ -378,7 +378,7 @@ static int ray_candidates(const ray_scratch *rs, double *cand, int maxc) {
 /* Render one ray.  out[4] = (C, A); returns flags.  With cand != NULL, also
  * lists the ray's valid images (see ray_candidates) and their count in *ncand. */
 static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratch *rs, double out[4],
-                 int64_t *nsamp, double *cand, int maxc, int *ncand) {
+                 int64_t *nsamp, int64_t *neval, double *cand, int maxc, int *ncand) {
   double o[3], d[3], lo[3], hi[3];
   int flags = 0, gtie = 0;
   pixel_ray(cam, u, v, o, d);
@@ -388,6 +388,7 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
   }
   for (int c = 0; c < 4; c++) out[c] = 0.0;
   *nsamp = 0;
+  *neval = 0;
   if (ncand) *ncand = 0;
   double tin, tout;
   int hit = slab(o, d, lo, hi, &tin, &tout, &gtie, sc->geom_margin);
@@ -414,6 +415,7 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
       if (s < 0.0) s = 0.0;
       if (s > 1.0) s = 1.0;
       s *= mask_at(sc, i0, f);
+      if (m < 1.0) (*neval)++; /* evaluated: the maximum had not reached 1 */
       if (s > m) m = s;
     }
     for (int c = 0; c < 4; c++) out[c] = m;
@@ -446,6 +448,7 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
     double val = trilinear(sc, p, i0, f);
     classify(sc, val, rgba, &ti, &tw, &sraw);
     rgba[3] *= mask_at(sc, i0, f);
+    if (!ch->stopped) (*neval)++;
     chain_feed(sc, ch, rgba);
     if (sc->nboxes == 0 && sc->tau < 1.0 && ch->hi_seen) break;
   }
@@ -475,7 +478,7 @@ static int trace(const or_scene *sc, const camera *cam, int u, int v, ray_scratc
 
 int or_render_candidates(const or_scene *sc, const or_view *views, int nviews, const int32_t *ray_view,
                          const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, uint8_t *flags,
-                         int64_t *nsamp, int maxc, double *cand, int32_t *ncand, int nthreads);
+                         int64_t *nsamp, int64_t *neval, int maxc, double *cand, int32_t *ncand, int nthreads);
 
 static int scene_ok(const or_scene *sc) {
   if (!sc || !sc->vol || !sc->tf || sc->M < 2 || sc->step <= 0.0) return 0;
@@ -495,14 +498,15 @@ static void set_threads(int nthreads) {
 /*
  * Render a list of rays.  ray_view/ray_u/ray_v select (view, pixel).  Outputs
  * per ray: rgba[4] (premultiplied colour, opacity), flags, nsamp (lattice
- * samples inside the volume box).  Any output pointer may be NULL.  Returns 0
- * on success, -1 on bad input.
+ * samples inside the volume box), neval (samples evaluated: those of each
+ * chain up to its stop).  Any output pointer may be NULL.  Returns 0 on
+ * success, -1 on bad input.
  */
 int or_render_rays(const or_scene *sc, const or_view *views, int nviews, const int32_t *ray_view,
                    const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, uint8_t *flags,
-                   int64_t *nsamp, int nthreads) {
-  return or_render_candidates(sc, views, nviews, ray_view, ray_u, ray_v, nrays, rgba, flags, nsamp, 0, NULL,
-                              NULL, nthreads);
+                   int64_t *nsamp, int64_t *neval, int nthreads) {
+  return or_render_candidates(sc, views, nviews, ray_view, ray_u, ray_v, nrays, rgba, flags, nsamp, neval, 0,
+                              NULL, NULL, nthreads);
 }
 
 /*
@@ -513,7 +517,7 @@ int or_render_rays(const or_scene *sc, const or_view *views, int nviews, const i
  */
 int or_render_candidates(const or_scene *sc, const or_view *views, int nviews, const int32_t *ray_view,
                          const int32_t *ray_u, const int32_t *ray_v, int64_t nrays, double *rgba, uint8_t *flags,
-                         int64_t *nsamp, int maxc, double *cand, int32_t *ncand, int nthreads) {
+                         int64_t *nsamp, int64_t *neval, int maxc, double *cand, int32_t *ncand, int nthreads) {
   if (!scene_ok(sc) || nviews < 1 || (cand && (maxc < 1 || !ncand))) return -1;
   set_threads(nthreads);
   camera *cams = (camera *)malloc(sizeof(camera) * (size_t)nviews);
@@ -533,13 +537,14 @@ int or_render_candidates(const or_scene *sc, const or_view *views, int nviews, c
         continue;
       }
       double o4[4];
-      int64_t ns;
+      int64_t ns, ne;
       int nc = 0;
-      int fl = trace(sc, &cams[vi], ray_u[r], ray_v[r], &rs, o4, &ns, cand ? cand + 4 * (int64_t)maxc * r : NULL,
-                     maxc, &nc);
+      int fl = trace(sc, &cams[vi], ray_u[r], ray_v[r], &rs, o4, &ns, &ne,
+                     cand ? cand + 4 * (int64_t)maxc * r : NULL, maxc, &nc);
       if (rgba) memcpy(rgba + 4 * r, o4, sizeof(o4));
       if (flags) flags[r] = (uint8_t)fl;
       if (nsamp) nsamp[r] = ns;
+      if (neval) neval[r] = ne;
       if (cand) ncand[r] = nc;
     }
     free(rs.chains);
@@ -569,8 +574,8 @@ int or_render_images(const or_scene *sc, const or_view *views, int nviews, doubl
       for (int64_t q = 0; q < npix; q++) {
         int u = (int)(q % cam.W), v = (int)(q / cam.W);
         double o4[4];
-        int64_t ns;
-        int fl = trace(sc, &cam, u, v, &rs, o4, &ns, NULL, 0, NULL);
+        int64_t ns, ne;
+        int fl = trace(sc, &cam, u, v, &rs, o4, &ns, &ne, NULL, 0, NULL);
         if (rgba) memcpy(rgba + 4 * (off + q), o4, sizeof(o4));
         if (flags) flags[off + q] = (uint8_t)fl;
         vtotal += ns;

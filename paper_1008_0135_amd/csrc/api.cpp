@@ -362,6 +362,13 @@ int vr_create(int device, vr_ctx** out) {
     const int k = std::atoi(m);
     if (k == 2 || k == 3) ctx->ring_nslots = k;
   }
+  if (const char* m = std::getenv("VR_FOOT")) ctx->foot = std::atoi(m) != 0 ? 1 : 0;
+  if (const char* m = std::getenv("VR_FOOT_PAD")) ctx->foot_pad = std::max(0, std::min(32, std::atoi(m)));
+  if (const char* m = std::getenv("VR_DEBUG_PLAN")) ctx->debug_plan = std::atoi(m) != 0;
+  if (const char* m = std::getenv("VR_FOOT_RAYS")) {
+    const double r = std::atof(m);
+    if (r >= 16.0 && r <= 64.0) ctx->foot_rays = r;
+  }
   if (const char* m = std::getenv("VR_BWD_LAYERS")) {
     const int k = std::atoi(m);
     if (k >= 1 && k <= 16) ctx->bwd_layer_cap = k;
@@ -413,6 +420,7 @@ int vr_destroy(vr_ctx* ctx) {
   if (ctx->d_arena) (void)hipFree(ctx->d_arena);
   if (ctx->d_small) (void)hipFree(ctx->d_small);
   if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+  if (ctx->d_ovf) (void)hipFree(ctx->d_ovf);
   for (auto& t : ctx->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -144,7 +145,54 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       vp.pixels = (int64_t)W * H;
     }
   }
+  // parallel rays on the ring march: footprint cells instead of 8 x 8 pixel
+  // tiles (the cell counts replace the tile counts of the plan)
+  const bool plain_ring = base.mc == 0 && !base.mask;
+  for (int32_t v = 0; v < nviews; v++) {
+    ViewPlan& vp = plans[v];
+    if (extras || cams[v].persp || !ctx->foot || !(mode == 0 || mode == 3) || tw != 8) continue;
+    FootShape fs;
+    if (!choose_foot(cams[v], kRingCap, base.M, kRingMaxWaves, kRingWantWaves, ctx->foot_rays,
+                     plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad))
+      continue;
+    if (ctx->debug_plan)
+      std::fprintf(stderr, "[vr] view %d: cells axis %d Tf %.1f Tg %.2f nf %d ng %d slot %d nslots %d wpb %d waves %d rf %.3f rg %.3f\n",
+                   v, fs.axis, fs.Tf, fs.Tg, fs.nf, fs.ng, fs.slot, fs.nslots, fs.wpb, fs.waves, fs.rf, fs.rg);
+    vp.foot = true;
+    vp.fs = fs;
+    Box whole;
+    for (int i = 0; i < 3; i++) {
+      whole.lo[i] = 0;
+      whole.hi[i] = vol->n[i] - 1;
+      whole.closed[i] = 1;
+    }
+    int32_t tiles = 0;
+    size_t w = 0;  // wave of the brick (whole-ray termination)
+    for (size_t i = 0; i < vp.bv.size(); i++) {
+      DevBrickView& b = vp.bv[i];
+      if (global) {
+        while (w + 1 < vp.wave_begin.size() && (int32_t)i >= vp.wave_begin[w + 1]) w++;
+        if ((int32_t)i == vp.wave_begin[w]) tiles = 0;
+      }
+      int32_t ncf, ncg;
+      foot_cells(cams[v], fs, bricked ? vol->part.boxes[b.brick] : whole, b.cf0, b.cg0, ncf, ncg, b.fa0, b.fb0);
+      b.tiles_x = ncf;
+      b.tile_begin = tiles;
+      tiles += ncf * ncg;
+      if (global) vp.wave_tiles[w] = tiles;
+    }
+    if (!global) vp.ntiles = tiles;
+  }
   if (bricked && arena_pix > 0) VR_TRY(ensure_device(&ctx->d_arena, &ctx->arena_bytes, (size_t)arena_pix * 16));
+  // overflow lists of the footprint-cell marches: one per stream a view may use
+  int64_t foot_tiles = 0;
+  for (const ViewPlan& vp : plans)
+    if (vp.foot) {
+      foot_tiles = std::max<int64_t>(foot_tiles, vp.ntiles);
+      for (int32_t t : vp.wave_tiles) foot_tiles = std::max<int64_t>(foot_tiles, t);
+    }
+  const size_t ovf_stride = align16(256 + 4 * (size_t)foot_tiles);
+  if (foot_tiles > 0) VR_TRY(ensure_device(&ctx->d_ovf, &ctx->ovf_bytes, ovf_stride * vr_ctx::kAux));
   float4* arena = reinterpret_cast<float4*>(ctx->d_arena);
 
   // pack: [whole-volume brick] then per view [DevBrickView...][CompLayer...]
@@ -202,7 +250,32 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     bool lds = false, ring = false;
     int ring_wpb = 4;
     a.lds_budget = budget;
-    if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8) {
+    if (vp.foot) {
+      const FootShape& fs = vp.fs;
+      ring = true;
+      a.foot = 1;
+      a.slab_axis = fs.axis;
+      a.ring_slot = fs.slot;
+      a.ring_nslots = fs.nslots;
+      ring_wpb = fs.wpb;
+      a.foot_nf = fs.nf;
+      a.foot_ng = fs.ng;
+      a.foot_Tf = fs.Tf;
+      a.foot_Tg = fs.Tg;
+      a.fa_u = fs.fa_u;
+      a.fa_v = fs.fa_v;
+      a.fb_u = fs.fb_u;
+      a.fb_v = fs.fb_v;
+      unsigned char* ovf = reinterpret_cast<unsigned char*>(ctx->d_ovf) + (global ? (size_t)(v % vr_ctx::kAux) * ovf_stride : 0);
+      a.ovf_count = reinterpret_cast<unsigned int*>(ovf);
+      a.ovf_tiles = reinterpret_cast<int32_t*>(ovf + 256);
+      // pixels of the brick images (or of the frame) whose rays have no
+      // sample are not written by the cells: clear them first
+      if (!global) {
+        VR_HIP(launch_zero(bricked ? arena : reinterpret_cast<float4*>(out) + (int64_t)v * W * H,
+                           bricked ? vp.pixels : (int64_t)W * H, s));
+      }
+    } else if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8) {
       if (cams[v].persp) {
         std::vector<TileRegion> regs;
         for (const DevBrickView& b : vp.bv) {
@@ -256,6 +329,9 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         }
       }
     }
+    if (ring && !vp.foot && ctx->debug_plan)
+      std::fprintf(stderr, "[vr] view %d: tiles axis %d slot %d nslots %d wpb %d\n", v, a.slab_axis, a.ring_slot,
+                   a.ring_nslots, ring_wpb);
     if (ring) {
       a.tile_order = ctx->tile_order;
       a.tile_bw = ctx->tile_bw;

@@ -17,6 +17,9 @@ struct ViewPlan {
   // wave w = bv[wave_begin[w] .. wave_begin[w + 1]) with tile_begin counted
   // from the wave's first brick and wave_tiles[w] tiles
   std::vector<int32_t> wave_begin, wave_tiles;
+  // ring march over footprint cells (parallel rays): bv counts cells, not tiles
+  bool foot = false;
+  FootShape fs;
 };
 
 // Hook that replaces the march launch (the differentiable forward saves

@@ -53,6 +53,94 @@ using namespace ring;
 
 constexpr int kSlotsMax = 3;
 
+// Pixels of footprint cell (ci, cj) of a brick: lane r holds the run of image
+// row vrow0 + r that falls in the cell (first column u0, inclusive and
+// exclusive counts over the rows before it); n = pixels in the cell.
+struct FootRuns {
+  int vrow0, u0, incl, excl, n;
+};
+
+__device__ FootRuns foot_runs(const MarchArgs& a, const DevBrickView& bvw, int ci, int cj, int lane) {
+  FootRuns fr;
+  const double au = a.fa_u, av = a.fa_v, bu = a.fb_u, bvv = a.fb_v;
+  const double det = au * bvv - av * bu;
+  // image rows the cell's corners span (one row of margin each side)
+  double vmn = INFINITY, vmx = -INFINITY;
+  for (int q = 0; q < 4; ++q) {
+    const double ra = (double)(ci + (q & 1)) - bvw.fa0, rb = (double)(cj + (q >> 1)) - bvw.fb0;
+    const double vq = (au * rb - bu * ra) / det;
+    vmn = fmin(vmn, vq);
+    vmx = fmax(vmx, vq);
+  }
+  fr.vrow0 = uni(max(0, (int)floor(vmn) - 1));
+  const int vlast = uni(min(a.cam.H - 1, (int)ceil(vmx) + 1));
+  const int vrow = fr.vrow0 + lane;
+  int cnt_row = 0;
+  fr.u0 = 0;
+  if (vrow <= vlast) {
+    // columns u in [0, W) of row vrow whose cell coordinate lies in
+    // [cell, cell + 1): one run, the coordinate being monotone along the row
+    auto run = [&](double c0, double su, double sv, int cell, int& lo_u, int& hi_u) {
+      const int Wm = a.cam.W;
+      if (su == 0.0) {
+        const double x = foot_cell_coord(c0, su, sv, 0, vrow);
+        const bool in = x >= (double)cell && x < (double)(cell + 1);
+        lo_u = in ? 0 : 1;
+        hi_u = in ? Wm - 1 : 0;
+        return;
+      }
+      const bool inc = su > 0.0;
+      int l = 0, h = Wm;  // first column past the cell's near edge
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        const double x = foot_cell_coord(c0, su, sv, m, vrow);
+        if (inc ? x >= (double)cell : x < (double)(cell + 1)) h = m;
+        else l = m + 1;
+      }
+      lo_u = l;
+      l = 0;
+      h = Wm;  // first column past the cell's far edge
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        const double x = foot_cell_coord(c0, su, sv, m, vrow);
+        if (inc ? x >= (double)(cell + 1) : x < (double)cell) h = m;
+        else l = m + 1;
+      }
+      hi_u = l - 1;
+    };
+    int fl, fh, gl, gh;
+    run(bvw.fa0, au, av, ci, fl, fh);
+    run(bvw.fb0, bu, bvv, cj, gl, gh);
+    fr.u0 = max(fl, gl);
+    cnt_row = max(0, min(fh, gh) - fr.u0 + 1);
+  }
+  fr.incl = cnt_row;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(fr.incl, off);
+    if (lane >= off) fr.incl += y;
+  }
+  fr.excl = fr.incl - cnt_row;
+  fr.n = uni(__builtin_amdgcn_readlane(fr.incl, 63));
+  return fr;
+}
+
+// Pixel k (0 <= k < n) of the cell: the row is the first whose inclusive count
+// exceeds k.  Every lane takes part (cross-lane reads).
+__device__ __forceinline__ void foot_pixel(const FootRuns& fr, int k, int& u, int& v) {
+  int r = 0;
+  for (int stp = 32; stp > 0; stp >>= 1)
+    if (__shfl(fr.incl, r + stp - 1) <= k) r += stp;
+  r = min(r, 63);
+  u = __shfl(fr.u0, r) + (k - __shfl(fr.excl, r));
+  v = fr.vrow0 + r;
+}
+
+// Footprint cell of work item t of a brick view.
+__device__ __forceinline__ void foot_cell(const DevBrickView& bvw, int t, int& ci, int& cj) {
+  ci = bvw.cf0 + t % bvw.tiles_x;
+  cj = bvw.cg0 + t / bvw.tiles_x;
+}
+
 // SAVE (differentiable forward, whole volume): also store, for every group of
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
@@ -88,50 +176,87 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   const DevBrickView bvw = a.bv[lo];
   const DevBrick br = a.bricks[bvw.brick];
-  // tile numbering inside the brick's rectangle.  Tiles started together run
-  // at about the same layer; the L2 keeps a line only a few microseconds, so
-  // lines two windows share (the partial 128-byte ends of rows, the halo
-  // rows) are fetched once only when the two tiles are close in this order.
-  // Blocks of tiles put neighbours on both image axes close, whichever way
-  // the view turns the image against the storage axes.
   const int t = tile - bvw.tile_begin;
-  int tx, ty;
-  if (a.tile_order == 1) {
-    const int th = (bvw.h + 7) >> 3;
-    tx = t / th;
-    ty = t - tx * th;
-  } else if (a.tile_order == 2) {
-    // blocks of bw x bh tiles in row order (tiles in a block in row order),
-    // then the tiles right of the last whole block column, then those below
-    // the last whole block row
-    const int tw = bvw.tiles_x, th = (bvw.h + 7) >> 3, bw = a.tile_bw, bh = a.tile_bh;
-    const int fw = tw / bw, fh = th / bh, nfull = fw * fh * bw * bh;
-    if (t < nfull) {
-      const int q = t / (bw * bh), r = t - q * (bw * bh), qy = q / fw;
-      const int ry = r / bw;
-      tx = (q - qy * fw) * bw + (r - ry * bw);
-      ty = qy * bh + ry;
-    } else {
-      int r = t - nfull;
-      const int rw = tw - fw * bw;
-      if (r < rw * th) {
-        ty = r / rw;
-        tx = fw * bw + (r - ty * rw);
-      } else {
-        r -= rw * th;
-        const int lw = fw * bw;
-        const int ry = r / lw;
-        tx = r - ry * lw;
-        ty = fh * bh + ry;
-      }
-    }
+  // Footprint cells (parallel rays): the wavefront's rays are the pixels whose
+  // rays cross the brick-local plane b = 0 inside cell (ci, cj) of the
+  // Tf x Tg grid in (f, g).  Each image row holds one run of them (the cell
+  // coordinate is monotone along a row); lane r measures the run of row
+  // vrow0 + r, and a wave scan numbers the cell's pixels row by row.  The
+  // wavefront marches the cell's first 64 pixels.
+  const bool foot = !PERSP && !SAVE && a.foot != 0;
+  int ci = 0, cj = 0;
+  FootRuns fr;
+  int tx = 0, ty = 0;
+  if (foot) {
+    foot_cell(bvw, t, ci, cj);
+    fr = foot_runs(a, bvw, ci, cj, lane);
+    // cells of more than 64 pixels: the pixels past the 64th are marched by
+    // k_march_ring_ovf after this launch
+    if (fr.n > 64 && lane == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
   } else {
-    ty = t / bvw.tiles_x;
-    tx = t - ty * bvw.tiles_x;
+    // tile numbering inside the brick's rectangle.  Tiles started together run
+    // at about the same layer; the L2 keeps a line only a few microseconds, so
+    // lines two windows share (the partial 128-byte ends of rows, the halo
+    // rows) are fetched once only when the two tiles are close in this order.
+    // Blocks of tiles put neighbours on both image axes close, whichever way
+    // the view turns the image against the storage axes.
+    if (a.tile_order == 1) {
+      const int th = (bvw.h + 7) >> 3;
+      tx = t / th;
+      ty = t - tx * th;
+    } else if (a.tile_order == 2) {
+      // blocks of bw x bh tiles in row order (tiles in a block in row order),
+      // then the tiles right of the last whole block column, then those below
+      // the last whole block row
+      const int tw = bvw.tiles_x, th = (bvw.h + 7) >> 3, bw = a.tile_bw, bh = a.tile_bh;
+      const int fw = tw / bw, fh = th / bh, nfull = fw * fh * bw * bh;
+      if (t < nfull) {
+        const int q = t / (bw * bh), r = t - q * (bw * bh), qy = q / fw;
+        const int ry = r / bw;
+        tx = (q - qy * fw) * bw + (r - ry * bw);
+        ty = qy * bh + ry;
+      } else {
+        int r = t - nfull;
+        const int rw = tw - fw * bw;
+        if (r < rw * th) {
+          ty = r / rw;
+          tx = fw * bw + (r - ty * rw);
+        } else {
+          r -= rw * th;
+          const int lw = fw * bw;
+          const int ry = r / lw;
+          tx = r - ry * lw;
+          ty = fh * bh + ry;
+        }
+      }
+    } else {
+      ty = t / bvw.tiles_x;
+      tx = t - ty * bvw.tiles_x;
+    }
   }
-  const int lx = tx * 8 + (lane & 7), ly = ty * 8 + (lane >> 3);
-  const bool valid = lx < bvw.w && ly < bvw.h;
-  const int u = bvw.x0 + min(lx, bvw.w - 1), v = bvw.y0 + min(ly, bvw.h - 1);
+  // the march of the wavefront's 64 rays (a single pass: early exits leave it)
+  do {
+  int lx, ly, u, v;
+  bool valid;
+  if (foot) {
+    int ur, vr;
+    foot_pixel(fr, lane, ur, vr);
+    valid = lane < fr.n;
+    u = valid ? ur : 0;
+    v = valid ? vr : 0;
+    lx = u - bvw.x0;
+    ly = v - bvw.y0;
+  } else {
+    lx = tx * 8 + (lane & 7);
+    ly = ty * 8 + (lane >> 3);
+    valid = lx < bvw.w && ly < bvw.h;
+    u = bvw.x0 + min(lx, bvw.w - 1);
+    v = bvw.y0 + min(ly, bvw.h - 1);
+  }
+  // a footprint cell's pixel lies in the brick's rectangle whenever its ray
+  // has samples here; the image arena (or output) was cleared before the
+  // march, so only pixels with samples are written
+  const bool inrect = lx >= 0 && lx < bvw.w && ly >= 0 && ly < bvw.h;
 
   // ---- per-lane ray setup (double precision, shared with every march)
   double o[3], dl[3];
@@ -147,6 +272,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   float px = 0.f, py = 0.f, pz = 0.f;
   float4* const dst =
       a.carry ? a.img + (int64_t)v * a.cam.W + u : a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
+  const bool wr_ok = a.carry || !foot || inrect;  // dst is this pixel's place
   float4 carried = make_float4(0.f, 0.f, 0.f, 1.f);
   if (a.carry && valid) carried = *dst;
   const bool live = !a.carry || 1.f - carried.w < a.tau;
@@ -267,9 +393,9 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   }
   const int pix = ly * bvw.w + lx;  // SAVE: pixel of the whole-volume image
   if (!force_gather && (up ? Lbeg > Lend : Lbeg < Lend)) {
-    if (valid && !a.carry) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid && !a.carry && !foot) *dst = make_float4(0.f, 0.f, 0.f, 0.f);
     if (SAVE && valid) sa.nused[pix] = 0;
-    return;
+    continue;
   }
   const int nlay = up ? Lend - Lbeg + 1 : Lbeg - Lend + 1;  // cell layers
   // SAVE: state of the ray at the start of group g (cell layers gK .. gK + K - 1)
@@ -286,7 +412,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   const double rfd = PERSP ? 0.0 : d[0] / db, rgd = PERSP ? 0.0 : dg / db;
   const float rf = (float)rfd, rg = (float)rgd;
   float Af = 0.f, Ag = 0.f;
-  if constexpr (!PERSP) {
+  if (!PERSP && !foot) {
     const int cx = bvw.x0 + tx * 8, cy = bvw.y0 + ty * 8;
     const int ex = min(cx + 7, bvw.x0 + bvw.w - 1), ey = min(cy + 7, bvw.y0 + bvw.h - 1);
     const int cc = lane & 3;
@@ -296,8 +422,14 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     Af = (float)(oc[0] - (double)br.lo[0] - ob * rfd);
     Ag = (float)((by ? oc[2] : oc[1]) - (double)(by ? br.lo[2] : br.lo[1]) - ob * rgd);
   }
-  const float Af_lo = unif(wmin4(Af)), Af_hi = unif(wmax4(Af));
-  const float Ag_lo = unif(wmin4(Ag)), Ag_hi = unif(wmax4(Ag));
+  float Af_lo = unif(wmin4(Af)), Af_hi = unif(wmax4(Af));
+  float Ag_lo = unif(wmin4(Ag)), Ag_hi = unif(wmax4(Ag));
+  if (foot) {  // the cell's rectangle on the plane b = 0
+    Af_lo = (float)((double)ci * a.foot_Tf);
+    Af_hi = (float)((double)(ci + 1) * a.foot_Tf);
+    Ag_lo = (float)((double)cj * a.foot_Tg);
+    Ag_hi = (float)((double)(cj + 1) * a.foot_Tg);
+  }
   const float arf = fabsf(rf), arg = fabsf(rg);
   // PERSP: the four corner lines as uniform values
   float cAf[4], crf[4], cAg[4], crg[4];
@@ -326,6 +458,9 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
       crange(cAg, crg, Vb - 1.f, Vb + 1.f, l1, h1);
       NG = uni((int)floorf(fmaxf(h0 - l0, h1 - l1) + 0.2f) + 3);
     }
+  } else if (foot) {
+    NF = a.foot_nf;
+    NG = a.foot_ng;
   } else {
     NF = uni((int)floorf(Af_hi - Af_lo + 2.f * arf + 0.2f) + 3);
     NG = uni((int)floorf(Ag_hi - Ag_lo + 2.f * arg + 0.2f) + 3);
@@ -372,11 +507,11 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     }
     // carried state: only rays with samples here write (another brick of the
     // wave whose rectangle holds the pixel may update it)
-    if (valid && cnt > 0)
+    if (valid && cnt > 0 && wr_ok)
       *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, a.carry ? T : 1.f - T);
-    else if (valid && !a.carry)
+    else if (valid && !a.carry && !foot)
       *dst = make_float4(0.f, 0.f, 0.f, 0.f);
-    return;
+    continue;
   }
 
   // window of voxel layer V (brick-local): rows [g0, g0 + NG), columns [f0, f0 + pitch)
@@ -593,11 +728,96 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
       ++k;
     }
   }
-  wait_loads();  // no load may still target LDS when the wavefront ends
+  wait_loads();  // no load may still target LDS when the wavefront ends (or the next batch starts)
   if (SAVE && valid) sa.nused[pix] = j;
-  if (valid && (cnt > 0 || !a.carry))
+  if (valid && wr_ok && (cnt > 0 || (!a.carry && !foot)))
     *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, a.carry ? T : 1.f - T);
+  } while (false);
+
 }
+
+// Pixels past the 64th of footprint cells (listed by the march): one ray per
+// lane, its corners read from global memory; the same samples, arithmetic and
+// order as every march.  Wavefronts take listed cells in turn until the list
+// is done.
+__device__ __forceinline__ int find_bv(const MarchArgs& a, int tile) {
+  int lo = 0, hi = a.nbv - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.bv[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <bool MIP, bool MASK>
+__global__ __launch_bounds__(256) void k_march_ring_ovf(MarchArgs a) {
+  extern __shared__ float4 smem[];
+  float4* s_tf = smem;
+  for (int i = threadIdx.x; i < a.M; i += blockDim.x) s_tf[i] = a.tf[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int nw = (int)(gridDim.x * (blockDim.x >> 6));
+  const int n_listed = (int)*a.ovf_count;
+  for (int e = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); e < n_listed; e += nw) {
+    const int tile = a.ovf_tiles[e];
+    const DevBrickView bvw = a.bv[find_bv(a, tile)];
+    const DevBrick br = a.bricks[bvw.brick];
+    int ci, cj;
+    foot_cell(bvw, tile - bvw.tile_begin, ci, cj);
+    const FootRuns fr = foot_runs(a, bvw, ci, cj, lane);
+    gfloat* gb = (gfloat*)br.base;
+    const int ys = br.sy, zs = br.sz;
+    for (int k0 = 64; k0 < fr.n; k0 += 64) {
+      int uu, vv;
+      foot_pixel(fr, k0 + lane, uu, vv);
+      if (k0 + lane >= fr.n) continue;
+      const int lx = uu - bvw.x0, ly = vv - bvw.y0;
+      const bool inr = lx >= 0 && lx < bvw.w && ly >= 0 && ly < bvw.h;
+      float4* const dst =
+          a.carry ? a.img + (int64_t)vv * a.cam.W + uu : a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
+      float4 c0 = make_float4(0.f, 0.f, 0.f, 1.f);
+      if (a.carry) c0 = *dst;
+      if (a.carry && !(1.f - c0.w < a.tau)) continue;
+      double o[3];
+      pixel_origin(a.cam, uu, vv, o);
+      const double* d = a.cam.e3;
+      double tin;
+      int64_t n, k0b, k1b;
+      if (!ray_lattice(o, d, a.hi, a.step, tin, n)) continue;
+      brick_krange(o, d, tin, a.step, n, br.lo, br.hi, br.closed, k0b, k1b);
+      if (k1b <= k0b) continue;
+      const double t0 = tin + ((double)k0b + 0.5) * a.step;
+      const float px = (float)(o[0] + t0 * d[0] - (double)br.lo[0]);
+      const float py = (float)(o[1] + t0 * d[1] - (double)br.lo[1]);
+      const float pz = (float)(o[2] + t0 * d[2] - (double)br.lo[2]);
+      const float sx = (float)(a.step * d[0]), sy = (float)(a.step * d[1]), sz = (float)(a.step * d[2]);
+      const int cnt = (int)(k1b - k0b);
+      float Cr = c0.x, Cg = c0.y, Cb = c0.z, T = c0.w, mx = 0.f;
+      for (int j = 0; j < cnt;) {
+        const Cell c = cell_of(sample_pos(j, px, py, pz, sx, sy, sz), br);
+        gfloat* p = gb + (c.iz * zs + c.iy * ys + c.ix);
+        const float val = trilerp(p[0], p[1], p[ys], p[ys + 1], p[zs], p[zs + 1], p[zs + ys], p[zs + ys + 1], c);
+        ++j;
+        if (MIP) {
+          float sv = norm_value(val, a.vmin, a.inv_range);
+          if constexpr (MASK) sv *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], c);
+          mx = fmaxf(mx, sv);
+          if (mx >= 1.f) break;
+        } else {
+          Classified k = classify(val, a.vmin, a.inv_range, a.M, s_tf);
+          if constexpr (MASK) k.a *= channel_weight(a.mask, a.mask_axis, br.lo[a.mask_axis], c);
+          accumulate(k, Cr, Cg, Cb, T);
+          if (1.f - T >= a.tau) break;
+        }
+      }
+      if (a.carry || inr)
+        *dst = MIP ? make_float4(mx, mx, mx, mx) : make_float4(Cr, Cg, Cb, a.carry ? T : 1.f - T);
+    }
+  }
+}
+
+__global__ void k_ovf_reset(unsigned int* count) { *count = 0u; }
 
 }  // namespace
 
@@ -606,8 +826,28 @@ size_t ring_lds_bytes(const MarchArgs& a, int wpb) {
   return sizeof(float4) * (size_t)a.M + sizeof(float) * (size_t)wpb * ns * (size_t)a.ring_slot;
 }
 
+static hipError_t launch_march_ring_main(const MarchArgs& a, int wpb, hipStream_t s);
+
 hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
+  if (!a.foot) return launch_march_ring_main(a, wpb, s);
+  // footprint cells: clear the overflow list, march, then the listed cells' pixels past the 64th
+  if (a.cam.persp || !a.ovf_count || !a.ovf_tiles) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ovf_reset, dim3(1), dim3(1), 0, s, a.ovf_count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_march_ring_main(a, wpb, s);
+  if (e != hipSuccess) return e;
+  const dim3 g(256), b(256);
+  const size_t lds = sizeof(float4) * (size_t)a.M;
+  if (a.mip && a.mask) hipLaunchKernelGGL((k_march_ring_ovf<true, true>), g, b, lds, s, a);
+  else if (a.mip) hipLaunchKernelGGL((k_march_ring_ovf<true, false>), g, b, lds, s, a);
+  else if (a.mask) hipLaunchKernelGGL((k_march_ring_ovf<false, true>), g, b, lds, s, a);
+  else hipLaunchKernelGGL((k_march_ring_ovf<false, false>), g, b, lds, s, a);
+  return hipGetLastError();
+}
+
+static hipError_t launch_march_ring_main(const MarchArgs& a, int wpb, hipStream_t s) {
   if (a.tile_w != 8 || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || (wpb != 1 && wpb != 2 && wpb != 4))
     return hipErrorInvalidValue;
   const int groups = (a.ntiles + wpb - 1) / wpb;

@@ -415,6 +415,99 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
   return found;
 }
 
+bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
+                 int32_t nslots_rule, FootShape& out, int32_t pad) {
+  if (cam.persp) return false;
+  const double p = cam.S / (double)cam.W;
+  const double* e1 = cam.e1;
+  const double* e2 = cam.e2;
+  const double* d = cam.e3;
+  double best = INFINITY;
+  bool found = false;
+  for (int b = 1; b <= 2; b++) {
+    const int g = 3 - b;
+    if (std::fabs(d[b]) < 0.05) continue;  // windows grow as 1 / |d_b|
+    const double rf = d[0] / d[b], rg = d[g] / d[b];
+    // cell coordinates (f, g on the plane b = 0) per pixel step: the ray
+    // origin moves by p e1 per column and p e2 per row
+    const double au = p * (e1[0] - e1[b] * rf), av = p * (e2[0] - e2[b] * rf);
+    const double bu = p * (e1[g] - e1[b] * rg), bv = p * (e2[g] - e2[b] * rg);
+    const double det = au * bv - av * bu;  // plane area per pixel (signed)
+    if (!(std::fabs(det) > 1e-9)) continue;
+    // rows along f of the window: the cell, the slant over two layers and the
+    // margin, about a whole number of 32-float lines
+    for (int k = 1; k <= 4; k++) {
+      const double Tf = std::max(4.0, 32.0 * k - 2.0 * std::fabs(rf) - 3.5);
+      const double Tg = std::max(1.0, rays * std::fabs(det) / Tf);
+      const int32_t nf = (int32_t)std::floor(Tf + 2.0 * std::fabs(rf) + 0.25) + 3 + pad;
+      const int32_t ng = (int32_t)std::floor(Tg + 2.0 * std::fabs(rg) + 0.25) + 3;
+      const int32_t pitch = (nf + 3) & ~3;
+      const int64_t slot = (int64_t)pitch * ng;
+      if (slot > cap || pitch > 256) continue;
+      // image rows a cell spans: v extent of the cell's two edge vectors
+      const double rows = std::fabs(bu * Tf / det) + std::fabs(au * Tg / det) + 3.0;
+      if (rows > 62.0) continue;
+      int32_t waves3 = 0, waves2 = 0;
+      const int w3 = ring_waves_per_block((int32_t)slot, M, max_waves, &waves3, 3);
+      const int w2 = ring_waves_per_block((int32_t)slot, M, max_waves, &waves2, 2);
+      const bool two = nslots_rule == 2 || (nslots_rule == 0 && waves2 > waves3);
+      const int32_t waves = two ? waves2 : waves3;
+      if (waves < 2) continue;
+      // 128-byte lines per window row (a row starts anywhere in a line), per
+      // ray, per unit of ray length (|d_b| layers)
+      const double lines = (double)ng * ((double)pitch + 31.0) / 32.0;
+      const double cost = lines / rays * std::fabs(d[b]) * std::max(1.0, (double)want_waves / (double)waves);
+      if (cost < best) {
+        best = cost;
+        found = true;
+        out.axis = b;
+        out.Tf = Tf;
+        out.Tg = Tg;
+        out.nf = nf;
+        out.ng = ng;
+        out.slot = (int32_t)slot;
+        out.wpb = two ? w2 : w3;
+        out.nslots = two ? 2 : 3;
+        out.waves = waves;
+        out.rf = rf;
+        out.rg = rg;
+        out.fa_u = au / Tf;
+        out.fa_v = av / Tf;
+        out.fb_u = bu / Tg;
+        out.fb_v = bv / Tg;
+        out.rays = rays;
+      }
+    }
+  }
+  return found;
+}
+
+void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t& cf0, int32_t& cg0, int32_t& ncf,
+                int32_t& ncg, double& fa0, double& fb0) {
+  const int b = fs.axis, g = 3 - b;
+  // a point q (brick-local) lies on the ray that crosses the plane b = 0 at
+  // f = q_f - q_b rf, g = q_g - q_b rg
+  double flo = INFINITY, fhi = -INFINITY, glo = INFINITY, ghi = -INFINITY;
+  for (int c = 0; c < 8; c++) {
+    double q[3];
+    for (int i = 0; i < 3; i++) q[i] = (c >> i) & 1 ? (double)(box.hi[i] - box.lo[i]) : 0.0;
+    const double f = q[0] - q[b] * fs.rf, gg = q[g] - q[b] * fs.rg;
+    flo = std::min(flo, f);
+    fhi = std::max(fhi, f);
+    glo = std::min(glo, gg);
+    ghi = std::max(ghi, gg);
+  }
+  cf0 = (int32_t)std::floor(flo / fs.Tf - 1e-6);
+  cg0 = (int32_t)std::floor(glo / fs.Tg - 1e-6);
+  ncf = (int32_t)std::floor(fhi / fs.Tf + 1e-6) - cf0 + 1;
+  ncg = (int32_t)std::floor(ghi / fs.Tg + 1e-6) - cg0 + 1;
+  double o[3];
+  pixel_origin(cam, 0, 0, o);
+  const double ob = o[b] - (double)box.lo[b];
+  fa0 = ((o[0] - (double)box.lo[0]) - ob * fs.rf) / fs.Tf;
+  fb0 = ((o[g] - (double)box.lo[g]) - ob * fs.rg) / fs.Tg;
+}
+
 // Window floats of the perspective ring march for the 8 x 8 tile with corner
 // pixels (cx, cy) .. (ex, ey) over box r, on the better of axes 2 and 3 (the
 // kernel's choice, bounded over the box's layers); infinity when neither suits.

@@ -110,6 +110,36 @@ struct TileRegion {
 bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
                        int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb);
 
+// Ring march with footprint cells (parallel rays): the work item of a
+// wavefront is the set of pixels whose rays cross a brick's plane b = 0 in one
+// Tf x Tg cell of (f, g) (f = axis 1, g = the other in-plane axis), so its
+// window per voxel layer is the cell moved along the rays plus the rays'
+// slant over two layers and the trilinear margin: rows along the storage axis
+// of nf floats, ng rows, whatever the view's roll (8 x 8 pixel tiles project
+// to rotated parallelograms whose bounding box is up to twice their area).
+struct FootShape {
+  int32_t axis = 0;           // slab axis b (1 = axis 2, 2 = axis 3)
+  double Tf = 0.0, Tg = 0.0;  // cell size on the plane, voxels
+  int32_t nf = 0, ng = 0;     // window extents (before rows are rounded to 16 bytes)
+  int32_t slot = 0;           // floats per window slot (rows rounded up)
+  int32_t wpb = 4, nslots = 3, waves = 0;
+  double rf = 0.0, rg = 0.0;  // ray slope along f and g per unit of b
+  double fa_u = 0.0, fa_v = 0.0, fb_u = 0.0, fb_v = 0.0;  // cell coordinates per pixel step
+  double rays = 0.0;          // mean pixels per cell
+};
+// Picks b and (Tf, Tg) for one view: cells of about `rays` pixels whose rows
+// of window span about whole multiples of 32 floats, at most 64 image rows and
+// `cap` floats per slot; the choice with the fewest 128-byte lines per ray and
+// unit of ray length, weighted by how far occupancy falls below want_waves.
+// nslots_rule: 3, 2, or 0 = two slots wherever they fit more wavefronts than
+// three (the plain march).  False when no axis suits.
+bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
+                 int32_t nslots_rule, FootShape& out, int32_t pad = 0);
+// Cells of one brick: the range of cells that rays crossing its ownership box
+// fall in, and the cell coordinates of pixel (0, 0)'s ray on its plane b = 0.
+void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t& cf0, int32_t& cg0, int32_t& ncf,
+                int32_t& ncg, double& fa0, double& fb0);
+
 // Sum over pixels of the whole-volume lattice count (no ERT, no skipping).
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step);
 

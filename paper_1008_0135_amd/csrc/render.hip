@@ -129,6 +129,11 @@ __global__ __launch_bounds__(256) void k_carry_init(float4* img, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) img[i] = make_float4(0.f, 0.f, 0.f, 1.f);
 }
+// Cleared pixels (brick images of footprint-cell marches).
+__global__ __launch_bounds__(256) void k_zero(float4* img, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) img[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
 __global__ __launch_bounds__(256) void k_carry_final(float4* img, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) {
@@ -171,6 +176,13 @@ hipError_t launch_carry(float4* img, int64_t n, bool final, hipStream_t s) {
   const int64_t grid = (n + 255) / 256;
   if (final) hipLaunchKernelGGL(k_carry_final, dim3((unsigned)grid), dim3(256), 0, s, img, n);
   else hipLaunchKernelGGL(k_carry_init, dim3((unsigned)grid), dim3(256), 0, s, img, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(float4* img, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)grid), dim3(256), 0, s, img, n);
   return hipGetLastError();
 }
 

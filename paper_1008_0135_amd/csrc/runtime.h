@@ -64,6 +64,10 @@ struct vr_ctx {
   size_t small_bytes = 0;
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  // footprint-cell marches: per side stream, a count and the work items of
+  // cells with more than 64 pixels
+  void* d_ovf = nullptr;
+  size_t ovf_bytes = 0;
   // per-call table uploads: pinned staging + device copy, reused round-robin
   static constexpr int kRing = 4;
   struct Slot {
@@ -102,6 +106,10 @@ struct vr_ctx {
   // blocks of tile_bw x tile_bh tiles (2)
   int32_t tile_order = 2, tile_bw = 2, tile_bh = 4;
   int32_t ring_nslots = 0;    // forward ring march (plain orthographic): LDS slots per wavefront, 3 or 2; 0 = by occupancy
+  int32_t foot = 1;           // forward ring march, parallel rays: footprint cells (1) or 8 x 8 pixel tiles (0)
+  double foot_rays = 60.0;    // footprint cells: mean pixels per cell (each holds at most 64 in one pass)
+  int32_t foot_pad = 0;       // footprint cells: extra floats per window row (LDS bank spread)
+  bool debug_plan = false;    // print each view's march shape to stderr
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
   struct TuneEntry {
     std::string key;

@@ -168,10 +168,14 @@ struct DevBrick {
 struct DevBrickView {
   int32_t brick;       // index into the DevBrick table
   int32_t x0, y0, w, h;
-  int32_t tiles_x;     // tiles along x of the rectangle
+  int32_t tiles_x;     // tiles along x of the rectangle (footprint cells: cells along f)
   int32_t tile_begin;  // first work-item (tile) index of this brick
-  int32_t pad;
+  int32_t cf0;         // footprint cells: index of the first cell along f
   int64_t img_off;     // offset (in pixels) of the brick image in the image arena
+  int32_t cg0;         // footprint cells: index of the first cell along g
+  int32_t pad;
+  double fa0, fb0;     // footprint cells: cell coordinates (f / Tf, g / Tg) of pixel (0, 0)'s ray on the
+                       // brick-local plane b = 0
 };
 
 // One layer of the over-composite, front to back.
@@ -212,7 +216,28 @@ struct MarchArgs {
   int32_t tile_order;    // ring march: tiles of a brick numbered along rows (0), down columns (1),
                          // or in blocks of tile_bw x tile_bh tiles (2)
   int32_t tile_bw, tile_bh;
+  // ring march, parallel rays: work items are footprint cells instead of 8 x 8
+  // pixel tiles (foot = 1).  A cell is the set of pixels whose rays cross the
+  // brick-local plane b = 0 inside [i Tf, (i + 1) Tf) x [j Tg, (j + 1) Tg)
+  // (f = axis 1, g = the other in-plane axis), taken through foot_cell_coord;
+  // its windows are the rectangle moved along the rays plus the trilinear
+  // margin, foot_nf x foot_ng floats
+  int32_t foot;
+  int32_t foot_nf, foot_ng;
+  int32_t foot_pad;
+  double foot_Tf, foot_Tg;
+  double fa_u, fa_v, fb_u, fb_v;  // cell coordinates per pixel step along u and v
+  unsigned int* ovf_count;        // cells of more than 64 pixels: count and work-item indices
+  int32_t* ovf_tiles;             // (room for every work item of the launch)
 };
+
+// Cell coordinate (f / Tf or g / Tg) of pixel (u, v)'s ray on a brick's plane
+// b = 0: an affine function of (u, v) evaluated with two fused multiply-adds,
+// which makes it exactly monotone along u within an image row (so the pixels
+// of a row that fall in one cell form one run).
+__host__ __device__ inline double foot_cell_coord(double c0, double su, double sv, int u, int v) {
+  return fma((double)u, su, fma((double)v, sv, c0));
+}
 
 struct CompArgs {
   const CompLayer* layers;
@@ -279,6 +304,8 @@ struct BatchArgs {
 hipError_t launch_march(const MarchArgs& a, hipStream_t s);
 // (C, T) = (0, 1) over a frame of n pixels (final = false), or (C, T) -> (C, 1 - T) (final = true)
 hipError_t launch_carry(float4* img, int64_t n, bool final, hipStream_t s);
+// (0, 0, 0, 0) over n pixels (a fill kernel, not a memset)
+hipError_t launch_zero(float4* img, int64_t n, hipStream_t s);
 // Ring march (march_ring.hip): 8 x 8 tiles, a.ring_slot floats per window slot,
 // `wpb` wavefronts per workgroup (1, 2 or 4).
 hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s);

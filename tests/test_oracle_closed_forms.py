@@ -255,3 +255,28 @@ def test_box_minmax_matches_numpy(orc):
     mn, mx = orc.box_minmax(v, (2, 3, 1), (7, 8, 5))
     sub = v[1:6, 3:9, 2:8]
     assert mn == float(sub.min()) and mx == float(sub.max())
+
+
+@pytest.mark.parametrize("tau", [0.5, 0.99, 2.0])
+def test_constant_cube_evaluated_samples(orc, tau):
+    """Evaluated samples per ray: n_eff = min(n, ceil(log(1-tau)/log(1-a))) on axis rays
+    (all n without early termination); with two sub-volumes along the ray each stops on
+    its own, so the count is the sum of the two chains' closed forms."""
+    n = 40
+    a = 0.0625
+    vol = np.full((n, n, n), 0.5, np.float32)
+    k = 2 * (n - 1)
+    ys, xs = np.meshgrid(np.arange(1, 4), np.arange(1, 4), indexing="ij")
+    rv = np.zeros(ys.size, np.int32)
+    res = orc.render_rays(vol, _const_tf(a), [np.eye(3)], 4, 4, rv, xs.ravel(), ys.ravel(), 0.0, 1.0, tau=tau,
+                          extent=float(n - 1))
+    stop = k if tau >= 1 else min(k, math.ceil(math.log(1 - tau) / math.log(1 - a)))
+    assert (res["nsamples"] == k).all()
+    assert (res["neval"] == stop).all()
+    # two sub-volumes split at z = 20: 40 samples in the front one, 38 behind
+    boxes = [((0, 0, 0), (n - 1, n - 1, 20), (1, 1, 0)), ((0, 0, 20), (n - 1, n - 1, n - 1), (1, 1, 1))]
+    res = orc.render_rays(vol, _const_tf(a), [np.eye(3)], 4, 4, rv, xs.ravel(), ys.ravel(), 0.0, 1.0, tau=tau,
+                          extent=float(n - 1), bricks=boxes)
+    per = [40, k - 40]
+    want = sum(c if tau >= 1 else min(c, math.ceil(math.log(1 - tau) / math.log(1 - a))) for c in per)
+    assert (res["neval"] == want).all()
