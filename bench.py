@@ -36,6 +36,12 @@ import synth  # noqa: E402
 
 METRIC = "Gsamples/s + ms per 1024² frame (fwd, batched, fwd+bwd), % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
+# non-packed FP32 vector issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, lane-ops/s
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# algorithmic VALU work of one sample (trilinear 7 lerps = 14, normalisation 3,
+# table lerp of four channels 8, compositing about 9, position and index
+# arithmetic about 16): an estimate of the lane operations a sample needs
+LANE_OPS_PER_SAMPLE = 50
 
 
 def log(msg):
@@ -61,6 +67,120 @@ def _events_ms(fn, reps, stream):
     b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def stream_peak(stream, gib=4.0):
+    """Measured stream peak: a device-to-device copy of `gib` GiB (reads + writes
+    counted), timed with HIP events on the launch stream."""
+    import torch
+    n = int(gib * 2**30) // 4
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    ms = _events_ms(lambda: y.copy_(x), 5, stream)
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def mc_transparent(mm, tf, vmin, vmax):
+    """Per macrocell: every table entry its range can reach (one entry of margin
+    each side) has opacity 0, as for bricks."""
+    M = tf.shape[0]
+    scale = (M - 1) / (vmax - vmin) if vmax > vmin else 0.0
+    u0 = np.clip((mm[..., 0].astype(np.float64) - vmin) * scale, 0, M - 1)
+    u1 = np.clip((mm[..., 1].astype(np.float64) - vmin) * scale, 0, M - 1)
+    i0 = np.maximum(0, np.floor(u0).astype(np.int64) - 1)
+    i1 = np.minimum(M - 1, np.ceil(u1).astype(np.int64) + 1)
+    nz = np.concatenate([[0], np.cumsum(tf[:, 3] != 0)])  # entries with opacity != 0 before index i
+    return (nz[i1 + 1] - nz[i0]) == 0
+
+
+def bench_tf_suppress(ctx, h, dims, views_R, W, H, vmin, vmax, stream):
+    """The same cube and views with the noise-suppressing table (opacity 0 below
+    6 sigma): whole bricks and macrocell steps whose range is transparent are
+    skipped.  Algorithmic bytes: the voxels of the macrocells that may be
+    opaque (each read once) + the brick-image writes."""
+    import torch
+    tf = synth.tf_noise_suppress(vmin, vmax, thresh=6.0)
+    vr.vr_tf_set(ctx, tf)
+    views = [vr.make_view(R, W, H) for R in views_R]
+    params = vr.make_params(step=0.5, tau=0.99, ess=1)
+    out = torch.empty((len(views), H, W, 4), device="cuda")
+    ms = _events_ms(lambda: vr.vr_render(ctx, h, views, params, out, stream), 3, stream)
+    vr.vr_set_profiling(ctx, True)
+    vr.vr_render(ctx, h, views, params, out, stream)
+    t, c = vr.vr_stage_times(ctx)
+    vr.vr_set_profiling(ctx, False)
+    march = t[vr.VR_STAGE_MARCH] / max(1, c[vr.VR_STAGE_MARCH])
+    edge, cnt, mm = vr.vr_volume_macrocell_info(h)
+    clear = mc_transparent(mm, tf, vmin, vmax)
+    n = np.array(dims, np.int64)
+    # voxels per macrocell (the last along each axis may be shorter)
+    ext = [np.minimum(edge, (n[i] - 1) - edge * np.arange(cnt[i])) for i in range(3)]
+    vox = ext[2][:, None, None] * ext[1][None, :, None] * ext[0][None, None, :]
+    alg = float(4 * vox[~clear].sum())
+    log(f"tf_suppress: {ms / len(views):.3f} ms/frame, march {march:.3f} ms/launch, "
+        f"{clear.mean() * 100:.2f} % of macrocells transparent")
+    vr.vr_tf_set(ctx, synth.tf_ramp(256))
+    return {"workload": "same cube and views, noise-suppressing table (opacity 0 below 6 sigma, ramp to 0.2), "
+                        "16^3 macrocells, bricks and macrocell steps of zero opacity skipped",
+            "ms_per_frame": round(ms / len(views), 4), "march_ms_per_launch": round(march, 4),
+            "macrocells_skipped_frac": round(float(clear.mean()), 5),
+            "roofline": {"bound": "hbm", "achieved": round(alg / (march * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(alg / (march * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "alg_bytes_per_launch": int(alg),
+                         "alg_bytes": "voxels of the macrocells that may be opaque x 4 B (brick images excluded)"}}
+
+
+def bench_c2(ctx, stream):
+    """512 x 512 x 1024 (1 GiB) in 2 x 2 x 2 bricks, 16 views at 1024^2, ramp
+    table, per-brick termination: more than one sample per voxel, so the VALU
+    and HBM fractions are both reported."""
+    import torch
+    cfg = synth.CONFIGS["C2"]
+    n1, n2, n3 = cfg["dims"]
+    W, H = cfg["image"]
+    vol = synth.config_cube("C2")
+    h = vr.vr_volume_create(ctx, vol, (n1, n2, n3), on_device=False)
+    vr.vr_volume_brick(h, vr.grid_spec(cfg["bricks"]))
+    bricks = vr.vr_volume_brick_info(h)
+    vr.vr_tf_set(ctx, synth.tf_ramp(256))
+    views = [vr.make_view(R, W, H) for R in synth.random_views(cfg["nviews"], cfg["view_seed"])]
+    params = vr.make_params(step=0.5, tau=0.99, ess=1)
+    nominal = sum(vr.vr_count_samples((n1, n2, n3), v, 0.5) for v in views)
+    out = torch.empty((len(views), H, W, 4), device="cuda")
+    ms = _events_ms(lambda: vr.vr_render(ctx, h, views, params, out, stream), 3, stream)
+    vr.vr_set_profiling(ctx, True)
+    vr.vr_render(ctx, h, views, params, out, stream)
+    t, c = vr.vr_stage_times(ctx)
+    vr.vr_set_profiling(ctx, False)
+    march = t[vr.VR_STAGE_MARCH] / max(1, c[vr.VR_STAGE_MARCH])
+    spec = vr.grid_spec(cfg["bricks"])
+    alg = 0.0
+    for v in views:
+        rects, _ = vr.vr_plan_view((n1, n2, n3), spec, v)
+        for b, (x0, y0, w, hh) in enumerate(rects):
+            if w and hh:
+                d = bricks[b]
+                vx = 1
+                for i in range(3):
+                    vx *= (d.hi[i] - d.lo[i] + (1 if d.closed[i] else 0))
+                alg += 4 * vx + 16 * w * hh
+    alg /= len(views)
+    per_launch = nominal / len(views)
+    vr.vr_volume_destroy(h)
+    gsps = nominal / ms / 1e6
+    log(f"C2: {ms / len(views):.3f} ms/frame, {gsps:.1f} Gsamples/s, march {march:.3f} ms/launch")
+    return {"workload": f"{n1}x{n2}x{n3} f32 cube (1 GiB), 2x2x2 bricks, {W}x{H}, {len(views)} views, ramp table, "
+                        "tau 0.99 per brick", "ms_per_frame": round(ms / len(views), 4),
+            "gsamples_per_s": round(gsps, 3), "march_ms_per_launch": round(march, 4),
+            "roofline_hbm": {"achieved": round(alg / (march * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(alg / (march * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "alg_bytes_per_launch": int(alg)},
+            "roofline_valu": {"achieved": round(LANE_OPS_PER_SAMPLE * per_launch / (march * 1e-3) / 1e12, 2),
+                              "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "T lane-ops/s",
+                              "frac": round(LANE_OPS_PER_SAMPLE * per_launch / (march * 1e-3) / VALU_PEAK_LANE_OPS, 4),
+                              "lane_ops_per_sample": LANE_OPS_PER_SAMPLE}}
 
 
 def bench_batched(ctx, stream):
@@ -97,16 +217,55 @@ def bench_batched(ctx, stream):
 
     ms_b = _events_ms(run_batch, 10, stream)
     ms_p = _events_ms(run_plain, 3, stream)
+    tiles = vr.vr_batch_tiles(ctx, reqs)
     vr.vr_batch_destroy(cache)
+    vbytes = 0
     for h in vols:
         vr.vr_volume_destroy(h)
+    for d in descs:
+        vbytes += 4 * d["dims"][0] * d["dims"][1] * d["dims"][2] + 16 * d["image"][0] * d["image"][1]
+    # the same 64 requests as plain launches with the batch's shapes: the gather
+    # march with each request's tuned tile (32 x 2 tiles run as 16 x 4, the
+    # widest the plain gather takes)
+    import os as _os
+    _os.environ["VR_MARCH"] = "gather"
+    ctx_g = vr.vr_create(0)
+    del _os.environ["VR_MARCH"]
+    same = []
+    for i, d in enumerate(descs):
+        n1, n2, n3 = d["dims"]
+        a = synth.cube(n1, n2, n3, seed=d["seed"], n_sources=d["n_sources"])
+        hg = vr.vr_volume_create(ctx_g, a, (n1, n2, n3), on_device=False)
+        _, view, tf, mn, mx, out, _ = plain[i]
+        same.append((hg, view, tf, mn, mx, out, vr.make_params(step=0.5, tau=0.99, ess=0, tile=min(16, tiles[i]))))
+
+    def run_same():
+        for hg, view, tf, mn, mx, out, pp in same:
+            vr.vr_tf_set(ctx_g, tf, mn, mx, stream)
+            vr.vr_render(ctx_g, hg, [view], pp, out, stream)
+
+    ms_s = _events_ms(run_same, 3, stream)
+    for hg, *_ in same:
+        vr.vr_volume_destroy(hg)
+    vr.vr_destroy(ctx_g)
+    ops = LANE_OPS_PER_SAMPLE * nominal
     log(f"batched: {ms_b:.3f} ms per 64-request batch ({nominal / ms_b / 1e6:.1f} Gsamples/s), "
-        f"64 plain launches {ms_p:.3f} ms, grid {tune.waves_per_cu} waves/CU")
+        f"64 plain launches {ms_p:.3f} ms (same shapes: {ms_s:.3f} ms), grid {tune.waves_per_cu} waves/CU, "
+        f"tiles {dict((t, tiles.count(t)) for t in sorted(set(tiles)))}")
     return {"workload": "64 requests, volumes U[32,256]^3 (non-cubic), images U[64,512]^2, random views and "
-                        "8-point tables, one persistent hipGraph launch", "ms_per_batch": round(ms_b, 4),
+                        "8-point tables, one persistent hipGraph launch; tile shape per size class and grid "
+                        "from the autotuner", "ms_per_batch": round(ms_b, 4),
             "gsamples_per_s": round(nominal / ms_b / 1e6, 3), "ms_64_plain_launches": round(ms_p, 4),
-            "speedup_vs_plain": round(ms_p / ms_b, 3), "nominal_samples": int(nominal),
-            "waves_per_cu": tune.waves_per_cu}
+            "speedup_vs_plain": round(ms_p / ms_b, 3),
+            "ms_64_plain_launches_same_shapes": round(ms_s, 4),
+            "speedup_vs_plain_same_shapes": round(ms_s / ms_b, 3), "nominal_samples": int(nominal),
+            "waves_per_cu": tune.waves_per_cu,
+            "tiles": {f"{t}x{64 // t}": tiles.count(t) for t in sorted(set(tiles))},
+            "roofline": {"bound": "alu", "achieved": round(ops / (ms_b * 1e-3) / 1e12, 2),
+                         "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "T lane-ops/s",
+                         "frac": round(ops / (ms_b * 1e-3) / VALU_PEAK_LANE_OPS, 4),
+                         "lane_ops_per_sample": LANE_OPS_PER_SAMPLE,
+                         "hbm_frac": round(vbytes / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def bench_fwd_bwd(ctx, stream):
@@ -143,14 +302,30 @@ def bench_fwd_bwd(ctx, stream):
 
     ms_f = _events_ms(fwd, 5, stream)
     ms_fb = _events_ms(fwd_bwd, 3, stream)
+    # checkpoint interval the plan took per view (ckpt_K = 32 bounds it)
+    st = vr.vr_render(ctx, h, views, params, out, stream, save=True)
+    spg = [vr.vr_state_info(st, i)[2] for i in range(len(views))]
+    lay = [vr.vr_state_info(st, i)[1] for i in range(len(views))]
+    # kernel time of the backward alone (stage timer on the launch stream)
+    vr.vr_set_profiling(ctx, True)
+    vr.vr_render_backward(ctx, h, st, out - target, gtf, gvol, False, stream)
+    tt, _ = vr.vr_stage_times(ctx)
+    vr.vr_set_profiling(ctx, False)
+    vr.vr_state_destroy(st)
+    ms_b_kernels = tt[vr.VR_STAGE_BACKWARD]
     vr.vr_volume_destroy(h)
-    log(f"fwd+bwd: forward {ms_f:.3f} ms, forward+backward {ms_fb:.3f} ms for {len(views)} views of 512^2")
+    log(f"fwd+bwd: forward {ms_f:.3f} ms, forward+backward {ms_fb:.3f} ms for {len(views)} views of 512^2 "
+        f"(backward kernels {ms_b_kernels:.3f} ms; checkpoints every {min(spg):.1f}-{max(spg):.1f} samples)")
     return {"workload": "256x256x512 f32 cube, 8 views at 512x512, colour-ramp table, L2 loss against a "
-                        "perturbed-table target, checkpoints every 32 samples, gradients to table and voxels",
+                        "perturbed-table target, ckpt_K 32 (checkpoint groups of at most 4 cell layers on the "
+                        "ring layout), gradients to table and voxels",
             "ms_forward": round(ms_f, 4), "ms_forward_backward": round(ms_fb, 4),
+            "ms_backward_kernels": round(ms_b_kernels, 4),
             "gsamples_per_s_forward": round(nominal / ms_f / 1e6, 3),
             "gsamples_per_s_forward_backward": round(nominal / ms_fb / 1e6, 3),
-            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3), "nominal_samples": int(nominal)}
+            "backward_over_forward": round((ms_fb - ms_f) / ms_f, 3), "nominal_samples": int(nominal),
+            "samples_per_checkpoint": {"min": round(min(spg), 2), "max": round(max(spg), 2)},
+            "cell_layers_per_group": sorted(set(lay))}
 
 
 def bench_variants(ctx, h, dims, views_R, W, H, stream):
@@ -213,7 +388,11 @@ def counter_traffic(config):
         return None
     fetch = float(kv["fetch_kib_per_dispatch"]) * (1048576.0 / float(kv["copy_fetch_kib_per_gib"]))
     write = float(kv["write_kib_per_dispatch"]) * (1048576.0 / float(kv["copy_write_kib_per_gib"]))
-    return int((fetch + write) * 1024)
+    hit = None
+    if "tcc_hit_per_dispatch" in kv and "tcc_miss_per_dispatch" in kv:
+        h, m = float(kv["tcc_hit_per_dispatch"]), float(kv["tcc_miss_per_dispatch"])
+        hit = h / (h + m) if h + m > 0 else None
+    return int((fetch + write) * 1024), hit
 
 
 def main():
@@ -329,6 +508,7 @@ def main():
     vr.vr_set_profiling(ctx, True)
     march_ms = []
     comp_ms = []
+    setup_ms = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -336,6 +516,7 @@ def main():
         ms, cnt = vr.vr_stage_times(ctx)
         march_ms.append(ms[vr.VR_STAGE_MARCH] / max(1, cnt[vr.VR_STAGE_MARCH]))
         comp_ms.append(ms[vr.VR_STAGE_COMPOSITE] / max(1, cnt[vr.VR_STAGE_COMPOSITE]))
+        setup_ms.append(ms[vr.VR_STAGE_SETUP] / nviews)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     vr.vr_set_profiling(ctx, False)
@@ -344,6 +525,9 @@ def main():
     avg_march = float(np.mean(march_ms))
     alg_bytes = float(np.mean([b + i for b, i, _ in imgs_per_view]))
     achieved = alg_bytes / (avg_march * 1e-3) / 1e9
+    peak_meas = stream_peak(stream)
+    traffic = counter_traffic(args.config)
+    log(f"measured stream peak (device copy, reads + writes): {peak_meas:.0f} GB/s")
     log(f"{ms_step:.2f} ms/step, {ms_step / nviews:.3f} ms/frame, {gsps:.1f} Gsamples/s; "
         f"march {avg_march:.3f} ms/launch, composite {float(np.mean(comp_ms)):.3f} ms/launch")
 
@@ -372,6 +556,10 @@ def main():
         "nominal_samples_per_frame": int(nominal // nviews),
         "march_ms_per_launch": round(avg_march, 4),
         "composite_ms_per_launch": round(float(np.mean(comp_ms)), 4),
+        "setup_ms_per_frame": round(float(np.mean(setup_ms)), 4),
+        "frame_time_decomposition": "ms_per_frame = setup (per-view tables to the device) + march + composite "
+                                    "+ host gaps; the cube's upload, bricking and ranges are done once, "
+                                    "before timing",
         "bricks_rendered_per_frame": float(np.mean([k for _, _, k in imgs_per_view])),
         "march_ms_per_view": {"min": round(float(np.min(view_ms)), 4), "median": round(float(np.median(view_ms)), 4),
                               "mean": round(float(np.mean(view_ms)), 4), "max": round(float(np.max(view_ms)), 4),
@@ -382,16 +570,26 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": counter_traffic(args.config),
+            "traffic": traffic[0] if traffic else None,
+            "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (L2-miss traffic, scaled by a "
+                              "plain copy), read from profiles/k_march_ring_c3_counters.txt when the kernel and "
+                              "planning sources hash to the values recorded there, else null",
+            "l2_hit_rate": round(traffic[1], 4) if traffic and traffic[1] is not None else None,
             "kernel": "k_march_ring",
             "alg_bytes_per_launch": int(alg_bytes),
+            "measured_stream_peak": round(peak_meas, 1),
+            "frac_of_measured_peak": round(achieved / peak_meas, 4),
+            "valu_frac": round(LANE_OPS_PER_SAMPLE * (nominal / nviews) / (avg_march * 1e-3) / VALU_PEAK_LANE_OPS, 4),
         },
     }
 
     if not args.no_extras:
         result.update(bench_variants(ctx, h, (n1, n2, n3), views_R, W, H, stream))
+        result["tf_suppress"] = bench_tf_suppress(ctx, h, (n1, n2, n3), views_R, W, H, vmin, vmax, stream)
         result["batched"] = bench_batched(ctx, stream)
         result["fwd_bwd"] = bench_fwd_bwd(ctx, stream)
+        if args.config == "C3":
+            result["c2"] = bench_c2(ctx, stream)
 
     if not args.no_oracle:
         import oracle
@@ -404,6 +602,7 @@ def main():
         stride = 4
         done_rays = 0
         done_samples = 0
+        done_eval = 0
         spent = 0.0
         worst = 0.0
         nv_done = 0
@@ -419,6 +618,7 @@ def main():
             nv_done += 1
             done_rays += yy.size
             done_samples += int(ref["nsamples"].sum())
+            done_eval += int(ref["neval"].sum())
             g = got[vv, yy.ravel(), xx.ravel()].astype(np.float64)
             ok = (ref["flags"] & oracle.FLAG_GEOM) == 0
             e = oracle.match_error(g, ref)[ok]
@@ -434,6 +634,11 @@ def main():
                       f"{done_samples} nominal samples, FP64, {spent:.1f} s",
         }
         result["parity_max_err_on_sample"] = float(f"{max(worst, 0.0):.3g}")
+        frac_eval = done_eval / max(1, done_samples)
+        result["effective_samples_per_frame"] = int(frac_eval * (nominal // nviews))
+        result["effective_samples_how"] = (f"nominal x {frac_eval:.4f}, the fraction of lattice samples evaluated "
+                                           "(each brick's samples up to its own early termination) on the oracle's "
+                                           "ray sample")
         log(f"oracle: {done_samples / spent / 1e6:.1f} Msamples/s on {cores} threads; parity {worst:.3g}")
 
     vr.vr_volume_destroy(h)

@@ -115,7 +115,7 @@ typedef struct {
                         volume has them), whose transfer-function opacity is 0 over their range */
   int32_t ert_scope; /* VR_ERT_LOCAL or VR_ERT_GLOBAL */
   int32_t mode;      /* VR_MODE_DVR or VR_MODE_MIP */
-  int32_t ckpt_K;    /* adjoint: transmittance checkpoint interval in samples (>= 1; 32 typical) */
+  int32_t ckpt_K;    /* adjoint: longest transmittance checkpoint interval in samples (1..64; 32 typical) */
   int32_t tile;      /* pixel tile edge of one wavefront: 0 = autotuned/default (8) */
   int32_t reserved;
 } vr_params;
@@ -332,17 +332,36 @@ int vr_composite(vr_ctx *ctx, const vr_brick_image *imgs, int32_t n, const int32
  * save.  grad_out: [nviews][H][W][4] float32 device.  grad_tf: [m][4] float32
  * device.  grad_vol: [n3][n2][n1] float32 device or NULL.  accumulate = 0
  * overwrites the outputs, 1 adds to them.  The normalisation window is a
- * constant.  Each ray is walked back to front, recomputing each stretch of
- * about ckpt_K samples forward from its saved transmittance checkpoint: on the
- * ring-window layout (the default where its windows fit) a stretch is a group
- * of cell layers of the ray's 8 x 8 tile holding about ckpt_K of its samples,
- * otherwise a segment of exactly ckpt_K samples.
+ * constant.  Each ray is walked back to front, recomputing each stretch
+ * forward from its saved transmittance checkpoint.  ckpt_K bounds a stretch:
+ * on the ring-window layout (the default where its windows fit) a stretch is
+ * a group of L cell layers of the ray's 8 x 8 tile, L = round(ckpt_K step
+ * |d_b|) capped at 4 layers (the environment variable VR_BWD_LAYERS sets the
+ * cap, 1 to 16: longer groups need more LDS per wavefront), so a checkpoint
+ * falls every min(ckpt_K, about 4 / (step |d_b|)) samples (vr_state_info
+ * reports it per view); otherwise a stretch is a segment of exactly ckpt_K
+ * samples.  Synchronises with `stream` at the end (it checks the adjoint's
+ * per-group sample bound).
  * Errors: VR_EINVAL, VR_ESTATE (state from another volume, or the transfer
- * function changed since the forward), VR_EHIP.
+ * function changed since the forward), VR_EHIP (also a group beyond its
+ * sample bound).
  */
 int vr_render_backward(vr_ctx *ctx, const vr_volume *vol, const vr_state *st, const float *grad_out,
                        float *grad_tf, float *grad_vol, int accumulate, uintptr_t stream);
 int vr_state_destroy(vr_state *st);
+
+/*
+ * How the forward state of one view checkpoints the transmittance (the
+ * interval the adjoint recomputes from): ring = 1 when the view uses the
+ * ring-window layout, whose checkpoints sit at the start of each group of
+ * layers_per_group cell layers of a ray's 8 x 8 tile, i.e. every
+ * samples_per_group = layers_per_group / (step |d_b|) samples along the ray
+ * (d_b: the view direction's component along the slab axis); ring = 0: every
+ * ckpt_K samples (layers_per_group = 0).  Any output pointer may be NULL.  No
+ * GPU use.  Errors: VR_EINVAL.
+ */
+int vr_state_info(const vr_state *st, int32_t view, int32_t *ring, int32_t *layers_per_group,
+                  double *samples_per_group);
 
 /* ------------------------------------------------------------------ batched */
 /* One request of a batch: its own volume (unbricked), view, table, window and output. */

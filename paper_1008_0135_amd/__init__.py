@@ -112,6 +112,7 @@ _SIGS = {
     "vr_composite": (_I, [_P, _P, _I32, _P, _I32, _I32, _P, _U]),
     "vr_render_backward": (_I, [_P, _P, _P, _P, _P, _P, _I, _U]),
     "vr_state_destroy": (_I, [_P]),
+    "vr_state_info": (_I, [_P, _I32, _P, _P, _P]),
     "vr_render_batch": (_I, [_P, _P, _I32, _P, _P, _U]),
     "vr_batch_destroy": (_I, [_P]),
     "vr_autotune": (_I, [_P, _P, _P, _P, _P, _U]),
@@ -360,6 +361,14 @@ def vr_render_backward(ctx, vol, state, grad_out, grad_tf, grad_vol=None, accumu
 
 def vr_state_destroy(state):
     _check(lib().vr_state_destroy(state), "vr_state_destroy")
+
+
+def vr_state_info(state, view=0):
+    """(ring layout?, cell layers per checkpoint group, samples per checkpoint) of one view."""
+    ring, layers, samples = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().vr_state_info(state, int(view), C.byref(ring), C.byref(layers), C.byref(samples)),
+           "vr_state_info")
+    return bool(ring.value), layers.value, samples.value
 
 
 def vr_render_batch(ctx, reqs, params, cache=None, stream=None):

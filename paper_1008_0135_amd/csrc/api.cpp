@@ -364,7 +364,12 @@ int vr_create(int device, vr_ctx** out) {
   }
   if (const char* m = std::getenv("VR_FOOT")) ctx->foot = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_FOOT_PAD")) ctx->foot_pad = std::max(0, std::min(32, std::atoi(m)));
+  if (const char* m = std::getenv("VR_FOOT_KMAX")) ctx->foot_kmax = std::max(1, std::min(4, std::atoi(m)));
   if (const char* m = std::getenv("VR_DEBUG_PLAN")) ctx->debug_plan = std::atoi(m) != 0;
+  if (const char* m = std::getenv("VR_PERSP_FIT")) {
+    const double f = std::atof(m);
+    if (f >= 0.3 && f <= 1.0) ctx->persp_fit = f;
+  }
   if (const char* m = std::getenv("VR_FOOT_RAYS")) {
     const double r = std::atof(m);
     if (r >= 16.0 && r <= 64.0) ctx->foot_rays = r;
@@ -421,6 +426,9 @@ int vr_destroy(vr_ctx* ctx) {
   if (ctx->d_small) (void)hipFree(ctx->d_small);
   if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
   if (ctx->d_ovf) (void)hipFree(ctx->d_ovf);
+  if (ctx->spare.ckpt) (void)hipFree(ctx->spare.ckpt);
+  if (ctx->spare.ckpt_j) (void)hipFree(ctx->spare.ckpt_j);
+  if (ctx->spare.nused) (void)hipFree(ctx->spare.nused);
   for (auto& t : ctx->timed) {
     (void)hipEventDestroy(t.a);
     (void)hipEventDestroy(t.b);

@@ -153,7 +153,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     if (extras || cams[v].persp || !ctx->foot || !(mode == 0 || mode == 3) || tw != 8) continue;
     FootShape fs;
     if (!choose_foot(cams[v], kRingCap, base.M, kRingMaxWaves, kRingWantWaves, ctx->foot_rays,
-                     plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad))
+                     plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad, ctx->foot_kmax))
       continue;
     if (ctx->debug_plan)
       std::fprintf(stderr, "[vr] view %d: cells axis %d Tf %.1f Tg %.2f nf %d ng %d slot %d nslots %d wpb %d waves %d rf %.3f rg %.3f\n",
@@ -291,7 +291,8 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
           regs.push_back(r);
         }
         a.slab_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
-        ring = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, ring_wpb);
+        ring = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, ring_wpb,
+                                 ctx->persp_fit);
         a.ring_nslots = 3;
         // two slots wherever they fit more wavefronts (as for parallel rays)
         if (ring && a.mc == 0 && !a.mask && ctx->ring_nslots != 3) {

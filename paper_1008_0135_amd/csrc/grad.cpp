@@ -31,7 +31,9 @@ struct vr_state {
   std::vector<View> vs;
   float* d_ckpt = nullptr;     // checkpoints, all views
   int32_t* d_ckpt_j = nullptr; // ring views: sample cursors at group starts
-  int32_t* d_nused = nullptr;  // [view][pixel]
+  int32_t* d_nused = nullptr;  // [view][pixel], then the adjoint's bound flag
+  size_t ckpt_bytes = 0, ckpt_j_bytes = 0, nused_bytes = 0;  // allocated sizes
+  int32_t* d_flag = nullptr;   // set by the adjoint when a group held more samples than its bound
 };
 
 namespace vr {
@@ -156,13 +158,37 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
       ck_total += (int64_t)st->nseg * npix;
     }
   }
-  const size_t ck_bytes = sizeof(float) * (size_t)ck_total;
-  if (hipMalloc(&st->d_ckpt, ck_bytes) != hipSuccess ||
-      hipMalloc(&st->d_nused, sizeof(int32_t) * nviews * npix) != hipSuccess ||
-      (ckj_total > 0 && hipMalloc(&st->d_ckpt_j, sizeof(int32_t) * (size_t)ck_total) != hipSuccess)) {
-    (void)hipGetLastError();
-    vr_state_destroy(st);
-    return fail(VR_ENOMEM, "hipMalloc for %zu bytes of checkpoints failed", ck_bytes);
+  const size_t ck_bytes = sizeof(float) * (size_t)std::max<int64_t>(ck_total, 1);
+  const size_t ckj_bytes = ckj_total > 0 ? sizeof(int32_t) * (size_t)ck_total : 0;
+  const size_t nu_bytes = sizeof(int32_t) * ((size_t)nviews * npix + 64);
+  // the buffers of the last destroyed state when they are large enough
+  vr_ctx::StateBufs& sp = ctx->spare;
+  if (sp.ckpt && sp.ckpt_bytes >= ck_bytes && sp.nused_bytes >= nu_bytes && sp.ckpt_j_bytes >= ckj_bytes) {
+    st->d_ckpt = sp.ckpt;
+    st->d_ckpt_j = sp.ckpt_j;
+    st->d_nused = sp.nused;
+    st->ckpt_bytes = sp.ckpt_bytes;
+    st->ckpt_j_bytes = sp.ckpt_j_bytes;
+    st->nused_bytes = sp.nused_bytes;
+    sp = vr_ctx::StateBufs();
+  } else {
+    st->ckpt_bytes = ck_bytes;
+    st->ckpt_j_bytes = ckj_bytes;
+    st->nused_bytes = nu_bytes;
+    if (hipMalloc(&st->d_ckpt, ck_bytes) != hipSuccess || hipMalloc(&st->d_nused, nu_bytes) != hipSuccess ||
+        (ckj_bytes > 0 && hipMalloc(&st->d_ckpt_j, ckj_bytes) != hipSuccess)) {
+      (void)hipGetLastError();
+      vr_state_destroy(st);
+      return fail(VR_ENOMEM, "hipMalloc for %zu bytes of checkpoints failed", ck_bytes);
+    }
+  }
+  st->d_flag = st->d_nused + (size_t)nviews * npix;
+  {
+    const hipError_t e = launch_fill(reinterpret_cast<float*>(st->d_flag), 1, 0.f, s);
+    if (e != hipSuccess) {
+      vr_state_destroy(st);
+      return fail(VR_EHIP, "flag clear: %s", hipGetErrorString(e));
+    }
   }
   MarchArgs base;
   std::memset(&base, 0, sizeof base);
@@ -220,11 +246,40 @@ extern "C" {
 int vr_state_destroy(vr_state* st) {
   if (!st) return VR_OK;
   DeviceGuard g(st->ctx->device);
-  (void)hipDeviceSynchronize();
-  if (st->d_ckpt) (void)hipFree(st->d_ckpt);
-  if (st->d_ckpt_j) (void)hipFree(st->d_ckpt_j);
-  if (st->d_nused) (void)hipFree(st->d_nused);
+  vr_ctx::StateBufs& sp = st->ctx->spare;
+  if (!sp.ckpt && st->d_ckpt && st->d_nused) {
+    // kept for the context's next forward with state (calls on a context are
+    // ordered, so no work of this state can still be reading them then)
+    sp.ckpt = st->d_ckpt;
+    sp.ckpt_j = st->d_ckpt_j;
+    sp.nused = st->d_nused;
+    sp.ckpt_bytes = st->ckpt_bytes;
+    sp.ckpt_j_bytes = st->ckpt_j_bytes;
+    sp.nused_bytes = st->nused_bytes;
+  } else {
+    (void)hipDeviceSynchronize();
+    if (st->d_ckpt) (void)hipFree(st->d_ckpt);
+    if (st->d_ckpt_j) (void)hipFree(st->d_ckpt_j);
+    if (st->d_nused) (void)hipFree(st->d_nused);
+  }
   delete st;
+  return VR_OK;
+}
+
+int vr_state_info(const vr_state* st, int32_t view, int32_t* ring, int32_t* layers_per_group, double* samples_per_group) {
+  clear_error();
+  if (!st || view < 0 || view >= st->nviews) return fail(VR_EINVAL, "state NULL or view out of range");
+  const vr_state::View& rv = st->vs[view];
+  if (ring) *ring = rv.ring ? 1 : 0;
+  if (layers_per_group) *layers_per_group = rv.ring ? rv.L : 0;
+  if (samples_per_group) {
+    if (rv.ring) {
+      const double* e3 = st->views[view].R + 6;
+      *samples_per_group = (double)rv.L / (st->p.step * std::fabs(e3[rv.axis]));
+    } else {
+      *samples_per_group = (double)st->K;
+    }
+  }
   return VR_OK;
 }
 
@@ -286,6 +341,7 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
     ba.K = rv.ring ? rv.L : st->K;
     ba.npix = (int32_t)npix;
     ba.smax = rv.smax;
+    ba.flag = st->d_flag;
     VR_TRY(stage_begin(ctx, VR_STAGE_BACKWARD, s));
     int nblocks;
     if (rv.ring) {
@@ -300,7 +356,14 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
     VR_HIP(launch_tf_reduce(part, nblocks, M * 4, grad_tf, slices, s));
     VR_TRY(stage_end(ctx, s));
   }
-  return ctx_end(ctx, s);
+  VR_TRY(ctx_end(ctx, s));
+  // the ring adjoint's bound on the samples of one ray in one checkpoint group
+  // holds by construction; a group that exceeded it is reported, not clamped
+  int32_t flag = 0;
+  VR_HIP(hipMemcpyAsync(&flag, st->d_flag, sizeof flag, hipMemcpyDeviceToHost, s));
+  VR_HIP(hipStreamSynchronize(s));
+  if (flag) return fail(VR_EHIP, "adjoint: a ray held more samples in one checkpoint group than the planned bound");
+  return VR_OK;
 }
 
 }  // extern "C"

@@ -20,9 +20,9 @@
 //   4. adds the gradient windows to the gradient volume with one float atomic
 //      per non-zero window voxel, row after row (coalesced), instead of eight
 //      scattered atomics per sample.
-// Samples are evaluated at the forward's single-precision positions and cells
-// (sample.h), with the trilinear value, the table lookup, the recursion and
-// the gradient algebra in double precision.  A tile whose window would not
+// Samples are evaluated at double-precision positions (start + j step, one
+// rounding per axis; cell_d), with the trilinear value, the table lookup, the
+// recursion and the gradient algebra in double precision.  A tile whose window would not
 // fit reads its corners from global memory and adds its voxel gradients with
 // global atomics directly (same groups, same arithmetic).
 #include "ring_common.h"
@@ -298,6 +298,12 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
           je = g + 1 < ngrp ? ba.ckpt_j[(int64_t)(g + 1) * npix + pix] : cnt;
           je = min(je, used);
           T = (double)ba.ckpt[(int64_t)g * npix + pix];
+          // the plan bounds a ray's samples in one group by smax (L layers
+          // at one step each); a group beyond it is flagged, not clamped
+          if (je - js > smax) {
+            atomicOr(ba.flag, 1);
+            je = js + smax;
+          }
         }
         // cell of sample j and its eight corners, from the windows when both of
         // its voxel layers are in the group's slots (always, up to rounding at
@@ -336,7 +342,7 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
           int lofs, uofs;
           corners(j, c, vv, lofs, uofs);
           const Eval S = eval_d(vv, c, ba.vmin, ba.inv_range, M, s_tf);
-          if (j - js < smax) s_T[(j - js) * 64 + lane] = (float)T;  // smax bounds a group's samples
+          s_T[(j - js) * 64 + lane] = (float)T;
           T = fma(-T, S.a, T);
         }
         // backward walk
@@ -346,7 +352,7 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
           int lofs, uofs;
           corners(j, c, vv, lofs, uofs);
           const Eval S = eval_d(vv, c, ba.vmin, ba.inv_range, M, s_tf);
-          const double Tp = (double)s_T[min(j - js, smax - 1) * 64 + lane];
+          const double Tp = (double)s_T[(j - js) * 64 + lane];
           const double ta = Tp * S.a;
           const double gr = gx * ta, gg = gy * ta, gb = gz * ta;
           const double ga = Tp * (gx * (S.r - R0) + gy * (S.g - R1) + gz * (S.b - R2) + gw * (1.0 - Q));

@@ -416,7 +416,7 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
 }
 
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
-                 int32_t nslots_rule, FootShape& out, int32_t pad) {
+                 int32_t nslots_rule, FootShape& out, int32_t pad, int32_t kmax) {
   if (cam.persp) return false;
   const double p = cam.S / (double)cam.W;
   const double* e1 = cam.e1;
@@ -436,7 +436,7 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
     if (!(std::fabs(det) > 1e-9)) continue;
     // rows along f of the window: the cell, the slant over two layers and the
     // margin, about a whole number of 32-float lines
-    for (int k = 1; k <= 4; k++) {
+    for (int k = 1; k <= kmax; k++) {
       const double Tf = std::max(4.0, 32.0 * k - 2.0 * std::fabs(rf) - 3.5);
       const double Tg = std::max(1.0, rays * std::fabs(det) / Tf);
       const int32_t nf = (int32_t)std::floor(Tf + 2.0 * std::fabs(rf) + 0.25) + 3 + pad;
@@ -547,7 +547,7 @@ static double persp_tile_window(const Camera& cam, const TileRegion& r, int cx, 
 }
 
 bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
-                       int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb) {
+                       int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb, double fit) {
   std::vector<std::pair<double, double>> est;  // (window of the region's worst sampled tile, tiles)
   double total = 0.0;
   for (const TileRegion& r : regs) {
@@ -568,7 +568,7 @@ bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, i
   double acc = 0.0, need = INFINITY;
   for (const auto& e : est) {
     acc += e.second;
-    if (acc >= 0.95 * total) {
+    if (acc >= fit * total) {
       need = e.first;
       break;
     }

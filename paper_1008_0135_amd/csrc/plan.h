@@ -108,7 +108,7 @@ struct TileRegion {
   int32_t x0, y0, w, h;
 };
 bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
-                       int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb);
+                       int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb, double fit = 0.95);
 
 // Ring march with footprint cells (parallel rays): the work item of a
 // wavefront is the set of pixels whose rays cross a brick's plane b = 0 in one
@@ -134,7 +134,7 @@ struct FootShape {
 // nslots_rule: 3, 2, or 0 = two slots wherever they fit more wavefronts than
 // three (the plain march).  False when no axis suits.
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
-                 int32_t nslots_rule, FootShape& out, int32_t pad = 0);
+                 int32_t nslots_rule, FootShape& out, int32_t pad = 0, int32_t kmax = 4);
 // Cells of one brick: the range of cells that rays crossing its ownership box
 // fall in, and the cell coordinates of pixel (0, 0)'s ray on its plane b = 0.
 void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t& cf0, int32_t& cg0, int32_t& ncf,

@@ -64,6 +64,14 @@ struct vr_ctx {
   size_t small_bytes = 0;
   void* d_scratch = nullptr;
   size_t scratch_bytes = 0;
+  // device buffers of the last destroyed forward state (checkpoints, sample
+  // cursors, samples used + the adjoint's bound flag), kept for the next one
+  struct StateBufs {
+    float* ckpt = nullptr;
+    int32_t* ckpt_j = nullptr;
+    int32_t* nused = nullptr;
+    size_t ckpt_bytes = 0, ckpt_j_bytes = 0, nused_bytes = 0;
+  } spare;
   // footprint-cell marches: per side stream, a count and the work items of
   // cells with more than 64 pixels
   void* d_ovf = nullptr;
@@ -109,7 +117,9 @@ struct vr_ctx {
   int32_t foot = 1;           // forward ring march, parallel rays: footprint cells (1) or 8 x 8 pixel tiles (0)
   double foot_rays = 60.0;    // footprint cells: mean pixels per cell (each holds at most 64 in one pass)
   int32_t foot_pad = 0;       // footprint cells: extra floats per window row (LDS bank spread)
+  int32_t foot_kmax = 4;      // footprint cells: window rows of at most this many 128-byte lines
   bool debug_plan = false;    // print each view's march shape to stderr
+  double persp_fit = 0.95;    // perspective ring march: fraction of tiles whose windows the slot holds
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
   struct TuneEntry {
     std::string key;

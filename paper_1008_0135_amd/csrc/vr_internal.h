@@ -269,6 +269,7 @@ struct BwdArgs {
   int32_t npix;
   int32_t smax;       // layer groups: samples of one ray in one group, at most
   int32_t pad;
+  int32_t* flag;      // set to 1 when a ray's group held more than smax samples
 };
 
 // Batched rendering: one descriptor per request (whole volume, own view,

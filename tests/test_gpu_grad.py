@@ -215,3 +215,42 @@ def test_c5_full_size_two_views(ctx):
     _say(f"C5 max rel err: tf {r_tf.max():.3g}, voxels {r_vol.max():.3g}")
     assert r_tf.max() <= 1e-3
     assert r_vol.max() <= 1e-3
+
+
+def test_checkpoint_interval_follows_ckpt_K(ctx):
+    """The planned checkpoint group follows ckpt_K: L = round(K step |d_b|) cell layers,
+    capped at 4, so the interval is min(K, about 4 / (step |d_b|)) samples; gradients
+    agree across intervals (the exact derivative does not depend on where the
+    recomputation restarts)."""
+    vol, tf, vmin, vmax = _case(seed=51)
+    n3, n2, n1 = vol.shape
+    dvol = torch.from_numpy(vol).cuda()
+    h = vr.vr_volume_wrap(ctx, dvol, (n1, n2, n3))
+    vr.vr_tf_set(ctx, tf, vmin, vmax)
+    R = synth.random_views(1, 52)[0]
+    W = H = 40
+    view = vr.make_view(R, W, H)
+    out = torch.empty((1, H, W, 4), device="cuda")
+    g = torch.from_numpy(np.random.Generator(np.random.PCG64(53)).normal(0, 1, (1, H, W, 4)).astype(np.float32)).cuda()
+    grads = {}
+    for K in (2, 4, 8, 32, 64):
+        st = vr.vr_render(ctx, h, [view], vr.make_params(tau=2.0, ckpt_K=K, ess=0), out, save=True)
+        ring, L, spg = vr.vr_state_info(st, 0)
+        assert ring
+        d = np.abs(np.asarray(R, np.float64)[2])
+        db = L / (0.5 * spg)  # |d_b| of the slab axis the plan took: axis 2 or 3
+        assert min(abs(db - d[1]), abs(db - d[2])) <= 1e-9, (db, d)
+        want = max(1, min(4, int(np.floor(K * 0.5 * db + 0.5))))
+        assert L == want, (K, L, want)
+        assert spg <= K + 1.0 / db + 1e-9, (K, L, spg)
+        _say(f"ckpt_K {K}: {L} cell layers per group, {spg:.2f} samples per checkpoint")
+        gtf = torch.empty((tf.shape[0], 4), device="cuda")
+        gvol = torch.empty_like(dvol)
+        vr.vr_render_backward(ctx, h, st, g, gtf, gvol)
+        torch.cuda.synchronize()
+        grads[K] = (gtf.cpu().numpy().astype(np.float64), gvol.cpu().numpy().astype(np.float64))
+        vr.vr_state_destroy(st)
+    for K in (2, 4, 8, 64):
+        assert _rel(grads[K][0], grads[32][0]).max() <= 1e-4
+        assert _rel(grads[K][1], grads[32][1]).max() <= 1e-4
+    vr.vr_volume_destroy(h)
