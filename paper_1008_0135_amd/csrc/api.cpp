@@ -363,6 +363,7 @@ int vr_create(int device, vr_ctx** out) {
     if (k == 2 || k == 3) ctx->ring_nslots = k;
   }
   if (const char* m = std::getenv("VR_FOOT")) ctx->foot = std::atoi(m) != 0 ? 1 : 0;
+  if (const char* m = std::getenv("VR_RING_REG")) ctx->ring_reg = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_FOOT_PAD")) ctx->foot_pad = std::max(0, std::min(32, std::atoi(m)));
   if (const char* m = std::getenv("VR_FOOT_KMAX")) ctx->foot_kmax = std::max(1, std::min(4, std::atoi(m)));
   if (const char* m = std::getenv("VR_DEBUG_PLAN")) ctx->debug_plan = std::atoi(m) != 0;

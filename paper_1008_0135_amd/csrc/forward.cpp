@@ -26,6 +26,8 @@ constexpr int32_t kRingCap = 8192;
 constexpr int32_t kRingMaxWaves = 24;
 constexpr int32_t kRingWantWaves = 12;  // below this the march starts to wait on its loads
 constexpr int32_t kRingMinWaves = 2;
+// register-staged ring march: its registers leave room for 4 wavefronts per SIMD
+constexpr int32_t kRingRegWaves = 16;
 
 }  // namespace
 
@@ -152,12 +154,14 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     ViewPlan& vp = plans[v];
     if (extras || cams[v].persp || !ctx->foot || !(mode == 0 || mode == 3) || tw != 8) continue;
     FootShape fs;
+    const bool reg = plain_ring && ctx->ring_reg && ctx->ring_nslots != 3;
     if (!choose_foot(cams[v], kRingCap, base.M, kRingMaxWaves, kRingWantWaves, ctx->foot_rays,
-                     plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad, ctx->foot_kmax))
+                     plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad, ctx->foot_kmax, reg ? kRingRegWaves : 0,
+                     kRingRegLoads))
       continue;
     if (ctx->debug_plan)
-      std::fprintf(stderr, "[vr] view %d: cells axis %d Tf %.1f Tg %.2f nf %d ng %d slot %d nslots %d wpb %d waves %d rf %.3f rg %.3f\n",
-                   v, fs.axis, fs.Tf, fs.Tg, fs.nf, fs.ng, fs.slot, fs.nslots, fs.wpb, fs.waves, fs.rf, fs.rg);
+      std::fprintf(stderr, "[vr] view %d: cells axis %d Tf %.1f Tg %.2f nf %d ng %d slot %d nslots %d reg %d wpb %d waves %d rf %.3f rg %.3f\n",
+                   v, fs.axis, fs.Tf, fs.Tg, fs.nf, fs.ng, fs.slot, fs.nslots, fs.reg, fs.wpb, fs.waves, fs.rf, fs.rg);
     vp.foot = true;
     vp.fs = fs;
     Box whole;
@@ -257,6 +261,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       a.slab_axis = fs.axis;
       a.ring_slot = fs.slot;
       a.ring_nslots = fs.nslots;
+      a.ring_reg = fs.reg;
       ring_wpb = fs.wpb;
       a.foot_nf = fs.nf;
       a.foot_ng = fs.ng;

@@ -415,8 +415,14 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
   return found;
 }
 
+int32_t window_loads(int32_t pitch, int32_t ng) {
+  const int32_t rows = 64 / std::max(1, pitch / 4);
+  return rows > 0 ? (ng + rows - 1) / rows : 1 << 30;
+}
+
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
-                 int32_t nslots_rule, FootShape& out, int32_t pad, int32_t kmax) {
+                 int32_t nslots_rule, FootShape& out, int32_t pad, int32_t kmax, int32_t reg_waves,
+                 int32_t reg_loads) {
   if (cam.persp) return false;
   const double p = cam.S / (double)cam.W;
   const double* e1 = cam.e1;
@@ -449,8 +455,10 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
       if (rows > 62.0) continue;
       int32_t waves3 = 0, waves2 = 0;
       const int w3 = ring_waves_per_block((int32_t)slot, M, max_waves, &waves3, 3);
-      const int w2 = ring_waves_per_block((int32_t)slot, M, max_waves, &waves2, 2);
-      const bool two = nslots_rule == 2 || (nslots_rule == 0 && waves2 > waves3);
+      const bool reg = reg_waves > 0 && window_loads(pitch, ng) <= reg_loads;
+      const int w2 = ring_waves_per_block((int32_t)slot, M, reg ? std::min(max_waves, reg_waves) : max_waves,
+                                          &waves2, 2);
+      const bool two = reg || nslots_rule == 2 || (nslots_rule == 0 && waves2 > waves3);
       const int32_t waves = two ? waves2 : waves3;
       if (waves < 2) continue;
       // 128-byte lines per window row (a row starts anywhere in a line), per
@@ -468,6 +476,7 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
         out.slot = (int32_t)slot;
         out.wpb = two ? w2 : w3;
         out.nslots = two ? 2 : 3;
+        out.reg = reg ? 1 : 0;
         out.waves = waves;
         out.rf = rf;
         out.rg = rg;

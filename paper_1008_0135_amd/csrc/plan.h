@@ -123,6 +123,7 @@ struct FootShape {
   int32_t nf = 0, ng = 0;     // window extents (before rows are rounded to 16 bytes)
   int32_t slot = 0;           // floats per window slot (rows rounded up)
   int32_t wpb = 4, nslots = 3, waves = 0;
+  int32_t reg = 0;            // 1: two slots, the layer after next staged in registers
   double rf = 0.0, rg = 0.0;  // ray slope along f and g per unit of b
   double fa_u = 0.0, fa_v = 0.0, fb_u = 0.0, fb_v = 0.0;  // cell coordinates per pixel step
   double rays = 0.0;          // mean pixels per cell
@@ -132,9 +133,16 @@ struct FootShape {
 // `cap` floats per slot; the choice with the fewest 128-byte lines per ray and
 // unit of ray length, weighted by how far occupancy falls below want_waves.
 // nslots_rule: 3, 2, or 0 = two slots wherever they fit more wavefronts than
-// three (the plain march).  False when no axis suits.
+// three (the plain march).  reg_waves > 0: the plain march stages the layer
+// after next in registers wherever a layer's window takes at most reg_loads
+// 16-byte loads per lane; two slots then, and at most reg_waves wavefronts
+// per compute unit (the registers it takes).  False when no axis suits.
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
-                 int32_t nslots_rule, FootShape& out, int32_t pad = 0, int32_t kmax = 4);
+                 int32_t nslots_rule, FootShape& out, int32_t pad = 0, int32_t kmax = 4, int32_t reg_waves = 0,
+                 int32_t reg_loads = 0);
+// 16-byte loads per lane that one window of pitch x ng floats takes (a load
+// instruction carries 64 / (pitch / 4) whole rows)
+int32_t window_loads(int32_t pitch, int32_t ng);
 // Cells of one brick: the range of cells that rays crossing its ownership box
 // fall in, and the cell coordinates of pixel (0, 0)'s ray on its plane b = 0.
 void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t& cf0, int32_t& cg0, int32_t& ncf,

@@ -211,6 +211,8 @@ struct MarchArgs {
   int32_t mc;            // macrocell edge in cells; 0 = no macrocell skipping
   int32_t mcn[3];        // macrocells per axis
   int32_t ring_nslots;   // ring march: LDS slots per wavefront, 3 (one layer in flight while sampling) or 2
+  int32_t ring_reg;      // two slots: 1 = the layer after next travels through registers while a
+                         // layer is sampled (at most kRingRegLoads loads per lane per layer)
   int32_t mask_axis;     // axis of the channel mask (2, or 1 in the permuted copy)
   const float* mask;     // channel weights along mask_axis (global indices), or null
   int32_t tile_order;    // ring march: tiles of a brick numbered along rows (0), down columns (1),
@@ -288,6 +290,8 @@ struct BatchReq {
 
 // Allocation-free batched entry point: its device scratch holds the
 // descriptor table of at most kNoAllocMaxReq requests, then the work counter.
+// register-staged ring march: 16-byte loads per lane for one voxel layer's window
+constexpr int kRingRegLoads = 8;
 constexpr int kNoAllocMaxReq = 512;
 constexpr size_t kNoAllocBytes = sizeof(BatchReq) * kNoAllocMaxReq + 256;
 constexpr int kMaxDevices = 64;

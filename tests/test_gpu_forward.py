@@ -243,10 +243,13 @@ def test_c2_full_size_strided_rays(ctx):
 
 def _ctx_with_march(mode):
     """A context with one march forced; "ring2" / "ring3": the ring march with
-    two / three LDS slots per wavefront."""
+    two / three LDS slots per wavefront ("ring2": the layer after next staged in
+    registers, "ring2mem": loaded straight into LDS after a layer is done)."""
     import os
     if mode in ("ring2", "ring3"):
         env = {"VR_MARCH": "ring", "VR_RING_SLOTS": mode[-1]}
+    elif mode == "ring2mem":  # two slots, the layer after next loaded straight into LDS
+        env = {"VR_MARCH": "ring", "VR_RING_SLOTS": "2", "VR_RING_REG": "0"}
     elif mode.startswith("ring:"):  # the ring march with tiles numbered in another order
         env = {"VR_MARCH": "ring", "VR_TILE_ORDER": mode[5:]}
     else:
@@ -275,7 +278,7 @@ def test_marches_identical():
     imgs = {}
     layouts = {"grid": vr.grid_spec((48, 64, 80)), "mat": vr.grid_spec((48, 64, 80), materialize=True),
                "kd": vr.kd_spec(7), "whole": None}
-    for mode in ("gather", "slab", "ring", "ring2", "ring3"):
+    for mode in ("gather", "slab", "ring", "ring2", "ring2mem", "ring3"):
         _say(f"  march {mode}")
         c = _ctx_with_march(mode)
         h = _upload(c, vol)
@@ -295,7 +298,7 @@ def test_marches_identical():
     for name in layouts:
         for W in (96, 333):
             a = imgs[("gather", name, W)]
-            for mode in ("slab", "ring", "ring2", "ring3"):
+            for mode in ("slab", "ring", "ring2", "ring2mem", "ring3"):
                 b = imgs[(mode, name, W)]
                 assert np.array_equal(a, b), (mode, name, W, float(np.abs(a - b).max()))
     mn, mx = float(vol.min()), float(vol.max())
