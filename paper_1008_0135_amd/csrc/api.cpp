@@ -364,6 +364,17 @@ int vr_create(int device, vr_ctx** out) {
   }
   if (const char* m = std::getenv("VR_FOOT")) ctx->foot = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_RING_REG")) ctx->ring_reg = std::atoi(m) != 0 ? 1 : 0;
+  if (const char* m = std::getenv("VR_CELLS_WAVES")) ctx->cells_waves = std::max(0, std::min(32, std::atoi(m)));
+  if (const char* m = std::getenv("VR_FOOT_BLOCK")) {
+    int bf = 0, bg = 0;
+    if (std::sscanf(m, "%dx%d", &bf, &bg) == 2 && bf >= 1 && bg >= 1 && bf * bg >= 2 && bf * bg <= 8) {
+      ctx->foot_block = 1;
+      ctx->foot_block_f = bf;
+      ctx->foot_block_g = bg;
+    } else {
+      ctx->foot_block = std::atoi(m) != 0 ? -1 : 0;
+    }
+  }
   if (const char* m = std::getenv("VR_FOOT_PAD")) ctx->foot_pad = std::max(0, std::min(32, std::atoi(m)));
   if (const char* m = std::getenv("VR_FOOT_KMAX")) ctx->foot_kmax = std::max(1, std::min(4, std::atoi(m)));
   if (const char* m = std::getenv("VR_DEBUG_PLAN")) ctx->debug_plan = std::atoi(m) != 0;

@@ -26,8 +26,9 @@ constexpr int32_t kRingCap = 8192;
 constexpr int32_t kRingMaxWaves = 24;
 constexpr int32_t kRingWantWaves = 12;  // below this the march starts to wait on its loads
 constexpr int32_t kRingMinWaves = 2;
-// register-staged ring march: its registers leave room for 4 wavefronts per SIMD
+// register-staged cells march: its registers leave room for 4 wavefronts per SIMD
 constexpr int32_t kRingRegWaves = 16;
+constexpr int32_t kLdsPerCu = 160 * 1024;
 
 }  // namespace
 
@@ -154,22 +155,44 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     ViewPlan& vp = plans[v];
     if (extras || cams[v].persp || !ctx->foot || !(mode == 0 || mode == 3) || tw != 8) continue;
     FootShape fs;
-    const bool reg = plain_ring && ctx->ring_reg && ctx->ring_nslots != 3;
-    if (!choose_foot(cams[v], kRingCap, base.M, kRingMaxWaves, kRingWantWaves, ctx->foot_rays,
+    // register-staged cells: a lane's offset inside a window's rows (at most
+    // kRingRegLoads instructions of up to 16 rows) must stay below 4 GiB
+    const int64_t row_stride = std::max(vol->n[0], vol->n[0] * vol->n[1]);
+    const bool reg = plain_ring && ctx->ring_reg > 0 && ctx->ring_nslots != 3 &&
+                     ((int64_t)kRingRegLoads * 16 * row_stride + 256) * 4 < ((int64_t)1 << 32);
+    if (!choose_foot(cams[v], kRingCap, base.M, kRingMaxWaves, reg ? kRingRegWaves : kRingWantWaves, ctx->foot_rays,
                      plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad, ctx->foot_kmax, reg ? kRingRegWaves : 0,
                      kRingRegLoads))
       continue;
-    if (ctx->debug_plan)
-      std::fprintf(stderr, "[vr] view %d: cells axis %d Tf %.1f Tg %.2f nf %d ng %d slot %d nslots %d reg %d wpb %d waves %d rf %.3f rg %.3f\n",
-                   v, fs.axis, fs.Tf, fs.Tg, fs.nf, fs.ng, fs.slot, fs.nslots, fs.reg, fs.wpb, fs.waves, fs.rf, fs.rg);
-    vp.foot = true;
-    vp.fs = fs;
     Box whole;
     for (int i = 0; i < 3; i++) {
       whole.lo[i] = 0;
       whole.hi[i] = vol->n[i] - 1;
       whole.closed[i] = 1;
     }
+    // blocks of cells (the plain march, emission-absorption or MIP): one
+    // workgroup per block, one window per layer; the window's rows must fit
+    // inside every brick along axis 1
+    if (plain_ring && ctx->foot_block != 0) {
+      int64_t ext[3] = {INT64_MAX, 0, 0};
+      for (const DevBrickView& b : vp.bv) {
+        const Box& bx = bricked ? vol->part.boxes[b.brick] : whole;
+        ext[0] = std::min<int64_t>(ext[0], bx.hi[0] - bx.lo[0]);
+        for (int i = 1; i < 3; i++) ext[i] = std::max<int64_t>(ext[i], bx.hi[i] - bx.lo[i]);
+      }
+      const Box& b0 = bricked ? vol->part.boxes[vp.bv.empty() ? 0 : vp.bv[0].brick] : whole;
+      int64_t typ[3];
+      for (int i = 0; i < 3; i++) typ[i] = b0.hi[i] - b0.lo[i];
+      typ[0] = std::min(typ[0], ext[0]);
+      choose_foot_block(cams[v], fs, typ, base.M, kRingRegWaves, kRingRegWaves, kRingRegLoads,
+                        ctx->foot_block > 0 ? ctx->foot_block_f : 0, ctx->foot_block > 0 ? ctx->foot_block_g : 0);
+    }
+    if (ctx->debug_plan)
+      std::fprintf(stderr, "[vr] view %d: cells axis %d Tf %.1f Tg %.2f nf %d ng %d slot %d nslots %d reg %d wpb %d waves %d rf %.3f rg %.3f blocks %dx%d nf %d ng %d waves %d\n",
+                   v, fs.axis, fs.Tf, fs.Tg, fs.nf, fs.ng, fs.slot, fs.nslots, fs.reg, fs.wpb, fs.waves, fs.rf, fs.rg,
+                   fs.blk_f, fs.blk_g, fs.blk_nf, fs.blk_ng, fs.blk_waves);
+    vp.foot = true;
+    vp.fs = fs;
     int32_t tiles = 0;
     size_t w = 0;  // wave of the brick (whole-ray termination)
     for (size_t i = 0; i < vp.bv.size(); i++) {
@@ -182,18 +205,25 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       foot_cells(cams[v], fs, bricked ? vol->part.boxes[b.brick] : whole, b.cf0, b.cg0, ncf, ncg, b.fa0, b.fb0);
       b.tiles_x = ncf;
       b.tile_begin = tiles;
-      tiles += ncf * ncg;
+      if (fs.blk_f > 0) {
+        b.blocks_x = (ncf + fs.blk_f - 1) / fs.blk_f;
+        tiles += b.blocks_x * ((ncg + fs.blk_g - 1) / fs.blk_g);
+      } else {
+        b.blocks_x = 0;
+        tiles += ncf * ncg;
+      }
       if (global) vp.wave_tiles[w] = tiles;
     }
     if (!global) vp.ntiles = tiles;
   }
   if (bricked && arena_pix > 0) VR_TRY(ensure_device(&ctx->d_arena, &ctx->arena_bytes, (size_t)arena_pix * 16));
   // overflow lists of the footprint-cell marches: one per stream a view may use
-  int64_t foot_tiles = 0;
+  int64_t foot_tiles = 0;  // cells of a launch (a block holds blk_f x blk_g)
   for (const ViewPlan& vp : plans)
     if (vp.foot) {
-      foot_tiles = std::max<int64_t>(foot_tiles, vp.ntiles);
-      for (int32_t t : vp.wave_tiles) foot_tiles = std::max<int64_t>(foot_tiles, t);
+      const int64_t per = vp.fs.blk_f > 0 ? (int64_t)vp.fs.blk_f * vp.fs.blk_g : 1;
+      foot_tiles = std::max<int64_t>(foot_tiles, vp.ntiles * per);
+      for (int32_t t : vp.wave_tiles) foot_tiles = std::max<int64_t>(foot_tiles, t * per);
     }
   const size_t ovf_stride = align16(256 + 4 * (size_t)foot_tiles);
   if (foot_tiles > 0) VR_TRY(ensure_device(&ctx->d_ovf, &ctx->ovf_bytes, ovf_stride * vr_ctx::kAux));
@@ -262,11 +292,27 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       a.ring_slot = fs.slot;
       a.ring_nslots = fs.nslots;
       a.ring_reg = fs.reg;
+      if (fs.reg && ctx->cells_waves > 0) {
+        // at most cells_waves wavefronts per compute unit: reserve LDS so that
+        // one workgroup more would not fit (more wavefronts ran slower: their
+        // windows crowd each other out of the caches)
+        const int32_t nwg = std::max(1, ctx->cells_waves / std::max(1, fs.wpb));
+        a.lds_floor = kLdsPerCu / (nwg + 1) + 1024;
+      }
       ring_wpb = fs.wpb;
       a.foot_nf = fs.nf;
       a.foot_ng = fs.ng;
       a.foot_Tf = fs.Tf;
       a.foot_Tg = fs.Tg;
+      if (fs.blk_f > 0) {
+        // one window per block: its rows and slot replace the cell's
+        a.blk_f = fs.blk_f;
+        a.blk_g = fs.blk_g;
+        a.foot_nf = fs.blk_nf;
+        a.foot_ng = fs.blk_ng;
+        a.ring_slot = fs.blk_slot;
+        a.ring_nslots = 2;
+      }
       a.fa_u = fs.fa_u;
       a.fa_v = fs.fa_v;
       a.fb_u = fs.fb_u;

@@ -53,108 +53,14 @@ using namespace ring;
 
 constexpr int kSlotsMax = 3;
 
-// Pixels of footprint cell (ci, cj) of a brick: lane r holds the run of image
-// row vrow0 + r that falls in the cell (first column u0, inclusive and
-// exclusive counts over the rows before it); n = pixels in the cell.
-struct FootRuns {
-  int vrow0, u0, incl, excl, n;
-};
-
-__device__ FootRuns foot_runs(const MarchArgs& a, const DevBrickView& bvw, int ci, int cj, int lane) {
-  FootRuns fr;
-  const double au = a.fa_u, av = a.fa_v, bu = a.fb_u, bvv = a.fb_v;
-  const double det = au * bvv - av * bu;
-  // image rows the cell's corners span (one row of margin each side)
-  double vmn = INFINITY, vmx = -INFINITY;
-  for (int q = 0; q < 4; ++q) {
-    const double ra = (double)(ci + (q & 1)) - bvw.fa0, rb = (double)(cj + (q >> 1)) - bvw.fb0;
-    const double vq = (au * rb - bu * ra) / det;
-    vmn = fmin(vmn, vq);
-    vmx = fmax(vmx, vq);
-  }
-  fr.vrow0 = uni(max(0, (int)floor(vmn) - 1));
-  const int vlast = uni(min(a.cam.H - 1, (int)ceil(vmx) + 1));
-  const int vrow = fr.vrow0 + lane;
-  int cnt_row = 0;
-  fr.u0 = 0;
-  if (vrow <= vlast) {
-    // columns u in [0, W) of row vrow whose cell coordinate lies in
-    // [cell, cell + 1): one run, the coordinate being monotone along the row
-    auto run = [&](double c0, double su, double sv, int cell, int& lo_u, int& hi_u) {
-      const int Wm = a.cam.W;
-      if (su == 0.0) {
-        const double x = foot_cell_coord(c0, su, sv, 0, vrow);
-        const bool in = x >= (double)cell && x < (double)(cell + 1);
-        lo_u = in ? 0 : 1;
-        hi_u = in ? Wm - 1 : 0;
-        return;
-      }
-      const bool inc = su > 0.0;
-      int l = 0, h = Wm;  // first column past the cell's near edge
-      while (l < h) {
-        const int m = (l + h) >> 1;
-        const double x = foot_cell_coord(c0, su, sv, m, vrow);
-        if (inc ? x >= (double)cell : x < (double)(cell + 1)) h = m;
-        else l = m + 1;
-      }
-      lo_u = l;
-      l = 0;
-      h = Wm;  // first column past the cell's far edge
-      while (l < h) {
-        const int m = (l + h) >> 1;
-        const double x = foot_cell_coord(c0, su, sv, m, vrow);
-        if (inc ? x >= (double)(cell + 1) : x < (double)cell) h = m;
-        else l = m + 1;
-      }
-      hi_u = l - 1;
-    };
-    int fl, fh, gl, gh;
-    run(bvw.fa0, au, av, ci, fl, fh);
-    run(bvw.fb0, bu, bvv, cj, gl, gh);
-    fr.u0 = max(fl, gl);
-    cnt_row = max(0, min(fh, gh) - fr.u0 + 1);
-  }
-  fr.incl = cnt_row;
-  for (int off = 1; off < 64; off <<= 1) {
-    const int y = __shfl_up(fr.incl, off);
-    if (lane >= off) fr.incl += y;
-  }
-  fr.excl = fr.incl - cnt_row;
-  fr.n = uni(__builtin_amdgcn_readlane(fr.incl, 63));
-  return fr;
-}
-
-// Pixel k (0 <= k < n) of the cell: the row is the first whose inclusive count
-// exceeds k.  Every lane takes part (cross-lane reads).
-__device__ __forceinline__ void foot_pixel(const FootRuns& fr, int k, int& u, int& v) {
-  int r = 0;
-  for (int stp = 32; stp > 0; stp >>= 1)
-    if (__shfl(fr.incl, r + stp - 1) <= k) r += stp;
-  r = min(r, 63);
-  u = __shfl(fr.u0, r) + (k - __shfl(fr.excl, r));
-  v = fr.vrow0 + r;
-}
-
-// Footprint cell of work item t of a brick view.
-__device__ __forceinline__ void foot_cell(const DevBrickView& bvw, int t, int& ci, int& cj) {
-  ci = bvw.cf0 + t % bvw.tiles_x;
-  cj = bvw.cg0 + t / bvw.tiles_x;
-}
-
 // SAVE (differentiable forward, whole volume): also store, for every group of
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
 // MIP: maximum intensity projection (no table, no skipping, no saving).
-// REG (two slots): the window of the layer after next is loaded into
-// registers while the current cell layer is sampled, and written to the slot
-// the finished layer frees; LDS holds only the two layers being sampled, so a
-// compute unit keeps as many wavefronts as with two slots and each still has
-// a layer in flight.
-template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false, bool MASK = false, bool REG = false>
+template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false, bool MASK = false>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   static_assert(!(PERSP && SAVE), "the checkpointing forward is orthographic");
   static_assert(!TWO || !(ESS || SAVE), "two slots: the plain march");
-  static_assert(!REG || TWO, "registers stage the third layer of a two-slot ring");
   static_assert(!(MASK && (SAVE || TWO)), "the channel mask: three-slot forward marches");
   constexpr int kSlots = TWO ? 2 : 3;
   extern __shared__ float4 smem[];
@@ -198,7 +104,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
     fr = foot_runs(a, bvw, ci, cj, lane);
     // cells of more than 64 pixels: the pixels past the 64th are marched by
     // k_march_ring_ovf after this launch
-    if (fr.n > 64 && lane == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile;
+    if (fr.n > 64 && lane == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile * 8;
   } else {
     // tile numbering inside the brick's rectangle.  Tiles started together run
     // at about the same layer; the L2 keeps a line only a few microseconds, so
@@ -562,81 +468,7 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   // cell layer c_k = Lbeg +- k reads V_k and V_{k+1}
   const int vstep = up ? 1 : -1;
   const int V0 = up ? Lbeg : Lbeg + 1;
-  if constexpr (REG) {
-    // two LDS slots; V_{k+2} waits in registers while c_k is sampled
-    const float fclo = (float)cloB, fchi = (float)chiB;
-    // every lane of a load instruction reads a row of the window (lanes past
-    // the instruction's rows, and rows past the window, re-read its last row)
-    // and only lanes holding a row of the window write it to LDS
-    typedef float v4f __attribute__((ext_vector_type(4)));
-    v4f rr[kRingRegLoads];
-    const int rl_c = min(rl, R - 1), c4_c = lane_on ? c4l : 0;
-    auto rload = [&](int V, const Window& w) {
-      gfloat* gb = gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0) + 4 * c4_c;
-#pragma unroll
-      for (int i = 0; i < kRingRegLoads; ++i)
-        if (i < nload)
-          rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (int64_t)min(i * R + rl_c, NG - 1) * sG);
-    };
-    auto rstore = [&](float* sdst) {
-      v4f* l = (v4f*)(sdst + 4 * lane);
-#pragma unroll
-      for (int i = 0; i < kRingRegLoads; ++i)
-        if (i < nload && lane_on && i * R + rl < NG) l[i * R * (pitch >> 2)] = rr[i];
-    };
-    Window w0 = window(V0), w1 = window(V0 + vstep), w2;
-    rload(V0, w0);
-    rstore(s_ring);
-    rload(V0 + vstep, w1);
-    rstore(s_ring + slot);
-    if (nlay > 1) {
-      w2 = window(V0 + 2 * vstep);
-      rload(V0 + 2 * vstep, w2);
-    }
-    int s0 = 0;  // slot of V_k (V_{k+1} is in the other)
-    for (int k = 0; k < nlay; ++k) {
-      const int c = up ? Lbeg + k : Lbeg - k;
-      const Window& wl = up ? w0 : w1;
-      const Window& wu = up ? w1 : w0;
-      const int sl = up ? s0 : s0 ^ 1, su = up ? s0 ^ 1 : s0;
-      const float* baseL = s_ring + (sl * slot - wl.g0 * pitch - wl.f0);
-      const int dU = (su * slot - wu.g0 * pitch - wu.f0) - (sl * slot - wl.g0 * pitch - wl.f0);
-      while (!done) {
-        const SamplePos q = sample_pos(j, px, py, pz, sx, sy, sz);
-        const int ib = (int)floorf(__builtin_amdgcn_fmed3f(by ? q.y : q.z, fclo, fchi));
-        if (ib != c) break;
-        const Cell cl = cell_of(q, br);
-        const int ig = by ? cl.iz : cl.iy;
-        const float* p = baseL + (__mul24(ig, pitch) + cl.ix);
-        const float* pu = p + dU;
-        const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];
-        const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
-        const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
-                             : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
-        ++j;
-        if (MIP) {
-          const float s = norm_value(val, a.vmin, a.inv_range);
-          mx = fmaxf(mx, s);
-          if (j >= cnt || mx >= 1.f) done = true;
-        } else {
-          const Classified kk = classify(val, a.vmin, a.inv_range, a.M, s_tf);
-          accumulate(kk, Cr, Cg, Cb, T);
-          if (j >= cnt || 1.f - T >= a.tau) done = true;
-        }
-      }
-      if (__all(done)) break;
-      if (k + 1 < nlay) {
-        rstore(s_ring + s0 * slot);  // V_{k+2} replaces V_k (same wavefront: LDS order holds)
-        w0 = w1;
-        w1 = w2;
-        if (k + 2 < nlay) {
-          w2 = window(V0 + (k + 3) * vstep);
-          rload(V0 + (k + 3) * vstep, w2);
-        }
-      }
-      s0 ^= 1;
-    }
-  } else if constexpr (!ESS) {
+  if constexpr (!ESS) {
     const float fclo = (float)cloB, fchi = (float)chiB;
     Window w0 = window(V0), w1 = window(V0 + vstep);
     issue(V0, w0, s_ring);
@@ -820,16 +652,6 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
 // lane, its corners read from global memory; the same samples, arithmetic and
 // order as every march.  Wavefronts take listed cells in turn until the list
 // is done.
-__device__ __forceinline__ int find_bv(const MarchArgs& a, int tile) {
-  int lo = 0, hi = a.nbv - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (a.bv[mid].tile_begin <= tile) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 template <bool MIP, bool MASK>
 __global__ __launch_bounds__(256) void k_march_ring_ovf(MarchArgs a) {
   extern __shared__ float4 smem[];
@@ -840,11 +662,12 @@ __global__ __launch_bounds__(256) void k_march_ring_ovf(MarchArgs a) {
   const int nw = (int)(gridDim.x * (blockDim.x >> 6));
   const int n_listed = (int)*a.ovf_count;
   for (int e = (int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); e < n_listed; e += nw) {
-    const int tile = a.ovf_tiles[e];
+    const int tile = a.ovf_tiles[e] >> 3, w = a.ovf_tiles[e] & 7;
     const DevBrickView bvw = a.bv[find_bv(a, tile)];
     const DevBrick br = a.bricks[bvw.brick];
     int ci, cj;
-    foot_cell(bvw, tile - bvw.tile_begin, ci, cj);
+    if (a.blk_f > 0) block_cell(a, bvw, tile - bvw.tile_begin, w, ci, cj);
+    else foot_cell(bvw, tile - bvw.tile_begin, ci, cj);
     const FootRuns fr = foot_runs(a, bvw, ci, cj, lane);
     gfloat* gb = (gfloat*)br.base;
     const int ys = br.sy, zs = br.sz;
@@ -916,7 +739,8 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   hipLaunchKernelGGL(k_ovf_reset, dim3(1), dim3(1), 0, s, a.ovf_count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = launch_march_ring_main(a, wpb, s);
+  e = a.blk_f > 0 ? launch_march_block(a, s)
+                   : (a.ring_reg ? launch_march_cells(a, wpb, s) : launch_march_ring_main(a, wpb, s));
   if (e != hipSuccess) return e;
   const dim3 g(256), b(256);
   const size_t lds = sizeof(float4) * (size_t)a.M;
@@ -961,10 +785,7 @@ static hipError_t launch_march_ring_main(const MarchArgs& a, int wpb, hipStream_
     else if (a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, false, true, true>), g, b, lds, s, a, none);
     else hipLaunchKernelGGL((k_march_ring<false, false, false, true>), g, b, lds, s, a, none);
   } else {
-    if (a.ring_nslots == 2 && a.ring_reg) {
-      if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, false, true, false, true>), g, b, lds, s, a, none);
-      else hipLaunchKernelGGL((k_march_ring<false, false, false, false, true, false, true>), g, b, lds, s, a, none);
-    } else if (a.mip && a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, true, false, true>), g, b, lds, s, a, none);
+    if (a.mip && a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, true, false, true>), g, b, lds, s, a, none);
     else if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, false>), g, b, lds, s, a, none);
     else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, false>), g, b, lds, s, a, none);
     else if (a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, false, false, true>), g, b, lds, s, a, none);

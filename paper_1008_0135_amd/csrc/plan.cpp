@@ -415,6 +415,41 @@ bool choose_ring(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
   return found;
 }
 
+// Most pixels any cell of Tf x Tg holds, over 32 placements of the cell grid
+// against the pixel lattice (Halton points): (su_f, sv_f) and (su_g, sv_g) are
+// the cell coordinates f / Tf and g / Tg per pixel step along u and v.  When a
+// cell edge runs nearly along a lattice direction the counts jump by whole
+// rows, so a mean well below 64 can still leave many cells above it.
+static int32_t foot_max_pixels(double su_f, double sv_f, double su_g, double sv_g) {
+  const double det = su_f * sv_g - sv_f * su_g;
+  if (!(std::fabs(det) > 1e-12)) return 1 << 30;
+  int32_t worst = 0;
+  for (int i = 1; i <= 32; i++) {
+    double a = 0.0, b = 0.0;
+    for (int n = i, f2 = 2; n > 0; n /= 2, f2 *= 2) a += (double)(n % 2) / f2;
+    for (int n = i, f3 = 3; n > 0; n /= 3, f3 *= 3) b += (double)(n % 3) / f3;
+    // pixel box of the cell 0 <= a + F < 1, 0 <= b + G < 1
+    double ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+    for (int c = 0; c < 4; c++) {
+      const double F = (double)(c & 1) - a, G = (double)(c >> 1) - b;
+      const double u = (F * sv_g - G * sv_f) / det, v = (G * su_f - F * su_g) / det;
+      ulo = std::min(ulo, u);
+      uhi = std::max(uhi, u);
+      vlo = std::min(vlo, v);
+      vhi = std::max(vhi, v);
+    }
+    if ((uhi - ulo + 1.0) * (vhi - vlo + 1.0) > 1e5) return 1 << 30;
+    int32_t n = 0;
+    for (int v = (int)std::floor(vlo); v <= (int)std::ceil(vhi); v++)
+      for (int u = (int)std::floor(ulo); u <= (int)std::ceil(uhi); u++) {
+        const double F = a + u * su_f + v * sv_f, G = b + u * su_g + v * sv_g;
+        n += (F >= 0.0 && F < 1.0 && G >= 0.0 && G < 1.0) ? 1 : 0;
+      }
+    worst = std::max(worst, n);
+  }
+  return worst;
+}
+
 int32_t window_loads(int32_t pitch, int32_t ng) {
   const int32_t rows = 64 / std::max(1, pitch / 4);
   return rows > 0 ? (ng + rows - 1) / rows : 1 << 30;
@@ -444,7 +479,14 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
     // margin, about a whole number of 32-float lines
     for (int k = 1; k <= kmax; k++) {
       const double Tf = std::max(4.0, 32.0 * k - 2.0 * std::fabs(rf) - 3.5);
-      const double Tg = std::max(1.0, rays * std::fabs(det) / Tf);
+      double Tg = std::max(1.0, rays * std::fabs(det) / Tf);
+      // shrink the cells until (nearly) none holds more than 64 pixels: the
+      // pixels past the 64th are marched by gathers
+      for (int it = 0; it < 8; it++) {
+        const int32_t most = foot_max_pixels(au / Tf, av / Tf, bu / Tg, bv / Tg);
+        if (most <= 64 || Tg <= 1.0) break;
+        Tg = std::max(1.0, Tg * std::min(0.98, 64.0 / most));
+      }
       const int32_t nf = (int32_t)std::floor(Tf + 2.0 * std::fabs(rf) + 0.25) + 3 + pad;
       const int32_t ng = (int32_t)std::floor(Tg + 2.0 * std::fabs(rg) + 0.25) + 3;
       const int32_t pitch = (nf + 3) & ~3;
@@ -464,7 +506,8 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
       // 128-byte lines per window row (a row starts anywhere in a line), per
       // ray, per unit of ray length (|d_b| layers)
       const double lines = (double)ng * ((double)pitch + 31.0) / 32.0;
-      const double cost = lines / rays * std::fabs(d[b]) * std::max(1.0, (double)want_waves / (double)waves);
+      const double cell_rays = Tf * Tg / std::fabs(det);  // mean pixels per cell
+      const double cost = lines / cell_rays * std::fabs(d[b]) * std::max(1.0, (double)want_waves / (double)waves);
       if (cost < best) {
         best = cost;
         found = true;
@@ -484,10 +527,68 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
         out.fa_v = av / Tf;
         out.fb_u = bu / Tg;
         out.fb_v = bv / Tg;
-        out.rays = rays;
+        out.rays = cell_rays;
       }
     }
   }
+  return found;
+}
+
+bool choose_foot_block(const Camera& cam, FootShape& fs, const int64_t ext[3], int32_t M, int32_t max_waves,
+                       int32_t want_waves, int32_t reg_loads, int32_t force_f, int32_t force_g) {
+  if (cam.persp || fs.axis == 0) return false;
+  const int b = fs.axis, g = 3 - b;
+  // cells of a typical brick
+  Box box;
+  for (int i = 0; i < 3; i++) {
+    box.lo[i] = 0;
+    box.hi[i] = ext[i];
+    box.closed[i] = 0;
+  }
+  int32_t cf0, cg0, ncf, ncg;
+  double fa0, fb0;
+  foot_cells(cam, fs, box, cf0, cg0, ncf, ncg, fa0, fb0);
+  (void)g;
+  const double rays = fs.rays;
+  // a wavefront per cell: lines per ray and layer
+  const int32_t pitch1 = (fs.nf + 3) & ~3;
+  const double base_cost = (double)fs.ng * ((double)pitch1 + 31.0) / 32.0 / rays *
+                           std::max(1.0, (double)want_waves / std::max(1, fs.waves));
+  double best = base_cost;
+  bool found = false;
+  for (int bf = 1; bf <= 8; bf++)
+    for (int bg = 1; bf * bg <= 8; bg++) {
+      if (bf * bg < 2) continue;
+      if (force_f > 0 && (bf != force_f || bg != force_g)) continue;
+      const int32_t nf = (int32_t)std::floor(bf * fs.Tf + 2.0 * std::fabs(fs.rf) + 0.25) + 3;
+      const int32_t ng = (int32_t)std::floor(bg * fs.Tg + 2.0 * std::fabs(fs.rg) + 0.25) + 3;
+      const int32_t pitch = (nf + 3) & ~3;
+      if (pitch > 256 || pitch > ext[0] + 1) continue;
+      const int32_t nw = bf * bg;
+      const int32_t loads = (window_loads(pitch, ng) + nw - 1) / nw;
+      if (loads > reg_loads) continue;
+      const int64_t slot = (int64_t)pitch * ng;
+      const int64_t lds_wg = 16 * (int64_t)M + 8 * slot + 128;
+      int64_t wgs = (160 * 1024) / lds_wg;
+      if (wgs * nw > max_waves) wgs = max_waves / nw;
+      const int32_t waves = (int32_t)(wgs * nw);
+      if (waves < nw || waves < 4) continue;
+      // cells the blocks of a typical brick hold, over the cells it has
+      const double pad = (double)(((ncf + bf - 1) / bf) * bf) * (double)(((ncg + bg - 1) / bg) * bg) /
+                         ((double)ncf * (double)ncg);
+      const double lines = (double)ng * ((double)pitch + 31.0) / 32.0;
+      const double cost = lines / (nw * rays) * pad * std::max(1.0, (double)want_waves / waves);
+      if (cost < best || force_f > 0) {
+        best = cost;
+        found = true;
+        fs.blk_f = bf;
+        fs.blk_g = bg;
+        fs.blk_nf = nf;
+        fs.blk_ng = ng;
+        fs.blk_slot = (int32_t)slot;
+        fs.blk_waves = waves;
+      }
+    }
   return found;
 }
 

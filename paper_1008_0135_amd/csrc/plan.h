@@ -124,6 +124,8 @@ struct FootShape {
   int32_t slot = 0;           // floats per window slot (rows rounded up)
   int32_t wpb = 4, nslots = 3, waves = 0;
   int32_t reg = 0;            // 1: two slots, the layer after next staged in registers
+  int32_t blk_f = 0, blk_g = 0;  // blocks of cells marched by one workgroup (0: a wavefront per cell)
+  int32_t blk_nf = 0, blk_ng = 0, blk_slot = 0, blk_waves = 0;  // the block's window and occupancy
   double rf = 0.0, rg = 0.0;  // ray slope along f and g per unit of b
   double fa_u = 0.0, fa_v = 0.0, fb_u = 0.0, fb_v = 0.0;  // cell coordinates per pixel step
   double rays = 0.0;          // mean pixels per cell
@@ -140,6 +142,14 @@ struct FootShape {
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
                  int32_t nslots_rule, FootShape& out, int32_t pad = 0, int32_t kmax = 4, int32_t reg_waves = 0,
                  int32_t reg_loads = 0);
+// Blocks of footprint cells for the chosen cell shape: blk_f x blk_g cells
+// (at most 8) marched by one workgroup with one window per voxel layer, the
+// choice with the fewest 128-byte lines per ray and layer, counting the cells
+// a typical brick (edges `ext`) leaves empty in its blocks, weighted by the
+// occupancy shortfall below want_waves.  force_f / force_g > 0 fix the block.
+// False (fs unchanged) when a wavefront per cell is cheaper.
+bool choose_foot_block(const Camera& cam, FootShape& fs, const int64_t ext[3], int32_t M, int32_t max_waves,
+                       int32_t want_waves, int32_t reg_loads, int32_t force_f = 0, int32_t force_g = 0);
 // 16-byte loads per lane that one window of pitch x ng floats takes (a load
 // instruction carries 64 / (pitch / 4) whole rows)
 int32_t window_loads(int32_t pitch, int32_t ng);

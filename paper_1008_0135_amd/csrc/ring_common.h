@@ -74,5 +74,114 @@ struct Window {
   int f0, g0;
 };
 
+// ---------------------------------------------------------------- footprint cells
+
+// Pixels of footprint cell (ci, cj) of a brick: lane r holds the run of image
+// row vrow0 + r that falls in the cell (first column u0, inclusive and
+// exclusive counts over the rows before it); n = pixels in the cell.
+struct FootRuns {
+  int vrow0, u0, incl, excl, n;
+};
+
+__device__ inline FootRuns foot_runs(const MarchArgs& a, const DevBrickView& bvw, int ci, int cj, int lane) {
+  FootRuns fr;
+  const double au = a.fa_u, av = a.fa_v, bu = a.fb_u, bvv = a.fb_v;
+  const double det = au * bvv - av * bu;
+  // image rows the cell's corners span (one row of margin each side)
+  double vmn = INFINITY, vmx = -INFINITY;
+  for (int q = 0; q < 4; ++q) {
+    const double ra = (double)(ci + (q & 1)) - bvw.fa0, rb = (double)(cj + (q >> 1)) - bvw.fb0;
+    const double vq = (au * rb - bu * ra) / det;
+    vmn = fmin(vmn, vq);
+    vmx = fmax(vmx, vq);
+  }
+  fr.vrow0 = uni(max(0, (int)floor(vmn) - 1));
+  const int vlast = uni(min(a.cam.H - 1, (int)ceil(vmx) + 1));
+  const int vrow = fr.vrow0 + lane;
+  int cnt_row = 0;
+  fr.u0 = 0;
+  if (vrow <= vlast) {
+    // columns u in [0, W) of row vrow whose cell coordinate lies in
+    // [cell, cell + 1): one run, the coordinate being monotone along the row
+    auto run = [&](double c0, double su, double sv, int cell, int& lo_u, int& hi_u) {
+      const int Wm = a.cam.W;
+      if (su == 0.0) {
+        const double x = foot_cell_coord(c0, su, sv, 0, vrow);
+        const bool in = x >= (double)cell && x < (double)(cell + 1);
+        lo_u = in ? 0 : 1;
+        hi_u = in ? Wm - 1 : 0;
+        return;
+      }
+      const bool inc = su > 0.0;
+      int l = 0, h = Wm;  // first column past the cell's near edge
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        const double x = foot_cell_coord(c0, su, sv, m, vrow);
+        if (inc ? x >= (double)cell : x < (double)(cell + 1)) h = m;
+        else l = m + 1;
+      }
+      lo_u = l;
+      l = 0;
+      h = Wm;  // first column past the cell's far edge
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        const double x = foot_cell_coord(c0, su, sv, m, vrow);
+        if (inc ? x >= (double)(cell + 1) : x < (double)cell) h = m;
+        else l = m + 1;
+      }
+      hi_u = l - 1;
+    };
+    int fl, fh, gl, gh;
+    run(bvw.fa0, au, av, ci, fl, fh);
+    run(bvw.fb0, bu, bvv, cj, gl, gh);
+    fr.u0 = max(fl, gl);
+    cnt_row = max(0, min(fh, gh) - fr.u0 + 1);
+  }
+  fr.incl = cnt_row;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(fr.incl, off);
+    if (lane >= off) fr.incl += y;
+  }
+  fr.excl = fr.incl - cnt_row;
+  fr.n = uni(__builtin_amdgcn_readlane(fr.incl, 63));
+  return fr;
+}
+
+// Pixel k (0 <= k < n) of the cell: the row is the first whose inclusive count
+// exceeds k.  Every lane takes part (cross-lane reads).
+__device__ __forceinline__ void foot_pixel(const FootRuns& fr, int k, int& u, int& v) {
+  int r = 0;
+  for (int stp = 32; stp > 0; stp >>= 1)
+    if (__shfl(fr.incl, r + stp - 1) <= k) r += stp;
+  r = min(r, 63);
+  u = __shfl(fr.u0, r) + (k - __shfl(fr.excl, r));
+  v = fr.vrow0 + r;
+}
+
+// Footprint cell of work item t of a brick view.
+__device__ __forceinline__ void foot_cell(const DevBrickView& bvw, int t, int& ci, int& cj) {
+  ci = bvw.cf0 + t % bvw.tiles_x;
+  cj = bvw.cg0 + t / bvw.tiles_x;
+}
+
+// Footprint cell of wavefront w of work item t when work items are blocks of
+// blk_f x blk_g cells (wavefronts along f first).
+__device__ __forceinline__ void block_cell(const MarchArgs& a, const DevBrickView& bvw, int t, int w, int& ci,
+                                           int& cj) {
+  const int bi = t % bvw.blocks_x, bj = t / bvw.blocks_x;
+  ci = bvw.cf0 + bi * a.blk_f + w % a.blk_f;
+  cj = bvw.cg0 + bj * a.blk_g + w / a.blk_f;
+}
+
+__device__ __forceinline__ int find_bv(const MarchArgs& a, int tile) {
+  int lo = 0, hi = a.nbv - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.bv[mid].tile_begin <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 }  // namespace ring
 }  // namespace vr

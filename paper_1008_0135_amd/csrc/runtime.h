@@ -115,10 +115,13 @@ struct vr_ctx {
   int32_t tile_order = 2, tile_bw = 2, tile_bh = 4;
   int32_t ring_nslots = 0;    // forward ring march (plain orthographic): LDS slots per wavefront, 3 or 2; 0 = by occupancy
   int32_t foot = 1;           // forward ring march, parallel rays: footprint cells (1) or 8 x 8 pixel tiles (0)
-  int32_t ring_reg = 1;       // footprint cells, plain march: stage the layer after next in registers (1)
+  int32_t cells_waves = 16;   // cells march: wavefronts per compute unit at most (0 = as LDS allows)
+  int32_t ring_reg = 1;       // footprint cells, plain march: the layer after next staged in registers (1)
   double foot_rays = 60.0;    // footprint cells: mean pixels per cell (each holds at most 64 in one pass)
   int32_t foot_pad = 0;       // footprint cells: extra floats per window row (LDS bank spread)
-  int32_t foot_kmax = 4;      // footprint cells: window rows of at most this many 128-byte lines
+  int32_t foot_kmax = 2;      // footprint cells: window rows of at most this many 128-byte lines
+  int32_t foot_block = 0;     // blocks of cells per workgroup: -1 = by cost, 0 = off, 1 = foot_block_f x _g
+  int32_t foot_block_f = 0, foot_block_g = 0;
   bool debug_plan = false;    // print each view's march shape to stderr
   double persp_fit = 0.95;    // perspective ring march: fraction of tiles whose windows the slot holds
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)

@@ -173,7 +173,7 @@ struct DevBrickView {
   int32_t cf0;         // footprint cells: index of the first cell along f
   int64_t img_off;     // offset (in pixels) of the brick image in the image arena
   int32_t cg0;         // footprint cells: index of the first cell along g
-  int32_t pad;
+  int32_t blocks_x;    // blocks of footprint cells: blocks along f
   double fa0, fb0;     // footprint cells: cell coordinates (f / Tf, g / Tg) of pixel (0, 0)'s ray on the
                        // brick-local plane b = 0
 };
@@ -211,8 +211,11 @@ struct MarchArgs {
   int32_t mc;            // macrocell edge in cells; 0 = no macrocell skipping
   int32_t mcn[3];        // macrocells per axis
   int32_t ring_nslots;   // ring march: LDS slots per wavefront, 3 (one layer in flight while sampling) or 2
-  int32_t ring_reg;      // two slots: 1 = the layer after next travels through registers while a
-                         // layer is sampled (at most kRingRegLoads loads per lane per layer)
+  int32_t lds_floor;     // cells march: LDS bytes reserved per workgroup at least (caps how many
+                         // workgroups share a compute unit); 0 = what the windows need
+  int32_t ring_reg;      // footprint cells, two slots: 1 = the layer after next travels through
+                         // registers while a layer is sampled (k_march_cells; at most
+                         // kRingRegLoads loads per lane per layer)
   int32_t mask_axis;     // axis of the channel mask (2, or 1 in the permuted copy)
   const float* mask;     // channel weights along mask_axis (global indices), or null
   int32_t tile_order;    // ring march: tiles of a brick numbered along rows (0), down columns (1),
@@ -229,8 +232,11 @@ struct MarchArgs {
   int32_t foot_pad;
   double foot_Tf, foot_Tg;
   double fa_u, fa_v, fb_u, fb_v;  // cell coordinates per pixel step along u and v
-  unsigned int* ovf_count;        // cells of more than 64 pixels: count and work-item indices
-  int32_t* ovf_tiles;             // (room for every work item of the launch)
+  unsigned int* ovf_count;        // cells of more than 64 pixels: count and entries 8 t + w (work
+  int32_t* ovf_tiles;             // item t, wavefront w of a block; room for every cell of the launch)
+  // blocks of footprint cells: a workgroup of blk_f x blk_g wavefronts marches
+  // one block (a wavefront per cell) with one window per voxel layer; 0 = off
+  int32_t blk_f, blk_g;
 };
 
 // Cell coordinate (f / Tf or g / Tg) of pixel (u, v)'s ray on a brick's plane
@@ -315,6 +321,13 @@ hipError_t launch_zero(float4* img, int64_t n, hipStream_t s);
 // `wpb` wavefronts per workgroup (1, 2 or 4).
 hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s);
 size_t ring_lds_bytes(const MarchArgs& a, int wpb);
+// footprint cells: a wavefront per cell, windows staged through registers
+// (the host keeps a lane's offset inside a window's rows below 4 GiB), or
+// blocks of a.blk_f x a.blk_g cells per workgroup
+hipError_t launch_march_cells(const MarchArgs& a, int wpb, hipStream_t s);
+size_t cells_lds_bytes(const MarchArgs& a, int wpb);
+hipError_t launch_march_block(const MarchArgs& a, hipStream_t s);
+size_t block_lds_bytes(const MarchArgs& a);
 // Differentiable forward on the ring layout (whole volume): also stores the
 // per-group checkpoints of sa (layer groups of sa.K cell layers).
 hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wpb, hipStream_t s);

@@ -244,12 +244,18 @@ def test_c2_full_size_strided_rays(ctx):
 def _ctx_with_march(mode):
     """A context with one march forced; "ring2" / "ring3": the ring march with
     two / three LDS slots per wavefront ("ring2": the layer after next staged in
-    registers, "ring2mem": loaded straight into LDS after a layer is done)."""
+    registers, "ring2reg2": the next two layers, "ring2mem": loaded straight into
+    LDS after a layer is done); "blkFxG": workgroups marching blocks of F x G
+    footprint cells with one window per layer ("blk0": a wavefront per cell)."""
     import os
     if mode in ("ring2", "ring3"):
         env = {"VR_MARCH": "ring", "VR_RING_SLOTS": mode[-1]}
     elif mode == "ring2mem":  # two slots, the layer after next loaded straight into LDS
         env = {"VR_MARCH": "ring", "VR_RING_SLOTS": "2", "VR_RING_REG": "0"}
+    elif mode == "ring2reg2":  # two slots, the next two layers staged in registers
+        env = {"VR_MARCH": "ring", "VR_RING_SLOTS": "2", "VR_RING_REG": "2"}
+    elif mode.startswith("blk"):  # blocks of footprint cells per workgroup ("blk0": a wavefront per cell)
+        env = {"VR_MARCH": "ring", "VR_FOOT_BLOCK": mode[3:]}
     elif mode.startswith("ring:"):  # the ring march with tiles numbered in another order
         env = {"VR_MARCH": "ring", "VR_TILE_ORDER": mode[5:]}
     else:
@@ -277,8 +283,9 @@ def test_marches_identical():
     views = synth.random_views(5, 28) + [synth.rot_axis(2, 90.0), synth.rot_axis(2, 87.0) @ synth.rot_axis(1, 3.0)]
     imgs = {}
     layouts = {"grid": vr.grid_spec((48, 64, 80)), "mat": vr.grid_spec((48, 64, 80), materialize=True),
-               "kd": vr.kd_spec(7), "whole": None}
-    for mode in ("gather", "slab", "ring", "ring2", "ring2mem", "ring3"):
+               "kd": vr.kd_spec(7), "whole": None, "wide": vr.grid_spec((128, 72, 88))}
+    for mode in ("gather", "slab", "ring", "ring2", "ring2reg2", "ring2mem", "ring3", "blk0", "blk2x2", "blk8x1",
+                 "blk1x4"):
         _say(f"  march {mode}")
         c = _ctx_with_march(mode)
         h = _upload(c, vol)
@@ -298,7 +305,7 @@ def test_marches_identical():
     for name in layouts:
         for W in (96, 333):
             a = imgs[("gather", name, W)]
-            for mode in ("slab", "ring", "ring2", "ring2mem", "ring3"):
+            for mode in ("slab", "ring", "ring2", "ring2reg2", "ring2mem", "ring3", "blk0", "blk2x2", "blk8x1", "blk1x4"):
                 b = imgs[(mode, name, W)]
                 assert np.array_equal(a, b), (mode, name, W, float(np.abs(a - b).max()))
     mn, mx = float(vol.min()), float(vol.max())
