@@ -412,7 +412,9 @@ def main():
     ap.add_argument("--oracle-seconds", type=float, default=15.0)
     ap.add_argument("--no-oracle", action="store_true")
     ap.add_argument("--per-view", action="store_true", help="print each view's march time to stderr")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and forward+backward legs")
+    ap.add_argument("--no-extras", action="store_true", help="skip every leg besides the headline march")
+    ap.add_argument("--legs", default="variants,tf_suppress,batched,fwd_bwd,c2",
+                    help="comma-separated extra legs to run (variants = perspective, MIP, whole-ray termination)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -583,13 +585,17 @@ def main():
         },
     }
 
-    if not args.no_extras:
+    legs = set() if args.no_extras else set(args.legs.split(","))
+    if "variants" in legs:
         result.update(bench_variants(ctx, h, (n1, n2, n3), views_R, W, H, stream))
+    if "tf_suppress" in legs:
         result["tf_suppress"] = bench_tf_suppress(ctx, h, (n1, n2, n3), views_R, W, H, vmin, vmax, stream)
+    if "batched" in legs:
         result["batched"] = bench_batched(ctx, stream)
+    if "fwd_bwd" in legs:
         result["fwd_bwd"] = bench_fwd_bwd(ctx, stream)
-        if args.config == "C3":
-            result["c2"] = bench_c2(ctx, stream)
+    if "c2" in legs and args.config == "C3":
+        result["c2"] = bench_c2(ctx, stream)
 
     if not args.no_oracle:
         import oracle

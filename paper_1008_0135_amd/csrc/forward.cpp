@@ -355,6 +355,8 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
             a.ring_nslots = 2;
           }
         }
+        // the layer after next staged in registers (emission-absorption)
+        if (ring && a.ring_nslots == 2 && !a.mip && a.mc == 0 && !a.mask && ctx->ring_reg) a.ring_reg = 1;
       } else {
         int32_t waves3 = 0;
         ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,

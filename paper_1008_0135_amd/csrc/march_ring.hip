@@ -57,11 +57,17 @@ constexpr int kSlotsMax = 3;
 // sa.K cell layers of the tile (in marching order), each ray's transmittance
 // and sample cursor at the group's start, and the samples applied per ray.
 // MIP: maximum intensity projection (no table, no skipping, no saving).
-template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false, bool MASK = false>
+// REG (two slots, perspective views): the window of the layer after next is
+// loaded into registers while the current cell layer is sampled and written
+// over the finished layer afterwards, for tiles whose window takes at most
+// kRingRegLoads loads per lane (the others load straight into LDS), so every
+// wavefront keeps a layer in flight without a third slot.
+template <bool ESS, bool SAVE, bool MIP, bool PERSP, bool TWO = false, bool MASK = false, bool REG = false>
 __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   static_assert(!(PERSP && SAVE), "the checkpointing forward is orthographic");
   static_assert(!TWO || !(ESS || SAVE), "two slots: the plain march");
   static_assert(!(MASK && (SAVE || TWO)), "the channel mask: three-slot forward marches");
+  static_assert(!REG || TWO, "registers stage the third layer of a two-slot ring");
   constexpr int kSlots = TWO ? 2 : 3;
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
@@ -468,7 +474,81 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   // cell layer c_k = Lbeg +- k reads V_k and V_{k+1}
   const int vstep = up ? 1 : -1;
   const int V0 = up ? Lbeg : Lbeg + 1;
-  if constexpr (!ESS) {
+  if (REG && nload <= kRingRegLoads) {
+    // two LDS slots; V_{k+2} waits in registers while c_k is sampled
+    const float fclo = (float)cloB, fchi = (float)chiB;
+    // every lane of a load instruction reads a row of the window (lanes past
+    // the instruction's rows, and rows past the window, re-read its last row)
+    // and only lanes holding a row of the window write it to LDS
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    v4f rr[kRingRegLoads];
+    const int rl_c = min(rl, R - 1), c4_c = lane_on ? c4l : 0;
+    auto rload = [&](int V, const Window& w) {
+      gfloat* gb = gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0) + 4 * c4_c;
+#pragma unroll
+      for (int i = 0; i < kRingRegLoads; ++i)
+        if (i < nload)
+          rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (int64_t)min(i * R + rl_c, NG - 1) * sG);
+    };
+    auto rstore = [&](float* sdst) {
+      v4f* l = (v4f*)(sdst + 4 * lane);
+#pragma unroll
+      for (int i = 0; i < kRingRegLoads; ++i)
+        if (i < nload && lane_on && i * R + rl < NG) l[i * R * (pitch >> 2)] = rr[i];
+    };
+    Window w0 = window(V0), w1 = window(V0 + vstep), w2;
+    rload(V0, w0);
+    rstore(s_ring);
+    rload(V0 + vstep, w1);
+    rstore(s_ring + slot);
+    if (nlay > 1) {
+      w2 = window(V0 + 2 * vstep);
+      rload(V0 + 2 * vstep, w2);
+    }
+    int s0 = 0;  // slot of V_k (V_{k+1} is in the other)
+    for (int k = 0; k < nlay; ++k) {
+      const int c = up ? Lbeg + k : Lbeg - k;
+      const Window& wl = up ? w0 : w1;
+      const Window& wu = up ? w1 : w0;
+      const int sl = up ? s0 : s0 ^ 1, su = up ? s0 ^ 1 : s0;
+      const float* baseL = s_ring + (sl * slot - wl.g0 * pitch - wl.f0);
+      const int dU = (su * slot - wu.g0 * pitch - wu.f0) - (sl * slot - wl.g0 * pitch - wl.f0);
+      while (!done) {
+        const SamplePos q = sample_pos(j, px, py, pz, sx, sy, sz);
+        const int ib = (int)floorf(__builtin_amdgcn_fmed3f(by ? q.y : q.z, fclo, fchi));
+        if (ib != c) break;
+        const Cell cl = cell_of(q, br);
+        const int ig = by ? cl.iz : cl.iy;
+        const float* p = baseL + (__mul24(ig, pitch) + cl.ix);
+        const float* pu = p + dU;
+        const float l00 = p[0], l01 = p[1], l10 = p[pitch], l11 = p[pitch + 1];
+        const float u00 = pu[0], u01 = pu[1], u10 = pu[pitch], u11 = pu[pitch + 1];
+        const float val = by ? trilerp(l00, l01, u00, u01, l10, l11, u10, u11, cl)
+                             : trilerp(l00, l01, l10, l11, u00, u01, u10, u11, cl);
+        ++j;
+        if (MIP) {
+          const float s = norm_value(val, a.vmin, a.inv_range);
+          mx = fmaxf(mx, s);
+          if (j >= cnt || mx >= 1.f) done = true;
+        } else {
+          const Classified kk = classify(val, a.vmin, a.inv_range, a.M, s_tf);
+          accumulate(kk, Cr, Cg, Cb, T);
+          if (j >= cnt || 1.f - T >= a.tau) done = true;
+        }
+      }
+      if (__all(done)) break;
+      if (k + 1 < nlay) {
+        rstore(s_ring + s0 * slot);  // V_{k+2} replaces V_k (same wavefront: LDS order holds)
+        w0 = w1;
+        w1 = w2;
+        if (k + 2 < nlay) {
+          w2 = window(V0 + (k + 3) * vstep);
+          rload(V0 + (k + 3) * vstep, w2);
+        }
+      }
+      s0 ^= 1;
+    }
+  } else if constexpr (!ESS) {
     const float fclo = (float)cloB, fchi = (float)chiB;
     Window w0 = window(V0), w1 = window(V0 + vstep);
     issue(V0, w0, s_ring);
@@ -779,7 +859,9 @@ static hipError_t launch_march_ring_main(const MarchArgs& a, int wpb, hipStream_
     return hipGetLastError();
   }
   if (a.cam.persp) {
-    if (a.mip && a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, true, true, true>), g, b, lds, s, a, none);
+    if (!a.mip && a.mc == 0 && a.ring_nslots == 2 && a.ring_reg)
+      hipLaunchKernelGGL((k_march_ring<false, false, false, true, true, false, true>), g, b, lds, s, a, none);
+    else if (a.mip && a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, true, true, true>), g, b, lds, s, a, none);
     else if (a.mip) hipLaunchKernelGGL((k_march_ring<false, false, true, true>), g, b, lds, s, a, none);
     else if (a.mc > 0) hipLaunchKernelGGL((k_march_ring<true, false, false, true>), g, b, lds, s, a, none);
     else if (a.ring_nslots == 2) hipLaunchKernelGGL((k_march_ring<false, false, false, true, true>), g, b, lds, s, a, none);
