@@ -371,7 +371,7 @@ def counter_traffic(config):
     1 GiB copy), or None when there is none for this workload or the kernel's
     sources changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_march_ring_c3_counters.txt")
+    path = os.path.join(ROOT, "profiles", "k_march_cells_c3_counters.txt")
     if config != "C3" or not os.path.exists(path):
         return None
     kv = {}
@@ -574,10 +574,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic[0] if traffic else None,
             "traffic_source": "rocprofv3 FETCH_SIZE + WRITE_SIZE per dispatch (L2-miss traffic, scaled by a "
-                              "plain copy), read from profiles/k_march_ring_c3_counters.txt when the kernel and "
+                              "plain copy), read from profiles/k_march_cells_c3_counters.txt when the kernel and "
                               "planning sources hash to the values recorded there, else null",
             "l2_hit_rate": round(traffic[1], 4) if traffic and traffic[1] is not None else None,
-            "kernel": "k_march_ring",
+            "kernel": "k_march_cells",
             "alg_bytes_per_launch": int(alg_bytes),
             "measured_stream_peak": round(peak_meas, 1),
             "frac_of_measured_peak": round(achieved / peak_meas, 4),
