@@ -365,6 +365,30 @@ def brick_transparent(bmin, bmax, tf, vmin, vmax):
     return bool((tf[i0:i1 + 1, 3] == 0).all())
 
 
+def traffic_model(config, twin):
+    """Bytes the footprint-cell march's window loads request per launch on the
+    config's views, from the host plan (vr_plan_cells; no GPU): the rendered
+    bricks' own voxels, the line-granular union of the windows (ghost layers,
+    halo beyond the bricks, cells straddling their sides), the sum of the
+    windows (halo shared by neighbouring cells), the same in 64-byte segments
+    and 128-byte lines (partly used lines), and each with the window columns
+    clipped to the brick's reach as the kernel loads them."""
+    cfg = synth.CONFIGS[config]
+    W, H = cfg["image"]
+    spec = vr.grid_spec(cfg["bricks"], twin=twin)
+    keys = ["own_bytes", "union_bytes", "window_bytes", "segment_bytes", "line_bytes", "clipped_window_bytes",
+            "clipped_segment_bytes", "clipped_line_bytes"]
+    tot = {k: 0.0 for k in keys}
+    views = synth.random_views(cfg["nviews"], cfg["view_seed"])
+    for R in views:
+        t = vr.vr_plan_cells(cfg["dims"], spec, vr.make_view(R, W, H))
+        for k in keys:
+            tot[k] += getattr(t, k)
+    n = len(views)
+    return {"workload": config, "views": n, "per_launch_gb": {k[:-6]: round(tot[k] / n / 1e9, 3) for k in keys},
+            "over_own": {k[:-6]: round(tot[k] / tot["own_bytes"], 4) for k in keys}}
+
+
 def counter_traffic(config):
     """HBM bytes per march launch from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter reads for a plain
@@ -415,6 +439,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip every leg besides the headline march")
     ap.add_argument("--legs", default="variants,tf_suppress,batched,fwd_bwd,c2",
                     help="comma-separated extra legs to run (variants = perspective, MIP, whole-ray termination)")
+    ap.add_argument("--traffic-model", action="store_true",
+                    help="only print the footprint-cell march's window-traffic model for the config's views "
+                         "(host planning, no GPU)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only run a device-to-device copy of this many GiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -423,6 +450,9 @@ def main():
               "(multi-GPU sort-last compositing is a design, not an implementation)", file=sys.stderr)
         sys.exit(2)
 
+    if args.traffic_model:
+        print(json.dumps(traffic_model(args.config, bool(args.twin))))
+        return
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)

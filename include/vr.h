@@ -483,6 +483,48 @@ int vr_partition(const int64_t dims[3], const vr_brick_spec *spec, int32_t *nb, 
  */
 int vr_count_samples(const int64_t dims[3], const vr_view *view, double step, int64_t *nominal);
 
+/*
+ * Window traffic of the footprint-cell march for one parallel view (a model
+ * from the plan, no GPU use).  The march of Sec. 2.4 reads every voxel of a
+ * rendered brick once at best (own_bytes); the cell march loads, per cell
+ * and voxel layer, a window of rows along axis 1 that its rays' samples
+ * between two neighbouring layers can touch.  Every cell is taken to march
+ * every layer its rays cross inside the brick (no early termination), with
+ * the windows placed and clamped as the kernel places them.  The terms:
+ *   union_bytes   128-byte lines that any window of a brick touches, per
+ *                 voxel layer and row (the brick with its ghost layers and the
+ *                 halo beyond its sides: what perfect reuse would fetch);
+ *   window_bytes  sum over cells and loaded layers of rows x row floats x 4
+ *                 (adds the halo that neighbouring cells share);
+ *   line_bytes    the same rows counted in whole 128-byte lines (adds the
+ *                 partly used lines at the rows' ends): the traffic with no
+ *                 reuse between cells.
+ * rays: mean pixels per cell (0: the library's default), kmax: window rows of
+ * at most this many 128-byte lines (0: default), tf_entries: table entries
+ * (they share the compute unit's LDS with the windows; 0: 256).  Bricks are
+ * those of spec over a volume of size dims, every brick with a non-empty
+ * rectangle counted (no transfer-function culling); with spec->twin set, a
+ * view looking mostly along axis 1 is planned on the permuted copy, as it is
+ * rendered.  Errors: VR_EINVAL (bad arguments, or a perspective view), and
+ * VR_EUNSUPPORTED when the view has no slab axis for the cell march.
+ */
+typedef struct {
+  double own_bytes, union_bytes, window_bytes, line_bytes;
+  double segment_bytes;          /* the rows of line_bytes counted in 64-byte segments */
+  double clipped_window_bytes, clipped_line_bytes, clipped_segment_bytes;  /* window rows clipped to the
+                                                          brick's voxels and one more on each side along axis 1
+                                                          (as the march loads them) */
+  double cells, cell_layers;     /* cells with samples; voxel layers loaded over all cells */
+  double rays_per_cell;          /* mean pixels per cell of the chosen shape */
+  double Tf, Tg;                 /* cell size on the slab plane, voxels */
+  int32_t axis;                  /* slab axis (2 or 3, of the volume rendered: the copy's for a permuted view) */
+  int32_t row_floats, rows;      /* window row length (floats, a multiple of 4) and rows per window */
+  int32_t twin;                  /* 1: planned on the permuted copy */
+} vr_cell_traffic;
+
+int vr_plan_cells(const int64_t dims[3], const vr_brick_spec *spec, const vr_view *view, double rays, int32_t kmax,
+                  int32_t tf_entries, vr_cell_traffic *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,14 @@ class vr_tune_result(C.Structure):
                 ("lds_budget", C.c_int32), ("march_mode", C.c_int32)]
 
 
+class vr_cell_traffic(C.Structure):
+    _fields_ = [("own_bytes", C.c_double), ("union_bytes", C.c_double), ("window_bytes", C.c_double),
+                ("line_bytes", C.c_double), ("segment_bytes", C.c_double), ("clipped_window_bytes", C.c_double),
+                ("clipped_line_bytes", C.c_double), ("clipped_segment_bytes", C.c_double), ("cells", C.c_double), ("cell_layers", C.c_double),
+                ("rays_per_cell", C.c_double), ("Tf", C.c_double), ("Tg", C.c_double), ("axis", C.c_int32),
+                ("row_floats", C.c_int32), ("rows", C.c_int32), ("twin", C.c_int32)]
+
+
 _P = C.c_void_p
 _I = C.c_int
 _I32 = C.c_int32
@@ -122,6 +130,7 @@ _SIGS = {
     "vr_plan_view": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "vr_count_samples": (_I, [_P, _P, _D, _P]),
     "vr_partition": (_I, [_P, _P, _P, _P]),
+    "vr_plan_cells": (_I, [_P, _P, _P, _D, _I32, _I32, _P]),
 }
 
 _lib = None
@@ -446,6 +455,16 @@ def vr_partition(dims, spec):
     arr = (vr_brick_desc * max(1, nb.value))()
     _check(lib().vr_partition(d, C.byref(spec), C.byref(nb), arr), "vr_partition")
     return [arr[i] for i in range(nb.value)]
+
+
+def vr_plan_cells(dims, spec, view, rays=0.0, kmax=0, tf_entries=0):
+    """Window-traffic model of the footprint-cell march for one parallel view
+    (host only); returns a vr_cell_traffic."""
+    d = (C.c_int64 * 3)(*[int(x) for x in dims])
+    out = vr_cell_traffic()
+    _check(lib().vr_plan_cells(d, C.byref(spec), C.byref(view), float(rays), int(kmax), int(tf_entries),
+                               C.byref(out)), "vr_plan_cells")
+    return out
 
 
 def vr_count_samples(dims, view, step=0.5):

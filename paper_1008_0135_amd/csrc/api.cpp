@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "forward.h"
 #include "plan.h"
 #include "runtime.h"
 #include "vr_internal.h"
@@ -377,6 +378,12 @@ int vr_create(int device, vr_ctx** out) {
   }
   if (const char* m = std::getenv("VR_FOOT_PAD")) ctx->foot_pad = std::max(0, std::min(32, std::atoi(m)));
   if (const char* m = std::getenv("VR_FOOT_KMAX")) ctx->foot_kmax = std::max(1, std::min(4, std::atoi(m)));
+  if (const char* m = std::getenv("VR_FOOT_CLIP")) ctx->foot_clip = std::atoi(m) != 0 ? 1 : 0;
+  if (const char* m = std::getenv("VR_PERSP_CLASSES")) ctx->persp_classes = std::max(1, std::min(4, std::atoi(m)));
+  if (const char* m = std::getenv("VR_CELLS_WPB")) {
+    const int k = std::atoi(m);
+    ctx->cells_wpb = (k == 1 || k == 2 || k == 4) ? k : 0;
+  }
   if (const char* m = std::getenv("VR_DEBUG_PLAN")) ctx->debug_plan = std::atoi(m) != 0;
   if (const char* m = std::getenv("VR_PERSP_FIT")) {
     const double f = std::atof(m);
@@ -1050,6 +1057,77 @@ int vr_count_samples(const int64_t dims[3], const vr_view* view, double step, in
   Camera cam;
   make_camera(*view, dims, cam);
   *nominal = count_samples(cam, dims, step);
+  return VR_OK;
+}
+
+int vr_plan_cells(const int64_t dims[3], const vr_brick_spec* spec, const vr_view* view, double rays, int32_t kmax,
+                  int32_t tf_entries, vr_cell_traffic* out) {
+  clear_error();
+  if (!dims || !spec || !view || !out) return fail(VR_EINVAL, "dims, spec, view and out must be non-NULL");
+  VR_TRY(check_dims(dims[0], dims[1], dims[2]));
+  VR_TRY(check_view(view, dims));
+  if (view->eye_dist > 0.0) return fail(VR_EINVAL, "the cell march renders parallel views only");
+  if (!(rays >= 0.0) || rays > 128.0) return fail(VR_EINVAL, "rays must be in [0, 128] (0: default)");
+  if (kmax < 0 || kmax > 4) return fail(VR_EINVAL, "kmax must be in [0, 4] (0: default)");
+  if (tf_entries < 0 || tf_entries > 4096) return fail(VR_EINVAL, "tf_entries must be in [0, 4096] (0: 256)");
+  Partition P;
+  std::string err;
+  if (spec->mode == VR_BRICK_GRID) {
+    if (!make_grid(dims, spec->size, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else if (spec->mode == VR_BRICK_LONGEST_AXIS) {
+    if (!make_kd(dims, spec->nparts, P, err)) return fail(VR_EINVAL, "%s", err.c_str());
+  } else {
+    return fail(VR_EINVAL, "unknown brick mode %d", spec->mode);
+  }
+  vr_ctx defaults;  // the library's defaults (no device state is made)
+  vr_view v = *view;
+  int64_t n[3] = {dims[0], dims[1], dims[2]};
+  // a view mostly along axis 1 is rendered from the copy with axes (2, 3, 1)
+  const bool tw = spec->twin && std::fabs(v.R[6]) > std::max(std::fabs(v.R[7]), std::fabs(v.R[8]));
+  if (tw) {
+    for (int r = 0; r < 3; r++) {
+      const double x = v.R[3 * r], y = v.R[3 * r + 1], z = v.R[3 * r + 2];
+      v.R[3 * r] = y;
+      v.R[3 * r + 1] = z;
+      v.R[3 * r + 2] = x;
+    }
+    n[0] = dims[1];
+    n[1] = dims[2];
+    n[2] = dims[0];
+    Partition Q;
+    permute_partition(P, n, Q);
+    P = Q;
+  }
+  Camera cam;
+  make_camera(v, n, cam);
+  FootShape fs;
+  if (!pick_foot(cam, n, tf_entries > 0 ? tf_entries : 256, true, defaults.ring_reg > 0, defaults.ring_nslots,
+                 rays > 0.0 ? rays : defaults.foot_rays, defaults.foot_pad, kmax > 0 ? kmax : defaults.foot_kmax, fs))
+    return fail(VR_EUNSUPPORTED, "no slab axis suits the cell march for this view");
+  FootTraffic t;
+  for (const Box& b : P.boxes) {
+    const Rect r = brick_rect(cam, b);
+    if (r.w <= 0 || r.h <= 0) continue;
+    foot_traffic(cam, fs, b, n, t);
+  }
+  std::memset(out, 0, sizeof *out);
+  out->own_bytes = t.own;
+  out->union_bytes = t.uni;
+  out->window_bytes = t.win;
+  out->line_bytes = t.line;
+  out->segment_bytes = t.seg;
+  out->clipped_window_bytes = t.clip_win;
+  out->clipped_line_bytes = t.clip_line;
+  out->clipped_segment_bytes = t.clip_seg;
+  out->cells = t.cells;
+  out->cell_layers = t.layers;
+  out->rays_per_cell = fs.rays;
+  out->Tf = fs.Tf;
+  out->Tg = fs.Tg;
+  out->axis = fs.axis + 1;
+  out->row_floats = (fs.nf + 3) & ~3;
+  out->rows = fs.ng;
+  out->twin = tw ? 1 : 0;
   return VR_OK;
 }
 

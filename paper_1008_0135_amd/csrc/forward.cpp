@@ -32,6 +32,18 @@ constexpr int32_t kLdsPerCu = 160 * 1024;
 
 }  // namespace
 
+bool pick_foot(const Camera& cam, const int64_t n[3], int32_t M, bool plain, bool reg_on, int32_t nslots,
+               double rays, int32_t pad, int32_t kmax, FootShape& fs) {
+  // register-staged cells: a lane's offset inside a window's rows (at most
+  // kRingRegLoads instructions of up to 16 rows) must stay below 4 GiB
+  const int64_t row_stride = std::max(n[0], n[0] * n[1]);
+  const bool reg = plain && reg_on && nslots != 3 && ((int64_t)kRingRegLoads * 16 * row_stride + 256) * 4 < ((int64_t)1 << 32);
+  const bool two = rays > 64.0;  // two pixels per lane: half the wavefronts, twice the window loads
+  const int32_t rw = two ? kRingRegWaves / 2 : kRingRegWaves;
+  return choose_foot(cam, kRingCap, M, kRingMaxWaves, reg ? rw : kRingWantWaves, rays, plain ? nslots : 3, fs, pad,
+                     kmax, reg ? rw : 0, two ? 2 * kRingRegLoads : kRingRegLoads);
+}
+
 // Plan one view of a bricked volume: rectangles, culling (empty rectangle or
 // transparent brick), launch order (brick index order, which keeps
 // neighbouring bricks together), arena offsets and the front-to-back layers.
@@ -148,6 +160,70 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       vp.pixels = (int64_t)W * H;
     }
   }
+  // perspective views on the ring march: rays from the eye spread with depth,
+  // so the 8 x 8 tiles of far bricks need windows about twice those of near
+  // ones, and one slot sized for nearly all tiles leaves the near bricks at a
+  // fraction of the wavefronts their windows allow.  Bricks are grouped into
+  // classes of similar window (about equal tile counts), launched one class
+  // at a time with a slot of its own.
+  for (int32_t v = 0; v < nviews; v++) {
+    ViewPlan& vp = plans[v];
+    vp.class_begin.clear();
+    vp.class_tiles.clear();
+    const int32_t ncls = ctx->persp_classes;
+    if (!bricked || global || extras || !cams[v].persp || !(mode == 0 || mode == 3) || tw != 8 || ncls < 2 ||
+        vp.bv.size() < (size_t)(2 * ncls))
+      continue;
+    std::vector<std::pair<double, int32_t>> est;  // (worst sampled window, bv index)
+    int64_t total = 0;
+    for (int32_t i = 0; i < (int32_t)vp.bv.size(); i++) {
+      const DevBrickView& b = vp.bv[i];
+      TileRegion r;
+      for (int k = 0; k < 3; k++) {
+        r.lo[k] = vol->part.boxes[b.brick].lo[k];
+        r.hi[k] = vol->part.boxes[b.brick].hi[k];
+      }
+      r.x0 = b.x0;
+      r.y0 = b.y0;
+      r.w = b.w;
+      r.h = b.h;
+      est.emplace_back(persp_region_window(cams[v], r), i);
+      total += (int64_t)b.tiles_x * ((b.h + th - 1) / th);
+    }
+    std::stable_sort(est.begin(), est.end(),
+                     [](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
+                       return x.first < y.first;
+                     });
+    // class boundaries at about equal tile counts; within a class, brick order
+    std::vector<int32_t> cls(vp.bv.size(), 0);
+    int64_t acc = 0;
+    for (const auto& e : est) {
+      const DevBrickView& b = vp.bv[e.second];
+      cls[e.second] = (int32_t)std::min<int64_t>(ncls - 1, acc * ncls / std::max<int64_t>(1, total));
+      acc += (int64_t)b.tiles_x * ((b.h + th - 1) / th);
+    }
+    std::vector<DevBrickView> nbv;
+    std::vector<int32_t> where(vp.bv.size(), -1);
+    nbv.reserve(vp.bv.size());
+    for (int32_t c = 0; c < ncls; c++) {
+      const int32_t first = (int32_t)nbv.size();
+      int32_t t = 0;
+      for (int32_t i = 0; i < (int32_t)vp.bv.size(); i++)
+        if (cls[i] == c) {
+          DevBrickView b = vp.bv[i];
+          b.tile_begin = t;
+          t += b.tiles_x * ((b.h + th - 1) / th);
+          where[i] = (int32_t)nbv.size();
+          nbv.push_back(b);
+        }
+      if (t == 0) continue;
+      vp.class_begin.push_back(first);
+      vp.class_tiles.push_back(t);
+    }
+    vp.class_begin.push_back((int32_t)nbv.size());
+    for (int32_t& l : vp.layers_order) l = where[l];
+    vp.bv.swap(nbv);
+  }
   // parallel rays on the ring march: footprint cells instead of 8 x 8 pixel
   // tiles (the cell counts replace the tile counts of the plan)
   const bool plain_ring = base.mc == 0 && !base.mask;
@@ -155,14 +231,8 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     ViewPlan& vp = plans[v];
     if (extras || cams[v].persp || !ctx->foot || !(mode == 0 || mode == 3) || tw != 8) continue;
     FootShape fs;
-    // register-staged cells: a lane's offset inside a window's rows (at most
-    // kRingRegLoads instructions of up to 16 rows) must stay below 4 GiB
-    const int64_t row_stride = std::max(vol->n[0], vol->n[0] * vol->n[1]);
-    const bool reg = plain_ring && ctx->ring_reg > 0 && ctx->ring_nslots != 3 &&
-                     ((int64_t)kRingRegLoads * 16 * row_stride + 256) * 4 < ((int64_t)1 << 32);
-    if (!choose_foot(cams[v], kRingCap, base.M, kRingMaxWaves, reg ? kRingRegWaves : kRingWantWaves, ctx->foot_rays,
-                     plain_ring ? ctx->ring_nslots : 3, fs, ctx->foot_pad, ctx->foot_kmax, reg ? kRingRegWaves : 0,
-                     kRingRegLoads))
+    if (!pick_foot(cams[v], vol->n, base.M, plain_ring, ctx->ring_reg > 0, ctx->ring_nslots, ctx->foot_rays,
+                   ctx->foot_pad, ctx->foot_kmax, fs))
       continue;
     Box whole;
     for (int i = 0; i < 3; i++) {
@@ -266,6 +336,44 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
     VR_TRY(aux_fork(ctx, s));
   }
+  // LDS slot, slots per wavefront and register staging of the perspective
+  // ring march for the bricks bv[first .. first + count) of view v; false
+  // when the windows do not fit (gather march)
+  auto persp_shape = [&](int32_t v, int32_t first, int32_t count, MarchArgs& a, int& wpb) {
+    const ViewPlan& vp = plans[v];
+    std::vector<TileRegion> regs;
+    for (int32_t k = first; k < first + count; k++) {
+      const DevBrickView& b = vp.bv[k];
+      TileRegion r;
+      for (int i = 0; i < 3; i++) {
+        r.lo[i] = bricked ? vol->part.boxes[b.brick].lo[i] : 0;
+        r.hi[i] = bricked ? vol->part.boxes[b.brick].hi[i] : vol->n[i] - 1;
+      }
+      r.x0 = b.x0;
+      r.y0 = b.y0;
+      r.w = b.w;
+      r.h = b.h;
+      regs.push_back(r);
+    }
+    a.slab_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
+    const bool ok = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, wpb,
+                                      ctx->persp_fit);
+    a.ring_nslots = 3;
+    a.ring_reg = 0;
+    // two slots wherever they fit more wavefronts (as for parallel rays)
+    if (ok && a.mc == 0 && !a.mask && ctx->ring_nslots != 3) {
+      int32_t waves3 = 0, waves2 = 0;
+      ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves3, 3);
+      const int32_t wpb2 = ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves2, 2);
+      if (ctx->ring_nslots == 2 || waves2 > waves3) {
+        wpb = wpb2;
+        a.ring_nslots = 2;
+      }
+    }
+    // the layer after next staged in registers (emission-absorption)
+    if (ok && a.ring_nslots == 2 && !a.mip && a.mc == 0 && !a.mask && ctx->ring_reg) a.ring_reg = 1;
+    return ok;
+  };
   for (int32_t v = 0; v < nviews; v++) {
     const ViewPlan& vp = plans[v];
     MarchArgs a = base;
@@ -292,14 +400,15 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       a.ring_slot = fs.slot;
       a.ring_nslots = fs.nslots;
       a.ring_reg = fs.reg;
+      a.foot_clip = ctx->foot_clip;
+      ring_wpb = fs.reg && ctx->cells_wpb > 0 ? ctx->cells_wpb : fs.wpb;
       if (fs.reg && ctx->cells_waves > 0) {
         // at most cells_waves wavefronts per compute unit: reserve LDS so that
         // one workgroup more would not fit (more wavefronts ran slower: their
         // windows crowd each other out of the caches)
-        const int32_t nwg = std::max(1, ctx->cells_waves / std::max(1, fs.wpb));
+        const int32_t nwg = std::max(1, ctx->cells_waves / ring_wpb);
         a.lds_floor = kLdsPerCu / (nwg + 1) + 1024;
       }
-      ring_wpb = fs.wpb;
       a.foot_nf = fs.nf;
       a.foot_ng = fs.ng;
       a.foot_Tf = fs.Tf;
@@ -328,35 +437,11 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       }
     } else if (!extras && (mode == 0 || mode == 3) && a.tile_w == 8) {
       if (cams[v].persp) {
-        std::vector<TileRegion> regs;
-        for (const DevBrickView& b : vp.bv) {
-          TileRegion r;
-          for (int i = 0; i < 3; i++) {
-            r.lo[i] = bricked ? vol->part.boxes[b.brick].lo[i] : 0;
-            r.hi[i] = bricked ? vol->part.boxes[b.brick].hi[i] : vol->n[i] - 1;
-          }
-          r.x0 = b.x0;
-          r.y0 = b.y0;
-          r.w = b.w;
-          r.h = b.h;
-          regs.push_back(r);
+        if (vp.class_begin.empty()) {
+          ring = persp_shape(v, 0, (int32_t)vp.bv.size(), a, ring_wpb);
+        } else {
+          ring = true;  // shapes per class at the launch
         }
-        a.slab_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
-        ring = choose_ring_persp(cams[v], regs, kRingCap, a.M, kRingMaxWaves, kRingMinWaves, a.ring_slot, ring_wpb,
-                                 ctx->persp_fit);
-        a.ring_nslots = 3;
-        // two slots wherever they fit more wavefronts (as for parallel rays)
-        if (ring && a.mc == 0 && !a.mask && ctx->ring_nslots != 3) {
-          int32_t waves3 = 0, waves2 = 0;
-          ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves3, 3);
-          const int32_t wpb2 = ring_waves_per_block(a.ring_slot, a.M, kRingMaxWaves, &waves2, 2);
-          if (ctx->ring_nslots == 2 || waves2 > waves3) {
-            ring_wpb = wpb2;
-            a.ring_nslots = 2;
-          }
-        }
-        // the layer after next staged in registers (emission-absorption)
-        if (ring && a.ring_nslots == 2 && !a.mip && a.mc == 0 && !a.mask && ctx->ring_reg) a.ring_reg = 1;
       } else {
         int32_t waves3 = 0;
         ring = choose_ring(cams[v], kRingCap, a.M, kRingMaxWaves, kRingWantWaves, kRingMinWaves, a.slab_axis,
@@ -418,8 +503,26 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       continue;
     }
     VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
-    VR_HIP(extras ? extras->launch(a, s)
-                  : (ring ? launch_march_ring(a, ring_wpb, s) : (lds ? launch_march_lds(a, s) : launch_march(a, s))));
+    if (!vp.class_begin.empty()) {
+      // perspective classes: one launch each, with the class's own slot
+      const DevBrickView* cbv = a.bv;
+      for (size_t c = 0; c + 1 < vp.class_begin.size(); c++) {
+        MarchArgs ac = a;
+        int cwpb = 4;
+        const int32_t first = vp.class_begin[c], count = vp.class_begin[c + 1] - first;
+        const bool cring = persp_shape(v, first, count, ac, cwpb);
+        ac.bv = cbv + first;
+        ac.nbv = count;
+        ac.ntiles = vp.class_tiles[c];
+        if (ctx->debug_plan)
+          std::fprintf(stderr, "[vr] view %d class %zu: bricks %d tiles %d ring %d slot %d nslots %d reg %d wpb %d\n", v, c,
+                       count, ac.ntiles, cring ? 1 : 0, ac.ring_slot, ac.ring_nslots, ac.ring_reg, cwpb);
+        VR_HIP(cring ? launch_march_ring(ac, cwpb, s) : launch_march(ac, s));
+      }
+    } else {
+      VR_HIP(extras ? extras->launch(a, s)
+                    : (ring ? launch_march_ring(a, ring_wpb, s) : (lds ? launch_march_lds(a, s) : launch_march(a, s))));
+    }
     VR_TRY(stage_end(ctx, s));
     if (bricked && out) {
       CompArgs c;

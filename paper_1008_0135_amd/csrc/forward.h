@@ -17,6 +17,11 @@ struct ViewPlan {
   // wave w = bv[wave_begin[w] .. wave_begin[w + 1]) with tile_begin counted
   // from the wave's first brick and wave_tiles[w] tiles
   std::vector<int32_t> wave_begin, wave_tiles;
+  // perspective ring march: bv grouped into classes of bricks with similar
+  // windows, class c = bv[class_begin[c] .. class_begin[c + 1]) with
+  // tile_begin counted from the class's first brick and class_tiles[c] tiles
+  // (empty: one launch for the view)
+  std::vector<int32_t> class_begin, class_tiles;
   // ring march over footprint cells (parallel rays): bv counts cells, not tiles
   bool foot = false;
   FootShape fs;
@@ -30,6 +35,14 @@ struct ForwardExtras {
   virtual hipError_t launch(const MarchArgs& a, hipStream_t s) = 0;
   double vmin = 0.0, vmax = 0.0;
 };
+
+// Footprint-cell shape of one parallel view of a volume of size n, as the
+// forward picks it: plain = the plain march (no macrocell skipping, no mask),
+// reg_on = register staging allowed, nslots = the ring-slot rule (0, 2 or 3),
+// cells of about `rays` pixels with window rows of at most kmax 128-byte
+// lines (+ pad floats).  False when the view has no suitable slab axis.
+bool pick_foot(const Camera& cam, const int64_t n[3], int32_t M, bool plain, bool reg_on, int32_t nslots,
+               double rays, int32_t pad, int32_t kmax, FootShape& fs);
 
 void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params* p, int32_t tile_w, const float* tf,
                        int32_t M, double vmin, double vmax, ViewPlan& vp, bool waves = false);

@@ -208,11 +208,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int rl = lane / nf4, c4l = lane - rl * nf4;
   // instructions that carry a row of the window for this lane
   const int nmine = rl < R ? (NG - rl + R - 1) / R : 0;
-  const unsigned lane_off = (unsigned)(rl * sG + 4 * c4l) * 4u;
+  const unsigned row_off = (unsigned)(rl * sG) * 4u;
   const unsigned step_off = (unsigned)(R * sG) * 4u;
+  // columns a sample can read: the brick's voxels along f and one more on
+  // each side (a sample's cell index is clamped only at the volume's faces)
+  const int extF = br.hi[0] - br.lo[0];
+  const bool clip = a.foot_clip != 0;
   v4f rr[kRingRegLoads];
   auto rload = [&](int V, const Window& w) {
     const char* gb = (const char*)unip(gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0));
+    // a lane whose 16 bytes lie wholly outside those columns reads the
+    // nearest chunk inside them instead (a line fetched anyway); what it
+    // leaves in its LDS place is never sampled
+    int kc = c4l;
+    if (clip) {
+      const int k_lo = uni(max(0, (-1 - w.f0) >> 2));
+      const int k_hi = uni(max(k_lo, min(nf4 - 1, (extF + 1 - w.f0) >> 2)));
+      kc = min(max(c4l, k_lo), k_hi);
+    }
+    const unsigned lane_off = row_off + (unsigned)kc * 16u;
 #pragma unroll
     for (int i = 0; i < kRingRegLoads; ++i)
       if (i < nmine) rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (lane_off + (unsigned)i * step_off));

@@ -463,6 +463,7 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
   const double* e1 = cam.e1;
   const double* e2 = cam.e2;
   const double* d = cam.e3;
+  const int32_t max_px = rays > 64.0 ? 128 : 64;  // pixels a wavefront marches: one or two per lane
   double best = INFINITY;
   bool found = false;
   for (int b = 1; b <= 2; b++) {
@@ -484,8 +485,8 @@ bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, i
       // pixels past the 64th are marched by gathers
       for (int it = 0; it < 8; it++) {
         const int32_t most = foot_max_pixels(au / Tf, av / Tf, bu / Tg, bv / Tg);
-        if (most <= 64 || Tg <= 1.0) break;
-        Tg = std::max(1.0, Tg * std::min(0.98, 64.0 / most));
+        if (most <= max_px || Tg <= 1.0) break;
+        Tg = std::max(1.0, Tg * std::min(0.98, (double)max_px / most));
       }
       const int32_t nf = (int32_t)std::floor(Tf + 2.0 * std::fabs(rf) + 0.25) + 3 + pad;
       const int32_t ng = (int32_t)std::floor(Tg + 2.0 * std::fabs(rg) + 0.25) + 3;
@@ -618,6 +619,83 @@ void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t&
   fb0 = ((o[g] - (double)box.lo[g]) - ob * fs.rg) / fs.Tg;
 }
 
+void foot_traffic(const Camera& cam, const FootShape& fs, const Box& box, const int64_t n[3], FootTraffic& t) {
+  const int b = fs.axis, g = 3 - b;
+  int64_t ext[3];
+  for (int i = 0; i < 3; i++) ext[i] = box.hi[i] - box.lo[i];
+  t.own += 4.0 * (double)(ext[0] + (box.closed[0] ? 1 : 0)) * (double)(ext[1] + (box.closed[1] ? 1 : 0)) *
+           (double)(ext[2] + (box.closed[2] ? 1 : 0));
+  // clamps of the local cell index, as on the device: global [0, n - 2] - lo
+  const int64_t cloF = -box.lo[0], chiF = n[0] - 2 - box.lo[0];
+  const int64_t cloG = -box.lo[g], chiG = n[g] - 2 - box.lo[g];
+  const int64_t cloB = -box.lo[b], chiB = n[b] - 2 - box.lo[b];
+  const int64_t pitch = (fs.nf + 3) & ~3;
+  const int64_t NG = std::min<int64_t>(fs.ng, chiG + 2 - cloG);
+  const int64_t sG = g == 1 ? n[0] : n[0] * n[1], sB = b == 1 ? n[0] : n[0] * n[1];
+  const double rf = fs.rf, rg = fs.rg, arf = std::fabs(rf), arg = std::fabs(rg);
+  int32_t cf0, cg0, ncf, ncg;
+  double fa0, fb0;
+  foot_cells(cam, fs, box, cf0, cg0, ncf, ncg, fa0, fb0);
+  // per (voxel layer, window row): the f range any window covers
+  const int64_t v_lo = std::max<int64_t>(cloB, -2), v_hi = std::min<int64_t>(chiB + 1, ext[b] + 2);
+  const int64_t g_lo = cloG, g_hi = chiG + 1;
+  if (v_hi < v_lo || g_hi < g_lo) return;
+  const int64_t nv = v_hi - v_lo + 1, nrow = std::min<int64_t>(g_hi - g_lo + 1, ext[g] + 2 * NG + 8);
+  const int64_t g_base = std::max<int64_t>(g_lo, -NG - 4);
+  std::vector<int64_t> fmin((size_t)(nv * nrow), INT64_MAX), fmax((size_t)(nv * nrow), INT64_MIN);
+  const double eb = (double)ext[b] + (box.closed[b] ? 1.0 : 0.0);
+  for (int32_t cj = cg0; cj < cg0 + ncg; cj++)
+    for (int32_t ci = cf0; ci < cf0 + ncf; ci++) {
+      const double F0 = ci * fs.Tf, F1 = (ci + 1) * fs.Tf, G0 = cj * fs.Tg, G1 = (cj + 1) * fs.Tg;
+      // cell layers c (samples with c <= q_b < c + 1) in which some ray of
+      // the cell is inside the box along f and g
+      int64_t c0 = INT64_MAX, c1 = INT64_MIN;
+      for (int64_t c = 0; c < (int64_t)std::ceil(eb); c++) {
+        const double lo_b = (double)c, hi_b = std::min((double)(c + 1), eb);
+        const double f_lo = F0 + std::min(lo_b * rf, hi_b * rf), f_hi = F1 + std::max(lo_b * rf, hi_b * rf);
+        const double gg_lo = G0 + std::min(lo_b * rg, hi_b * rg), gg_hi = G1 + std::max(lo_b * rg, hi_b * rg);
+        if (f_hi <= 0.0 || f_lo >= (double)ext[0] + (box.closed[0] ? 1e-9 : 0.0)) continue;
+        if (gg_hi <= 0.0 || gg_lo >= (double)ext[g] + (box.closed[g] ? 1e-9 : 0.0)) continue;
+        c0 = std::min(c0, c);
+        c1 = std::max(c1, c);
+      }
+      if (c1 < c0) continue;
+      t.cells += 1.0;
+      // voxel layers c0 .. c1 + 1, whichever way the rays run
+      for (int64_t V = c0; V <= c1 + 1; V++) {
+        t.layers += 1.0;
+        const int64_t flo = std::max<int64_t>((int64_t)std::floor(F0 + V * rf - arf - 0.05), cloF);
+        const int64_t glo = std::max<int64_t>((int64_t)std::floor(G0 + V * rg - arg - 0.05), cloG);
+        const int64_t f0 = std::max(cloF, std::min(flo, chiF + 2 - pitch));
+        const int64_t g0 = std::max(cloG, std::min(glo, chiG + 2 - NG));
+        t.win += 4.0 * (double)(pitch * NG);
+        const int64_t iv = V - v_lo;
+        // the columns of the window inside the brick's reach along axis 1 (its
+        // voxels and one more on each side), as the kernel clips its loads
+        const int64_t cf_lo = std::max(f0, (int64_t)-1), cf_hi = std::min(f0 + pitch, ext[0] + 2);
+        for (int64_t r = 0; r < NG; r++) {
+          const int64_t row = box.lo[0] + (box.lo[g] + g0 + r) * sG + (box.lo[b] + V) * sB;
+          const int64_t a0 = row + f0;
+          t.line += 128.0 * (double)((a0 + pitch - 1) / 32 - a0 / 32 + 1);
+          t.seg += 64.0 * (double)((a0 + pitch - 1) / 16 - a0 / 16 + 1);
+          if (cf_hi > cf_lo) {
+            const int64_t c0 = row + cf_lo, c1 = row + cf_hi;
+            t.clip_win += 4.0 * (double)(c1 - c0);
+            t.clip_line += 128.0 * (double)((c1 - 1) / 32 - c0 / 32 + 1);
+            t.clip_seg += 64.0 * (double)((c1 - 1) / 16 - c0 / 16 + 1);
+          }
+          const int64_t ir = g0 + r - g_base;
+          if (iv < 0 || iv >= nv || ir < 0 || ir >= nrow) continue;
+          const size_t k = (size_t)(iv * nrow + ir);
+          fmin[k] = std::min(fmin[k], a0);
+          fmax[k] = std::max(fmax[k], a0 + pitch);
+        }
+      }
+    }
+  for (size_t k = 0; k < fmin.size(); k++)
+    if (fmax[k] > fmin[k]) t.uni += 128.0 * (double)((fmax[k] - 1) / 32 - fmin[k] / 32 + 1);
+}
+
 // Window floats of the perspective ring march for the 8 x 8 tile with corner
 // pixels (cx, cy) .. (ex, ey) over box r, on the better of axes 2 and 3 (the
 // kernel's choice, bounded over the box's layers); infinity when neither suits.
@@ -656,6 +734,19 @@ static double persp_tile_window(const Camera& cam, const TileRegion& r, int cx, 
   return best;
 }
 
+double persp_region_window(const Camera& cam, const TileRegion& r) {
+  if (r.w <= 0 || r.h <= 0) return 0.0;
+  const int ntx = (r.w + 7) / 8, nty = (r.h + 7) / 8;
+  const int sx[5] = {0, ntx - 1, 0, ntx - 1, ntx / 2}, sy[5] = {0, 0, nty - 1, nty - 1, nty / 2};
+  double worst = 0.0;
+  for (int k = 0; k < 5; k++) {
+    const int cx = r.x0 + 8 * sx[k], cy = r.y0 + 8 * sy[k];
+    const int ex = std::min(cx + 7, r.x0 + r.w - 1), ey = std::min(cy + 7, r.y0 + r.h - 1);
+    worst = std::max(worst, persp_tile_window(cam, r, cx, cy, ex, ey));
+  }
+  return worst;
+}
+
 bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
                        int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb, double fit) {
   std::vector<std::pair<double, double>> est;  // (window of the region's worst sampled tile, tiles)
@@ -663,14 +754,7 @@ bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, i
   for (const TileRegion& r : regs) {
     if (r.w <= 0 || r.h <= 0) continue;
     const int ntx = (r.w + 7) / 8, nty = (r.h + 7) / 8;
-    const int sx[5] = {0, ntx - 1, 0, ntx - 1, ntx / 2}, sy[5] = {0, 0, nty - 1, nty - 1, nty / 2};
-    double worst = 0.0;
-    for (int k = 0; k < 5; k++) {
-      const int cx = r.x0 + 8 * sx[k], cy = r.y0 + 8 * sy[k];
-      const int ex = std::min(cx + 7, r.x0 + r.w - 1), ey = std::min(cy + 7, r.y0 + r.h - 1);
-      worst = std::max(worst, persp_tile_window(cam, r, cx, cy, ex, ey));
-    }
-    est.emplace_back(worst, (double)ntx * nty);
+    est.emplace_back(persp_region_window(cam, r), (double)ntx * nty);
     total += (double)ntx * nty;
   }
   if (est.empty()) return false;

@@ -107,6 +107,9 @@ struct TileRegion {
   int64_t lo[3], hi[3];
   int32_t x0, y0, w, h;
 };
+// Window floats of the worst of five sampled 8 x 8 tiles of region r (its
+// corners and centre) for the perspective ring march.
+double persp_region_window(const Camera& cam, const TileRegion& r);
 bool choose_ring_persp(const Camera& cam, const std::vector<TileRegion>& regs, int32_t cap, int32_t M,
                        int32_t max_waves, int32_t min_waves, int32_t& slot, int32_t& wpb, double fit = 0.95);
 
@@ -157,6 +160,25 @@ int32_t window_loads(int32_t pitch, int32_t ng);
 // fall in, and the cell coordinates of pixel (0, 0)'s ray on its plane b = 0.
 void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t& cf0, int32_t& cg0, int32_t& ncf,
                 int32_t& ncg, double& fa0, double& fb0);
+
+// Bytes the window loads of the footprint-cell march request over one brick
+// (a model from the plan: every cell marches every layer its rays cross
+// inside the brick's ownership box, windows placed and clamped as the kernel
+// places them).  The terms separate what the design costs beyond the
+// brick's own voxels: ghost layers and halo beyond the brick (union), halo
+// shared by neighbouring cells (window), and 128-byte lines that a window
+// row only partly uses (line).
+struct FootTraffic {
+  double own = 0.0;     // the ownership box's voxels x 4
+  double uni = 0.0;     // 128-byte lines any window touches (per voxel layer and row) x 128
+  double win = 0.0;     // sum over cells and loaded voxel layers of rows x pitch x 4
+  double line = 0.0;    // the same rows counted in whole 128-byte lines
+  double seg = 0.0;     // ... in 64-byte segments
+  double clip_win = 0.0, clip_line = 0.0, clip_seg = 0.0;  // rows clipped to the brick's voxels +- 1 along axis 1
+  double cells = 0.0;   // cells with at least one layer
+  double layers = 0.0;  // voxel layers loaded, summed over cells
+};
+void foot_traffic(const Camera& cam, const FootShape& fs, const Box& box, const int64_t n[3], FootTraffic& t);
 
 // Sum over pixels of the whole-volume lattice count (no ERT, no skipping).
 int64_t count_samples(const Camera& cam, const int64_t n[3], double step);

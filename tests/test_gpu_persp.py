@@ -43,16 +43,23 @@ def _render(ctx, h, views, W, H, params, eye):
 
 
 def _ctx_with_march(mode):
+    """A context with one march forced; "auto:K": the default march with the
+    perspective ring march's bricks launched in K classes of similar window
+    size (K = 1: one launch per view)."""
     import os
-    old = os.environ.get("VR_MARCH")
-    os.environ["VR_MARCH"] = mode
+    env = {"VR_MARCH": mode}
+    if mode.startswith("auto:"):
+        env = {"VR_MARCH": "auto", "VR_PERSP_CLASSES": mode[5:]}
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
     try:
         return vr.vr_create(0)
     finally:
-        if old is None:
-            del os.environ["VR_MARCH"]
-        else:
-            os.environ["VR_MARCH"] = old
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
 
 
 DIMS = (96, 80, 112)  # half diagonal 84.9
@@ -85,7 +92,7 @@ def test_persp_parity_with_oracle(ctx, layout, eye, mode):
 
 
 def test_persp_marches_identical_and_skipping_inert():
-    _say("perspective: ring / gather bit identity; macrocell skipping inert")
+    _say("perspective: ring (one launch, or bricks in classes of similar window) / gather bit identity; macrocell skipping inert")
     dims = (150, 120, 170)
     vol = synth.cube(*dims, seed=103, n_sources=10, sigma_range=(2.0, 4.0))
     mn, mx = float(vol.min()), float(vol.max())
@@ -94,7 +101,7 @@ def test_persp_marches_identical_and_skipping_inert():
     layouts = {"whole": None, "grid": vr.grid_spec((64, 64, 64), macrocell=8), "kd": vr.kd_spec(7, macrocell=12),
                "mat": vr.grid_spec((75, 60, 85), materialize=True, macrocell=16)}
     imgs = {}
-    for march in ("gather", "auto"):
+    for march in ("gather", "auto", "auto:1", "auto:4"):
         c = _ctx_with_march(march)
         h = vr.vr_volume_create(c, vol, dims)
         for name, spec in layouts.items():
@@ -112,8 +119,9 @@ def test_persp_marches_identical_and_skipping_inert():
         vr.vr_volume_destroy(h)
         vr.vr_destroy(c)
     for k in [k for k in imgs if k[0] == "gather"]:
-        a, b = imgs[k], imgs[("auto",) + k[1:]]
-        assert np.array_equal(a, b), (k, float(np.abs(a - b).max()))
+        for m in ("auto", "auto:1", "auto:4"):
+            a, b = imgs[k], imgs[(m,) + k[1:]]
+            assert np.array_equal(a, b), (m, k, float(np.abs(a - b).max()))
     ref = oracle.render(vol, tables["colour"], views, 160, 136, mn, mx, tau=0.99, bricks={"grid": (64, 64, 64)},
                         eye_dist=135.0)
     parity(imgs[("auto", "grid", "colour", 135.0, 0)], ref, label="perspective ring march")
