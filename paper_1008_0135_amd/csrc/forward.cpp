@@ -166,16 +166,119 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   // fraction of the wavefronts their windows allow.  Bricks are grouped into
   // classes of similar window (about equal tile counts), launched one class
   // at a time with a slot of its own.
+  // bricks of a view grouped into ncls classes of about equal work by a size
+  // key (the window), launched one class at a time; items(b): the work items
+  // (tiles or cells) of brick view b
+  auto group_classes = [&](ViewPlan& vp, const std::vector<double>& key, int32_t ncls, auto items) {
+    std::vector<int32_t> idx(vp.bv.size());
+    int64_t total = 0;
+    for (int32_t i = 0; i < (int32_t)vp.bv.size(); i++) {
+      idx[i] = i;
+      total += items(vp.bv[i]);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+    // class boundaries at about equal work; within a class, brick order
+    std::vector<int32_t> cls(vp.bv.size(), 0);
+    int64_t acc = 0;
+    for (int32_t i : idx) {
+      cls[i] = (int32_t)std::min<int64_t>(ncls - 1, acc * ncls / std::max<int64_t>(1, total));
+      acc += items(vp.bv[i]);
+    }
+    std::vector<DevBrickView> nbv;
+    std::vector<int32_t> where(vp.bv.size(), -1);
+    nbv.reserve(vp.bv.size());
+    vp.class_begin.clear();
+    vp.class_tiles.clear();
+    for (int32_t c = 0; c < ncls; c++) {
+      const int32_t first = (int32_t)nbv.size();
+      int32_t t = 0;
+      for (int32_t i = 0; i < (int32_t)vp.bv.size(); i++)
+        if (cls[i] == c) {
+          DevBrickView b = vp.bv[i];
+          b.tile_begin = t;
+          t += (int32_t)items(b);
+          where[i] = (int32_t)nbv.size();
+          nbv.push_back(b);
+        }
+      if (t == 0) continue;
+      vp.class_begin.push_back(first);
+      vp.class_tiles.push_back(t);
+    }
+    vp.class_begin.push_back((int32_t)nbv.size());
+    for (int32_t& l : vp.layers_order) l = where[l];
+    vp.bv.swap(nbv);
+  };
+  // perspective views on footprint cells sized per brick (the plain march of
+  // emission-absorption or MIP, register-staged): one slab axis for the view,
+  // the one along which the eye lies outside every brick's slab.  A view
+  // where some brick does not suit keeps the 8 x 8 tiles.
   for (int32_t v = 0; v < nviews; v++) {
     ViewPlan& vp = plans[v];
+    vp.pfoot = false;
+    if (!bricked || global || extras || !cams[v].persp || !(mode == 0 || mode == 3) || tw != 8 ||
+        !ctx->persp_cells || base.mc != 0 || base.mask || ctx->ring_reg <= 0 || ctx->ring_nslots == 3 ||
+        vp.bv.empty())
+      continue;
+    const int first_axis = std::fabs(cams[v].e3[1]) >= std::fabs(cams[v].e3[2]) ? 1 : 2;
+    std::vector<PerspCells> pcs(vp.bv.size());
+    int axis = 0;
+    for (int tryax : {first_axis, 3 - first_axis}) {
+      bool all = true;
+      for (size_t i = 0; i < vp.bv.size() && all; i++) {
+        const DevBrickView& b = vp.bv[i];
+        Rect rc;
+        rc.x0 = b.x0;
+        rc.y0 = b.y0;
+        rc.w = b.w;
+        rc.h = b.h;
+        all = persp_cells(cams[v], tryax, vol->part.boxes[b.brick], rc, ctx->foot_rays, ctx->foot_kmax, kRingCap,
+                          kRingRegLoads, pcs[i]);
+      }
+      if (all) {
+        axis = tryax;
+        break;
+      }
+    }
+    if (axis == 0) continue;
+    std::vector<double> key(vp.bv.size());
+    for (size_t i = 0; i < vp.bv.size(); i++) {
+      DevBrickView& b = vp.bv[i];
+      const PerspCells& pc = pcs[i];
+      b.tiles_x = pc.ncf;
+      b.cf0 = pc.cf0;
+      b.cg0 = pc.cg0;
+      b.blocks_x = pc.ncg;  // cells along g (the cell count is tiles_x x blocks_x)
+      b.pTf = pc.Tf;
+      b.pTg = pc.Tg;
+      b.ppitch = pc.pitch;
+      b.png = pc.ng;
+      key[i] = (double)pc.pitch * pc.ng;
+    }
+    // one launch: the cell shapes are chosen for the occupancy their windows
+    // allow, so their slots differ little (three launches measured slower)
+    group_classes(vp, key, 1, [](const DevBrickView& b) { return (int64_t)b.tiles_x * b.blocks_x; });
+    vp.pfoot = true;
+    vp.paxis = axis;
+    int64_t cells = 0;
+    for (int32_t t : vp.class_tiles) cells += t;
+    vp.ntiles = (int32_t)cells;
+  }
+  // perspective views on the ring march's 8 x 8 tiles: rays from the eye
+  // spread with depth, so the tiles of far bricks need windows about twice
+  // those of near ones, and one slot sized for nearly all tiles leaves the
+  // near bricks at a fraction of the wavefronts their windows allow.  Bricks
+  // are grouped into classes of similar window (about equal tile counts),
+  // launched one class at a time with a slot of its own.
+  for (int32_t v = 0; v < nviews; v++) {
+    ViewPlan& vp = plans[v];
+    if (vp.pfoot) continue;
     vp.class_begin.clear();
     vp.class_tiles.clear();
     const int32_t ncls = ctx->persp_classes;
     if (!bricked || global || extras || !cams[v].persp || !(mode == 0 || mode == 3) || tw != 8 || ncls < 2 ||
         vp.bv.size() < (size_t)(2 * ncls))
       continue;
-    std::vector<std::pair<double, int32_t>> est;  // (worst sampled window, bv index)
-    int64_t total = 0;
+    std::vector<double> key(vp.bv.size());
     for (int32_t i = 0; i < (int32_t)vp.bv.size(); i++) {
       const DevBrickView& b = vp.bv[i];
       TileRegion r;
@@ -187,42 +290,9 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       r.y0 = b.y0;
       r.w = b.w;
       r.h = b.h;
-      est.emplace_back(persp_region_window(cams[v], r), i);
-      total += (int64_t)b.tiles_x * ((b.h + th - 1) / th);
+      key[i] = persp_region_window(cams[v], r);
     }
-    std::stable_sort(est.begin(), est.end(),
-                     [](const std::pair<double, int32_t>& x, const std::pair<double, int32_t>& y) {
-                       return x.first < y.first;
-                     });
-    // class boundaries at about equal tile counts; within a class, brick order
-    std::vector<int32_t> cls(vp.bv.size(), 0);
-    int64_t acc = 0;
-    for (const auto& e : est) {
-      const DevBrickView& b = vp.bv[e.second];
-      cls[e.second] = (int32_t)std::min<int64_t>(ncls - 1, acc * ncls / std::max<int64_t>(1, total));
-      acc += (int64_t)b.tiles_x * ((b.h + th - 1) / th);
-    }
-    std::vector<DevBrickView> nbv;
-    std::vector<int32_t> where(vp.bv.size(), -1);
-    nbv.reserve(vp.bv.size());
-    for (int32_t c = 0; c < ncls; c++) {
-      const int32_t first = (int32_t)nbv.size();
-      int32_t t = 0;
-      for (int32_t i = 0; i < (int32_t)vp.bv.size(); i++)
-        if (cls[i] == c) {
-          DevBrickView b = vp.bv[i];
-          b.tile_begin = t;
-          t += b.tiles_x * ((b.h + th - 1) / th);
-          where[i] = (int32_t)nbv.size();
-          nbv.push_back(b);
-        }
-      if (t == 0) continue;
-      vp.class_begin.push_back(first);
-      vp.class_tiles.push_back(t);
-    }
-    vp.class_begin.push_back((int32_t)nbv.size());
-    for (int32_t& l : vp.layers_order) l = where[l];
-    vp.bv.swap(nbv);
+    group_classes(vp, key, ncls, [th](const DevBrickView& b) { return (int64_t)b.tiles_x * ((b.h + th - 1) / th); });
   }
   // parallel rays on the ring march: footprint cells instead of 8 x 8 pixel
   // tiles (the cell counts replace the tile counts of the plan)
@@ -289,12 +359,15 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
   if (bricked && arena_pix > 0) VR_TRY(ensure_device(&ctx->d_arena, &ctx->arena_bytes, (size_t)arena_pix * 16));
   // overflow lists of the footprint-cell marches: one per stream a view may use
   int64_t foot_tiles = 0;  // cells of a launch (a block holds blk_f x blk_g)
-  for (const ViewPlan& vp : plans)
+  for (const ViewPlan& vp : plans) {
     if (vp.foot) {
       const int64_t per = vp.fs.blk_f > 0 ? (int64_t)vp.fs.blk_f * vp.fs.blk_g : 1;
       foot_tiles = std::max<int64_t>(foot_tiles, vp.ntiles * per);
       for (int32_t t : vp.wave_tiles) foot_tiles = std::max<int64_t>(foot_tiles, t * per);
     }
+    if (vp.pfoot)
+      for (int32_t t : vp.class_tiles) foot_tiles = std::max<int64_t>(foot_tiles, t);
+  }
   const size_t ovf_stride = align16(256 + 4 * (size_t)foot_tiles);
   if (foot_tiles > 0) VR_TRY(ensure_device(&ctx->d_ovf, &ctx->ovf_bytes, ovf_stride * vr_ctx::kAux));
   float4* arena = reinterpret_cast<float4*>(ctx->d_arena);
@@ -503,7 +576,49 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       continue;
     }
     VR_TRY(stage_begin(ctx, VR_STAGE_MARCH, s));
-    if (!vp.class_begin.empty()) {
+    if (vp.pfoot) {
+      // perspective footprint cells: the brick images' pixels without samples
+      // are not written, so the arena is cleared first; one launch per class
+      // of window size, the class's largest window as the slot
+      VR_HIP(launch_zero(arena, vp.pixels, s));
+      const DevBrickView* cbv = a.bv;
+      for (size_t c = 0; c + 1 < vp.class_begin.size(); c++) {
+        MarchArgs ac = a;
+        const int32_t first = vp.class_begin[c], count = vp.class_begin[c + 1] - first;
+        int32_t slot = 0, mpitch = 0, mng = 0;
+        for (int32_t k = first; k < first + count; k++) {
+          slot = std::max(slot, vp.bv[k].ppitch * vp.bv[k].png);
+          mpitch = std::max(mpitch, vp.bv[k].ppitch);
+          mng = std::max(mng, vp.bv[k].png);
+        }
+        ac.bv = cbv + first;
+        ac.nbv = count;
+        ac.ntiles = vp.class_tiles[c];
+        ac.foot = 1;
+        ac.blk_f = ac.blk_g = 0;
+        ac.slab_axis = vp.paxis;
+        ac.ring_slot = slot;
+        ac.ring_nslots = 2;
+        ac.ring_reg = 1;
+        ac.foot_clip = ctx->foot_clip;
+        ac.foot_nf = mpitch;
+        ac.foot_ng = mng;
+        int32_t waves = 0;
+        int cwpb = ring_waves_per_block(slot, ac.M, kRingRegWaves, &waves, 2);
+        if (ctx->cells_wpb > 0) cwpb = ctx->cells_wpb;
+        if (ctx->cells_waves > 0) {
+          const int32_t nwg = std::max(1, ctx->cells_waves / cwpb);
+          ac.lds_floor = kLdsPerCu / (nwg + 1) + 1024;
+        }
+        unsigned char* ovf = reinterpret_cast<unsigned char*>(ctx->d_ovf);
+        ac.ovf_count = reinterpret_cast<unsigned int*>(ovf);
+        ac.ovf_tiles = reinterpret_cast<int32_t*>(ovf + 256);
+        if (ctx->debug_plan)
+          std::fprintf(stderr, "[vr] view %d cells class %zu: bricks %d cells %d axis %d slot %d pitch<=%d ng<=%d wpb %d waves %d\n",
+                       v, c, count, ac.ntiles, vp.paxis, slot, mpitch, mng, cwpb, waves);
+        VR_HIP(launch_march_ring(ac, cwpb, s));
+      }
+    } else if (!vp.class_begin.empty()) {
       // perspective classes: one launch each, with the class's own slot
       const DevBrickView* cbv = a.bv;
       for (size_t c = 0; c + 1 < vp.class_begin.size(); c++) {

@@ -22,6 +22,10 @@ struct ViewPlan {
   // tile_begin counted from the class's first brick and class_tiles[c] tiles
   // (empty: one launch for the view)
   std::vector<int32_t> class_begin, class_tiles;
+  // perspective views on footprint cells sized per brick (pfoot): bv counts
+  // cells, grouped into the classes above by window size; paxis = slab axis
+  bool pfoot = false;
+  int32_t paxis = 0;
   // ring march over footprint cells (parallel rays): bv counts cells, not tiles
   bool foot = false;
   FootShape fs;

@@ -67,9 +67,8 @@ __device__ __forceinline__ CellRay cell_ray(const MarchArgs& a, const DevBrickVi
   }
   const int lx = u - bvw.x0, ly = v - bvw.y0;
   const bool inrect = lx >= 0 && lx < bvw.w && ly >= 0 && ly < bvw.h;
-  double o[3];
-  const double* d = a.cam.e3;
-  pixel_origin(a.cam, u, v, o);
+  double o[3], d[3];
+  pixel_ray(a.cam, u, v, o, d);  // parallel rays: the view direction
   r.cnt = 0;
   r.px = r.py = r.pz = 0.f;
   r.dst = a.carry ? a.img + (int64_t)v * a.cam.W + u : a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
@@ -132,7 +131,7 @@ __device__ __forceinline__ void sample_layer(const MarchArgs& a, const DevBrick&
   }
 }
 
-template <bool MIP, bool BY>
+template <bool MIP, bool BY, bool PERSP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_march_cells(MarchArgs a) {
   extern __shared__ float4 smem[];
   float4* s_tf = smem;
@@ -155,7 +154,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const DevBrick br = a.bricks[bvw.brick];
   int ci, cj;
   foot_cell(bvw, tile - bvw.tile_begin, ci, cj);
-  const FootRuns fr = foot_runs(a, bvw, ci, cj, lane);
+  const FootRuns fr = PERSP ? foot_runs_persp(a, bvw, br, ci, cj, lane) : foot_runs(a, bvw, ci, cj, lane);
   // pixels past the 64th of a cell are marched by k_march_ring_ovf afterwards
   if (fr.n > 64 && lane == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile * 8;
   const CellRay r = cell_ray(a, bvw, br, fr, lane);
@@ -166,7 +165,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int cloG = BY ? br.clo[2] : br.clo[1], chiG = BY ? br.chi[2] : br.chi[1];
   const int cloF = br.clo[0], chiF = br.chi[0];
   const double db = BY ? a.cam.e3[1] : a.cam.e3[2], dg = BY ? a.cam.e3[2] : a.cam.e3[1];
-  const bool up = db > 0.0;
+  // perspective: the brick-local eye E; the rays run away from it along b
+  const double Eb = PERSP ? a.cam.eye[BY ? 1 : 2] - (double)br.lo[BY ? 1 : 2] : 0.0;
+  const bool up = PERSP ? Eb < 0.0 : db > 0.0;
 
   // cell layers (along b) of the lane's first and last samples
   int c_first = up ? 0x7fffffff : -0x7fffffff, c_last = up ? -0x7fffffff : 0x7fffffff;
@@ -182,20 +183,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   // ---- window geometry: the cell's rectangle on the plane b = 0 moves by
   // (rf, rg) per layer; window of voxel layer V = that rectangle over the
   // planes [V - 1, V + 1], cells floor(q) .. floor(q) + 1, 0.05 margins
-  const float rf = (float)(a.cam.e3[0] / db), rg = (float)(dg / db);
+  const float rf = PERSP ? 0.f : (float)(a.cam.e3[0] / db), rg = PERSP ? 0.f : (float)(dg / db);
   const float arf = fabsf(rf), arg = fabsf(rg);
-  const float Af_lo = (float)((double)ci * a.foot_Tf), Ag_lo = (float)((double)cj * a.foot_Tg);
-  const int pitch = (a.foot_nf + 3) & ~3;
-  const int NG = min(a.foot_ng, chiG + 2 - cloG);
+  const double Tf = PERSP ? bvw.pTf : a.foot_Tf, Tg = PERSP ? bvw.pTg : a.foot_Tg;
+  const float Af_lo = (float)((double)ci * Tf), Ag_lo = (float)((double)cj * Tg);
+  const float Af_hi = (float)((double)(ci + 1) * Tf), Ag_hi = (float)((double)(cj + 1) * Tg);
+  // perspective: on the plane b = P the cell's rays fill its rectangle scaled
+  // by s(P) = 1 - P / E_b about the eye's foot point (Ef, Eg)
+  const float Ef = PERSP ? (float)(a.cam.eye[0] - (double)br.lo[0]) : 0.f;
+  const float Eg = PERSP ? (float)(a.cam.eye[BY ? 2 : 1] - (double)br.lo[BY ? 2 : 1]) : 0.f;
+  const float inv_Eb = PERSP ? (float)(1.0 / Eb) : 0.f;
+  const int pitch = PERSP ? bvw.ppitch : (a.foot_nf + 3) & ~3;
+  const int NG = min(PERSP ? bvw.png : a.foot_ng, chiG + 2 - cloG);
   const int sB = BY ? br.sy : br.sz, sG = BY ? br.sz : br.sy;
   gfloat* gbase = (gfloat*)br.base;
   auto window = [&](int V) {
     Window w;
-    const float Pf = (float)V * rf, Pg = (float)V * rg;
-    const int flo = max((int)floorf(Af_lo + Pf - arf - 0.05f), cloF);
-    const int glo = max((int)floorf(Ag_lo + Pg - arg - 0.05f), cloG);
+    int flo, glo;
+    if constexpr (PERSP) {
+      const float s0 = fmaf(-(float)(V - 1), inv_Eb, 1.f), s1 = fmaf(-(float)(V + 1), inv_Eb, 1.f);
+      const float f00 = fmaf(s0, Af_lo - Ef, Ef), f01 = fmaf(s0, Af_hi - Ef, Ef);
+      const float f10 = fmaf(s1, Af_lo - Ef, Ef), f11 = fmaf(s1, Af_hi - Ef, Ef);
+      const float g00 = fmaf(s0, Ag_lo - Eg, Eg), g01 = fmaf(s0, Ag_hi - Eg, Eg);
+      const float g10 = fmaf(s1, Ag_lo - Eg, Eg), g11 = fmaf(s1, Ag_hi - Eg, Eg);
+      flo = max((int)floorf(fminf(fminf(f00, f01), fminf(f10, f11)) - 0.05f), cloF);
+      glo = max((int)floorf(fminf(fminf(g00, g01), fminf(g10, g11)) - 0.05f), cloG);
+      // the window is sized for the brick's widest layer; this layer's samples
+      // read columns and rows up to these (the trilinear neighbour included)
+      w.fb = (int)floorf(fmaxf(fmaxf(f00, f01), fmaxf(f10, f11)) + 0.05f) + 1;
+      w.gb = (int)floorf(fmaxf(fmaxf(g00, g01), fmaxf(g10, g11)) + 0.05f) + 1;
+    } else {
+      const float Pf = (float)V * rf, Pg = (float)V * rg;
+      flo = max((int)floorf(Af_lo + Pf - arf - 0.05f), cloF);
+      glo = max((int)floorf(Ag_lo + Pg - arg - 0.05f), cloG);
+      w.fb = w.gb = 0;
+    }
     w.f0 = uni(max(cloF, min(flo, chiF + 2 - pitch)));
     w.g0 = uni(max(cloG, min(glo, chiG + 2 - NG)));
+    if constexpr (PERSP) {
+      w.fb = uni(w.fb - w.f0);
+      w.gb = uni(w.gb - w.g0);
+    }
     return w;
   };
 
@@ -220,16 +248,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     // a lane whose 16 bytes lie wholly outside those columns reads the
     // nearest chunk inside them instead (a line fetched anyway); what it
     // leaves in its LDS place is never sampled
-    int kc = c4l;
-    if (clip) {
-      const int k_lo = uni(max(0, (-1 - w.f0) >> 2));
-      const int k_hi = uni(max(k_lo, min(nf4 - 1, (extF + 1 - w.f0) >> 2)));
-      kc = min(max(c4l, k_lo), k_hi);
-    }
-    const unsigned lane_off = row_off + (unsigned)kc * 16u;
+    if constexpr (PERSP) {
+      // the window is sized for the brick's widest layer: this layer's
+      // columns and rows end earlier
+      int kc = c4l;
+      if (clip) {
+        const int k_lo = uni(max(0, (-1 - w.f0) >> 2));
+        const int k_hi = uni(max(k_lo, min(min(nf4 - 1, (extF + 1 - w.f0) >> 2), w.fb >> 2)));
+        kc = min(max(c4l, k_lo), k_hi);
+      }
+      // rows past this layer's last read that row again (lines fetched
+      // anyway); the predicate stays the cell's, so no load waits on another
+      const unsigned col_off = (unsigned)kc * 16u;
+      const unsigned last_off = (unsigned)(min(NG - 1, w.gb) * sG) * 4u;
 #pragma unroll
-    for (int i = 0; i < kRingRegLoads; ++i)
-      if (i < nmine) rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (lane_off + (unsigned)i * step_off));
+      for (int i = 0; i < kRingRegLoads; ++i)
+        if (i < nmine)
+          rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (min(row_off + (unsigned)i * step_off, last_off) +
+                                                                          col_off));
+    } else {
+      int kc = c4l;
+      if (clip) {
+        const int k_lo = uni(max(0, (-1 - w.f0) >> 2));
+        const int k_hi = uni(max(k_lo, min(nf4 - 1, (extF + 1 - w.f0) >> 2)));
+        kc = min(max(c4l, k_lo), k_hi);
+      }
+      const unsigned lane_off = row_off + (unsigned)kc * 16u;
+#pragma unroll
+      for (int i = 0; i < kRingRegLoads; ++i)
+        if (i < nmine) rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (lane_off + (unsigned)i * step_off));
+    }
   };
   auto rstore = [&](float* sdst) {
     v4f* l = (v4f*)(sdst + 4 * lane);
@@ -352,6 +400,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int glo = max((int)floorf(Ag_lo + Pg - arg - 0.05f), cloG);
     w.f0 = uni(max(cloF, min(flo, chiF + 2 - pitch)));
     w.g0 = uni(max(cloG, min(glo, chiG + 2 - NG)));
+    w.fb = w.gb = 0;
     return w;
   };
 
@@ -437,9 +486,13 @@ size_t cells_lds_bytes(const MarchArgs& a, int wpb) {
 // assume them
 static bool cells_args_ok(const MarchArgs& a, int waves_per_window) {
   const int64_t pitch = (a.foot_nf + 3) & ~3;
-  if (a.cam.persp || a.mc != 0 || a.mask || !a.foot || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 || pitch > 256 ||
-      pitch * a.foot_ng > a.ring_slot || (a.slab_axis != 1 && a.slab_axis != 2))
+  if (a.mc != 0 || a.mask || !a.foot || a.ring_slot <= 0 || (a.ring_slot & 3) != 0 ||
+      (a.slab_axis != 1 && a.slab_axis != 2))
     return false;
+  // perspective: windows sized per brick, each checked against the slot and
+  // the register loads when the launch was planned
+  if (a.cam.persp) return waves_per_window == 1;
+  if (pitch > 256 || pitch * a.foot_ng > a.ring_slot) return false;
   const int64_t R = 64 / (pitch / 4);
   const int64_t nload = (a.foot_ng + R - 1) / R;
   return (nload + waves_per_window - 1) / waves_per_window <= kRingRegLoads;
@@ -468,10 +521,17 @@ hipError_t launch_march_cells(const MarchArgs& a, int wpb, hipStream_t s) {
   const dim3 g(grid), b(64 * wpb);
   const size_t lds = std::max(cells_lds_bytes(a, wpb), (size_t)std::max(0, a.lds_floor));
   const bool by = a.slab_axis == 1;
-  if (a.mip && by) hipLaunchKernelGGL((k_march_cells<true, true>), g, b, lds, s, a);
-  else if (a.mip) hipLaunchKernelGGL((k_march_cells<true, false>), g, b, lds, s, a);
-  else if (by) hipLaunchKernelGGL((k_march_cells<false, true>), g, b, lds, s, a);
-  else hipLaunchKernelGGL((k_march_cells<false, false>), g, b, lds, s, a);
+  if (a.cam.persp) {
+    if (a.mip && by) hipLaunchKernelGGL((k_march_cells<true, true, true>), g, b, lds, s, a);
+    else if (a.mip) hipLaunchKernelGGL((k_march_cells<true, false, true>), g, b, lds, s, a);
+    else if (by) hipLaunchKernelGGL((k_march_cells<false, true, true>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((k_march_cells<false, false, true>), g, b, lds, s, a);
+  } else {
+    if (a.mip && by) hipLaunchKernelGGL((k_march_cells<true, true, false>), g, b, lds, s, a);
+    else if (a.mip) hipLaunchKernelGGL((k_march_cells<true, false, false>), g, b, lds, s, a);
+    else if (by) hipLaunchKernelGGL((k_march_cells<false, true, false>), g, b, lds, s, a);
+    else hipLaunchKernelGGL((k_march_cells<false, false, false>), g, b, lds, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -748,7 +748,7 @@ __global__ __launch_bounds__(256) void k_march_ring_ovf(MarchArgs a) {
     int ci, cj;
     if (a.blk_f > 0) block_cell(a, bvw, tile - bvw.tile_begin, w, ci, cj);
     else foot_cell(bvw, tile - bvw.tile_begin, ci, cj);
-    const FootRuns fr = foot_runs(a, bvw, ci, cj, lane);
+    const FootRuns fr = a.cam.persp ? foot_runs_persp(a, bvw, br, ci, cj, lane) : foot_runs(a, bvw, ci, cj, lane);
     gfloat* gb = (gfloat*)br.base;
     const int ys = br.sy, zs = br.sz;
     for (int k0 = 64; k0 < fr.n; k0 += 64) {
@@ -762,9 +762,8 @@ __global__ __launch_bounds__(256) void k_march_ring_ovf(MarchArgs a) {
       float4 c0 = make_float4(0.f, 0.f, 0.f, 1.f);
       if (a.carry) c0 = *dst;
       if (a.carry && !(1.f - c0.w < a.tau)) continue;
-      double o[3];
-      pixel_origin(a.cam, uu, vv, o);
-      const double* d = a.cam.e3;
+      double o[3], d[3];
+      pixel_ray(a.cam, uu, vv, o, d);  // parallel rays: the view direction
       double tin;
       int64_t n, k0b, k1b;
       if (!ray_lattice(o, d, a.hi, a.step, tin, n)) continue;
@@ -815,7 +814,8 @@ hipError_t launch_march_ring(const MarchArgs& a, int wpb, hipStream_t s) {
   if (a.ntiles <= 0) return hipSuccess;
   if (!a.foot) return launch_march_ring_main(a, wpb, s);
   // footprint cells: clear the overflow list, march, then the listed cells' pixels past the 64th
-  if (a.cam.persp || !a.ovf_count || !a.ovf_tiles) return hipErrorInvalidValue;
+  // (perspective views: the register-staged cell march only)
+  if ((a.cam.persp && (!a.ring_reg || a.blk_f > 0)) || !a.ovf_count || !a.ovf_tiles) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_ovf_reset, dim3(1), dim3(1), 0, s, a.ovf_count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -619,6 +619,123 @@ void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t&
   fb0 = ((o[g] - (double)box.lo[g]) - ob * fs.rg) / fs.Tg;
 }
 
+bool persp_cells(const Camera& cam, int b, const Box& box, const Rect& rect, double rays, int32_t kmax,
+                 int32_t cap, int32_t reg_loads, PerspCells& out) {
+  if (!cam.persp || rect.w <= 0 || rect.h <= 0) return false;
+  const int g = 3 - b;
+  double E[3], ext[3];
+  for (int i = 0; i < 3; i++) {
+    E[i] = cam.eye[i] - (double)box.lo[i];
+    ext[i] = (double)(box.hi[i] - box.lo[i]);
+  }
+  // the eye well outside the brick's slab along b: every ray of the brick
+  // then crosses the planes b = const one way, in front of the eye
+  if (!(E[b] < -8.0 || E[b] > ext[b] + 8.0)) return false;
+  const double sgn = E[b] < 0.0 ? 1.0 : -1.0;  // sign of w_b toward the brick
+  const double px0 = rect.x0 - 0.5, py0 = rect.y0 - 0.5, px1 = rect.x0 + rect.w - 0.5, py1 = rect.y0 + rect.h - 0.5;
+  for (int c = 0; c < 4; c++) {
+    const double u = (c & 1) ? px1 : px0, v = (c & 2) ? py1 : py0;
+    const double x = ((u + 0.5) / (double)cam.W - 0.5) * cam.S;
+    const double y = ((v + 0.5) / (double)cam.H - 0.5) * cam.S * (double)cam.H / (double)cam.W;
+    const double wb = x * cam.e1[b] + y * cam.e2[b] + cam.D * cam.e3[b];
+    if (!(sgn * wb > 1e-3 * cam.D)) return false;
+  }
+  // the brick seen from the eye on the plane b = 0 (its corners, one voxel of
+  // margin): every ray through the brick crosses the plane in this box
+  double flo = INFINITY, fhi = -INFINITY, glo = INFINITY, ghi = -INFINITY;
+  for (int c = 0; c < 8; c++) {
+    double q[3];
+    for (int i = 0; i < 3; i++) q[i] = (c >> i) & 1 ? ext[i] + 1.0 : -1.0;
+    const double t = -E[b] / (q[b] - E[b]);
+    const double f = E[0] + t * (q[0] - E[0]), gg = E[g] + t * (q[g] - E[g]);
+    flo = std::min(flo, f);
+    fhi = std::max(fhi, f);
+    glo = std::min(glo, gg);
+    ghi = std::max(ghi, gg);
+  }
+  // scale of the plane b = V against b = 0 about the eye's foot point, over
+  // the voxel layers a window can cover
+  const double s_a = 1.0 - (-2.0) / E[b], s_b = 1.0 - (ext[b] + 3.0) / E[b];
+  const double s_max = std::max(s_a, s_b);
+  // growth of a window over its two layers: the scale changes by 2 / |E_b|
+  // across them, times the distance from the eye's foot point
+  const double slant_f = 2.0 * std::max(std::fabs(flo - E[0]), std::fabs(fhi - E[0])) / std::fabs(E[b]);
+  const double slant_g = 2.0 * std::max(std::fabs(glo - E[g]), std::fabs(ghi - E[g])) / std::fabs(E[b]);
+  // plane coordinates per pixel step at the rectangle's corners and centre;
+  // the densest point sizes the cells, the one with the most image rows per
+  // cell bounds the rows a cell spans
+  double su_f = 0, sv_f = 0, su_g = 0, sv_g = 0, det_min = INFINITY, rows_f = 0.0, rows_g = 0.0;
+  for (int c = 0; c < 5; c++) {
+    const double u = c == 4 ? 0.5 * (px0 + px1) : ((c & 1) ? px1 : px0);
+    const double v = c == 4 ? 0.5 * (py0 + py1) : ((c & 2) ? py1 : py0);
+    double f0, g0, fu, gu, fv, gv;
+    persp_plane_point(cam, E, b, g, u, v, f0, g0);
+    persp_plane_point(cam, E, b, g, u + 1.0, v, fu, gu);
+    persp_plane_point(cam, E, b, g, u, v + 1.0, fv, gv);
+    const double au = fu - f0, av = fv - f0, bu = gu - g0, bv = gv - g0;
+    const double det = au * bv - av * bu;
+    if (!(std::fabs(det) > 1e-12)) return false;
+    if (std::fabs(det) < det_min) {
+      det_min = std::fabs(det);
+      su_f = au;
+      sv_f = av;
+      su_g = bu;
+      sv_g = bv;
+    }
+    // image rows per unit of f and of g (the inverse map's v row)
+    rows_f = std::max(rows_f, std::fabs(bu / det));
+    rows_g = std::max(rows_g, std::fabs(au / det));
+  }
+  double best = INFINITY;
+  bool found = false;
+  // fewer rays per cell shrink the windows of far bricks (sparse rays), which
+  // lets more wavefronts share a compute unit: the cost weighs the lines per
+  // ray by the occupancy shortfall below 16 wavefronts
+  for (int k = 1; k <= kmax; k++)
+  for (const double rr : {rays, 0.8 * rays, 0.65 * rays, 0.5 * rays}) {
+    const double Tf = (32.0 * k - slant_f - 3.5) / s_max;
+    if (Tf < 4.0) continue;
+    double Tg = std::max(1.0, rr * det_min / Tf);
+    int32_t most = 0;
+    for (int it = 0; it < 8; it++) {
+      most = foot_max_pixels(su_f / Tf, sv_f / Tf, su_g / Tg, sv_g / Tg);
+      if (most <= 64 || Tg <= 1.0) break;
+      Tg = std::max(1.0, Tg * std::min(0.98, 64.0 / most));
+    }
+    if (most > 64) continue;  // too many pixels even in the thinnest cells of this width
+    // the cells of the grid's first and last columns and rows reach up to
+    // two cells past the brick's box: their distance from the foot point
+    const double wf = 2.0 * std::max(std::fabs(flo - 2.0 * Tf - E[0]), std::fabs(fhi + 2.0 * Tf - E[0])) /
+                      std::fabs(E[b]);
+    const double wg = 2.0 * std::max(std::fabs(glo - 2.0 * Tg - E[g]), std::fabs(ghi + 2.0 * Tg - E[g])) /
+                      std::fabs(E[b]);
+    const int32_t nf = (int32_t)std::floor(s_max * Tf + wf + 0.25) + 3;
+    const int32_t ng = (int32_t)std::floor(s_max * Tg + wg + 0.25) + 3;
+    const int32_t pitch = (nf + 3) & ~3;
+    if ((int64_t)pitch * ng > cap || pitch > 256 || window_loads(pitch, ng) > reg_loads) continue;
+    if (rows_f * Tf + rows_g * Tg + 4.0 > 60.0) continue;
+    const double cell_rays = Tf * Tg / det_min;
+    int32_t waves = 0;
+    ring_waves_per_block(pitch * ng, 256, 16, &waves, 2);
+    const double cost = (double)ng * ((double)pitch + 31.0) / 32.0 / cell_rays * std::max(1.0, 16.0 / std::max(1, waves));
+    if (cost < best) {
+      best = cost;
+      found = true;
+      out.Tf = Tf;
+      out.Tg = Tg;
+      out.pitch = pitch;
+      out.ng = ng;
+      out.rays = cell_rays;
+    }
+  }
+  if (!found) return false;
+  out.cf0 = (int32_t)std::floor(flo / out.Tf) - 1;
+  out.cg0 = (int32_t)std::floor(glo / out.Tg) - 1;
+  out.ncf = (int32_t)std::floor(fhi / out.Tf) + 1 - out.cf0 + 1;
+  out.ncg = (int32_t)std::floor(ghi / out.Tg) + 1 - out.cg0 + 1;
+  return true;
+}
+
 void foot_traffic(const Camera& cam, const FootShape& fs, const Box& box, const int64_t n[3], FootTraffic& t) {
   const int b = fs.axis, g = 3 - b;
   int64_t ext[3];

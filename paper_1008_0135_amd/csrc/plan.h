@@ -161,6 +161,26 @@ int32_t window_loads(int32_t pitch, int32_t ng);
 void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t& cf0, int32_t& cg0, int32_t& ncf,
                 int32_t& ncg, double& fa0, double& fb0);
 
+// Footprint cells of one brick of a perspective view, slab axis b (1 = axis 2,
+// 2 = axis 3): the pixels whose rays (from the eye) cross the brick-local
+// plane b = 0 inside one Tf x Tg rectangle.  On the plane b = V the rays of a
+// cell fill that rectangle scaled about the eye's foot point by
+// s(V) = 1 - V / E_b (E = eye - lo), so the window of voxel layer V is the
+// scaled rectangle over [V - 1, V + 1] plus the trilinear margin.  Cells of
+// about `rays` pixels (at most 64 where the pixels are densest), rows of at
+// most kmax 128-byte lines, windows of at most reg_loads 16-byte loads per
+// lane and cap floats.  False when the eye lies within the brick's slab along
+// b, when a ray of the brick's rectangle runs the other way along b, or when
+// no cell shape fits.
+struct PerspCells {
+  double Tf = 0.0, Tg = 0.0;
+  int32_t cf0 = 0, cg0 = 0, ncf = 0, ncg = 0;
+  int32_t pitch = 0, ng = 0;  // window of one voxel layer: row floats (multiple of 4), rows
+  double rays = 0.0;          // mean pixels per cell where they are densest
+};
+bool persp_cells(const Camera& cam, int b, const Box& box, const Rect& rect, double rays, int32_t kmax,
+                 int32_t cap, int32_t reg_loads, PerspCells& out);
+
 // Bytes the window loads of the footprint-cell march request over one brick
 // (a model from the plan: every cell marches every layer its rays cross
 // inside the brick's ownership box, windows placed and clamped as the kernel

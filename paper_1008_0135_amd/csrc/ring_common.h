@@ -72,6 +72,7 @@ __device__ __forceinline__ unsigned lds_addr(const float* p) {
 // along the in-plane axis g; origin (f0, g0) in brick-local voxel indices.
 struct Window {
   int f0, g0;
+  int fb, gb;  // perspective cells: last column and row (origin-relative) the layer's samples can read
 };
 
 // ---------------------------------------------------------------- footprint cells
@@ -134,6 +135,88 @@ __device__ inline FootRuns foot_runs(const MarchArgs& a, const DevBrickView& bvw
     int fl, fh, gl, gh;
     run(bvw.fa0, au, av, ci, fl, fh);
     run(bvw.fb0, bu, bvv, cj, gl, gh);
+    fr.u0 = max(fl, gl);
+    cnt_row = max(0, min(fh, gh) - fr.u0 + 1);
+  }
+  fr.incl = cnt_row;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(fr.incl, off);
+    if (lane >= off) fr.incl += y;
+  }
+  fr.excl = fr.incl - cnt_row;
+  fr.n = uni(__builtin_amdgcn_readlane(fr.incl, 63));
+  return fr;
+}
+
+// Perspective views: the pixels of cell (ci, cj) of a brick are those whose
+// rays cross the brick-local plane b = 0 inside [ci Tf, (ci + 1) Tf) x
+// [cj Tg, (cj + 1) Tg) (persp_plane_point).  Along an image row inside the
+// brick's rectangle each plane coordinate is a monotone function of the
+// column (a ratio of two linear functions whose denominator keeps its sign
+// there), so the cell's pixels of a row are again one run, found by
+// bisection; the rows are those of the cell's corners seen from the eye.
+__device__ inline FootRuns foot_runs_persp(const MarchArgs& a, const DevBrickView& bvw, const DevBrick& br, int ci,
+                                           int cj, int lane) {
+  FootRuns fr;
+  const int b = a.slab_axis == 1 ? 1 : 2, g = 3 - b;
+  double E[3];
+  for (int i = 0; i < 3; ++i) E[i] = a.cam.eye[i] - (double)br.lo[i];
+  const double F0 = (double)ci * bvw.pTf, F1 = (double)(ci + 1) * bvw.pTf;
+  const double G0 = (double)cj * bvw.pTg, G1 = (double)(cj + 1) * bvw.pTg;
+  double vmn = INFINITY, vmx = -INFINITY;
+  for (int q = 0; q < 4; ++q) {
+    double r[3], uq, vq;
+    r[0] = ((q & 1) ? F1 : F0) - E[0];
+    r[g] = ((q & 2) ? G1 : G0) - E[g];
+    r[b] = -E[b];
+    persp_image_uv(a.cam, r, uq, vq);
+    vmn = fmin(vmn, vq);
+    vmx = fmax(vmx, vq);
+  }
+  // rows of the cell inside the brick's rectangle; at most 64 (the plan
+  // bounds a cell's rows well below that)
+  fr.vrow0 = uni(max(bvw.y0, (int)floor(vmn) - 1));
+  const int vlast = uni(min(min(bvw.y0 + bvw.h - 1, (int)ceil(vmx) + 1), fr.vrow0 + 63));
+  const int vrow = fr.vrow0 + lane;
+  int cnt_row = 0;
+  fr.u0 = 0;
+  if (vrow <= vlast) {
+    const int ul = bvw.x0, uh = bvw.x0 + bvw.w;  // columns [ul, uh)
+    auto coord = [&](int u, bool along_f) {
+      double pf, pg;
+      persp_plane_point(a.cam, E, b, g, (double)u, (double)vrow, pf, pg);
+      return along_f ? pf / bvw.pTf : pg / bvw.pTg;
+    };
+    auto run = [&](bool along_f, int cell, int& lo_u, int& hi_u) {
+      const double x0 = coord(ul, along_f), x1 = coord(uh - 1, along_f);
+      if (x1 == x0) {
+        const bool in = x0 >= (double)cell && x0 < (double)(cell + 1);
+        lo_u = in ? ul : uh;
+        hi_u = in ? uh - 1 : ul - 1;
+        return;
+      }
+      const bool inc = x1 > x0;
+      int l = ul, h = uh;  // first column past the cell's near edge
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        const double x = coord(m, along_f);
+        if (inc ? x >= (double)cell : x < (double)(cell + 1)) h = m;
+        else l = m + 1;
+      }
+      lo_u = l;
+      l = ul;
+      h = uh;  // first column past the cell's far edge
+      while (l < h) {
+        const int m = (l + h) >> 1;
+        const double x = coord(m, along_f);
+        if (inc ? x >= (double)(cell + 1) : x < (double)cell) h = m;
+        else l = m + 1;
+      }
+      hi_u = l - 1;
+    };
+    int fl, fh, gl, gh;
+    run(true, ci, fl, fh);
+    run(false, cj, gl, gh);
     fr.u0 = max(fl, gl);
     cnt_row = max(0, min(fh, gh) - fr.u0 + 1);
   }

@@ -77,6 +77,34 @@ __host__ __device__ inline void pixel_ray(const Camera& cam, int u, int v, doubl
   for (int i = 0; i < 3; i++) d[i] = w[i] / len;
 }
 
+// Perspective camera, footprint cells: where the ray of pixel (u, v) crosses
+// the brick-local plane b = 0, with E = eye - lo (brick-local eye) and g the
+// other of axes 2, 3: f = E_f - E_b w_f / w_b, g = E_g - E_b w_g / w_b for the
+// unnormalised direction w = x e1 + y e2 + D e3 of pixel_ray.  One expression
+// everywhere, so every evaluation puts a pixel in the same cell.
+__host__ __device__ inline void persp_plane_point(const Camera& cam, const double E[3], int b, int g, double u,
+                                                  double v, double& pf, double& pg) {
+#pragma clang fp contract(off)
+  const double x = ((u + 0.5) / (double)cam.W - 0.5) * cam.S;
+  const double y = ((v + 0.5) / (double)cam.H - 0.5) * cam.S * (double)cam.H / (double)cam.W;
+  const double wf = x * cam.e1[0] + y * cam.e2[0] + cam.D * cam.e3[0];
+  const double wg = x * cam.e1[g] + y * cam.e2[g] + cam.D * cam.e3[g];
+  const double wb = x * cam.e1[b] + y * cam.e2[b] + cam.D * cam.e3[b];
+  const double t = -E[b] / wb;
+  pf = E[0] + t * wf;
+  pg = E[g] + t * wg;
+}
+
+// Image position (pixel units, centres at integers) of the point at offset r
+// from the eye, for a perspective camera.
+__host__ __device__ inline void persp_image_uv(const Camera& cam, const double r[3], double& u, double& v) {
+  const double z = r[0] * cam.e3[0] + r[1] * cam.e3[1] + r[2] * cam.e3[2];
+  const double x = cam.D * (r[0] * cam.e1[0] + r[1] * cam.e1[1] + r[2] * cam.e1[2]) / z;
+  const double y = cam.D * (r[0] * cam.e2[0] + r[1] * cam.e2[1] + r[2] * cam.e2[2]) / z;
+  u = (x / cam.S + 0.5) * (double)cam.W - 0.5;
+  v = (y / (cam.S * (double)cam.H / (double)cam.W) + 0.5) * (double)cam.H - 0.5;
+}
+
 // Whole-volume ray/box test (slab method against the closed box [0, hi]) and
 // lattice count n = max(0, ceil((t_out - t_in)/step - 1/2)): samples sit at
 // t_k = t_in + (k + 1/2) step for k in [0, n) (paper Sec. 2.4: entry and exit
@@ -176,6 +204,11 @@ struct DevBrickView {
   int32_t blocks_x;    // blocks of footprint cells: blocks along f
   double fa0, fb0;     // footprint cells: cell coordinates (f / Tf, g / Tg) of pixel (0, 0)'s ray on the
                        // brick-local plane b = 0
+  // footprint cells of a perspective view (sized per brick: rays from the eye
+  // are denser on near bricks): cell size on the plane b = 0 and the window
+  // of one voxel layer (row floats, a multiple of 4, and rows)
+  double pTf, pTg;
+  int32_t ppitch, png;
 };
 
 // One layer of the over-composite, front to back.

@@ -3,9 +3,10 @@
 * parity with the FP64 oracle for an unbricked volume, grid bricks and
   longest-axis bricks, near and far eyes, with early termination, and for
   maximum intensity projection;
-* the ring and gather marches give the same image bits (emission-absorption
-  and MIP, virtual and materialised bricks), and macrocell skipping changes no
-  bit;
+* the footprint-cell march (cells sized per brick), the ring march's 8 x 8
+  tiles (one launch per view, or per class of bricks with similar windows) and
+  the gather march give the same image bits (emission-absorption and MIP,
+  virtual and materialised bricks), and macrocell skipping changes no bit;
 * the batched launch gives the same bits as plain renders;
 * table and voxel gradients vs the oracle's exact FP64 gradient;
 * an eye inside the box's circumsphere is rejected.
@@ -43,13 +44,17 @@ def _render(ctx, h, views, W, H, params, eye):
 
 
 def _ctx_with_march(mode):
-    """A context with one march forced; "auto:K": the default march with the
-    perspective ring march's bricks launched in K classes of similar window
-    size (K = 1: one launch per view)."""
+    """A context with one march forced; "auto:K": the default march (footprint
+    cells sized per brick where every brick of the view suits them, else the
+    ring march's 8 x 8 tiles) with the bricks launched in K classes of similar
+    window size (K = 1: one launch per view); "tiles" / "tiles:K": the same
+    with 8 x 8 tiles for every perspective view."""
     import os
     env = {"VR_MARCH": mode}
     if mode.startswith("auto:"):
         env = {"VR_MARCH": "auto", "VR_PERSP_CLASSES": mode[5:]}
+    elif mode.startswith("tiles"):
+        env = {"VR_MARCH": "auto", "VR_PERSP_CELLS": "0", "VR_PERSP_CLASSES": mode[6:] or "3"}
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -92,7 +97,7 @@ def test_persp_parity_with_oracle(ctx, layout, eye, mode):
 
 
 def test_persp_marches_identical_and_skipping_inert():
-    _say("perspective: ring (one launch, or bricks in classes of similar window) / gather bit identity; macrocell skipping inert")
+    _say("perspective: footprint cells / ring tiles (one launch, or bricks in classes of similar window) / gather bit identity; macrocell skipping inert")
     dims = (150, 120, 170)
     vol = synth.cube(*dims, seed=103, n_sources=10, sigma_range=(2.0, 4.0))
     mn, mx = float(vol.min()), float(vol.max())
@@ -101,7 +106,7 @@ def test_persp_marches_identical_and_skipping_inert():
     layouts = {"whole": None, "grid": vr.grid_spec((64, 64, 64), macrocell=8), "kd": vr.kd_spec(7, macrocell=12),
                "mat": vr.grid_spec((75, 60, 85), materialize=True, macrocell=16)}
     imgs = {}
-    for march in ("gather", "auto", "auto:1", "auto:4"):
+    for march in ("gather", "auto", "auto:1", "tiles", "tiles:1"):
         c = _ctx_with_march(march)
         h = vr.vr_volume_create(c, vol, dims)
         for name, spec in layouts.items():
@@ -119,7 +124,7 @@ def test_persp_marches_identical_and_skipping_inert():
         vr.vr_volume_destroy(h)
         vr.vr_destroy(c)
     for k in [k for k in imgs if k[0] == "gather"]:
-        for m in ("auto", "auto:1", "auto:4"):
+        for m in ("auto", "auto:1", "tiles", "tiles:1"):
             a, b = imgs[k], imgs[(m,) + k[1:]]
             assert np.array_equal(a, b), (m, k, float(np.abs(a - b).max()))
     ref = oracle.render(vol, tables["colour"], views, 160, 136, mn, mx, tau=0.99, bricks={"grid": (64, 64, 64)},
