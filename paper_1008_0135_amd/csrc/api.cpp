@@ -381,6 +381,7 @@ int vr_create(int device, vr_ctx** out) {
   if (const char* m = std::getenv("VR_FOOT_CLIP")) ctx->foot_clip = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_PERSP_CLASSES")) ctx->persp_classes = std::max(1, std::min(4, std::atoi(m)));
   if (const char* m = std::getenv("VR_PERSP_CELLS")) ctx->persp_cells = std::atoi(m) != 0 ? 1 : 0;
+  if (const char* m = std::getenv("VR_PERSP_KMAX")) ctx->persp_kmax = std::max(1, std::min(4, std::atoi(m)));
   if (const char* m = std::getenv("VR_CELLS_WPB")) {
     const int k = std::atoi(m);
     ctx->cells_wpb = (k == 1 || k == 2 || k == 4) ? k : 0;

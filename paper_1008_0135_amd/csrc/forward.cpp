@@ -231,7 +231,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         rc.y0 = b.y0;
         rc.w = b.w;
         rc.h = b.h;
-        all = persp_cells(cams[v], tryax, vol->part.boxes[b.brick], rc, ctx->foot_rays, ctx->foot_kmax, kRingCap,
+        all = persp_cells(cams[v], tryax, vol->part.boxes[b.brick], rc, ctx->foot_rays, ctx->persp_kmax, kRingCap,
                           kRingRegLoads, pcs[i]);
       }
       if (all) {

@@ -128,6 +128,7 @@ struct vr_ctx {
   double persp_fit = 0.95;    // perspective ring march: fraction of tiles whose windows the slot holds
   int32_t persp_classes = 3;  // perspective ring march: launches per view, bricks grouped by window size
   int32_t persp_cells = 1;    // perspective views: footprint cells sized per brick (0: 8 x 8 pixel tiles)
+  int32_t persp_kmax = 1;     // perspective footprint cells: window rows of at most this many 128-byte lines
   // autotune cache: render shapes -> (tile edge, LDS budget, march mode)
   struct TuneEntry {
     std::string key;
