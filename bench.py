@@ -368,16 +368,14 @@ def brick_transparent(bmin, bmax, tf, vmin, vmax):
 def traffic_model(config, twin):
     """Bytes the footprint-cell march's window loads request per launch on the
     config's views, from the host plan (vr_plan_cells; no GPU): the rendered
-    bricks' own voxels, the line-granular union of the windows (ghost layers,
-    halo beyond the bricks, cells straddling their sides), the sum of the
-    windows (halo shared by neighbouring cells), the same in 64-byte segments
-    and 128-byte lines (partly used lines), and each with the window columns
-    clipped to the brick's reach as the kernel loads them."""
+    bricks' own voxels, the line-granular union of the windows (ghost layers
+    and the rows two bricks' windows share), the sum of the windows (halo
+    shared by neighbouring cells), the same in 64-byte segments and in 128-byte
+    lines (partly used lines)."""
     cfg = synth.CONFIGS[config]
     W, H = cfg["image"]
     spec = vr.grid_spec(cfg["bricks"], twin=twin)
-    keys = ["own_bytes", "union_bytes", "window_bytes", "segment_bytes", "line_bytes", "clipped_window_bytes",
-            "clipped_segment_bytes", "clipped_line_bytes"]
+    keys = ["own_bytes", "union_bytes", "window_bytes", "segment_bytes", "line_bytes"]
     tot = {k: 0.0 for k in keys}
     views = synth.random_views(cfg["nviews"], cfg["view_seed"])
     for R in views:

@@ -511,9 +511,6 @@ int vr_count_samples(const int64_t dims[3], const vr_view *view, double step, in
 typedef struct {
   double own_bytes, union_bytes, window_bytes, line_bytes;
   double segment_bytes;          /* the rows of line_bytes counted in 64-byte segments */
-  double clipped_window_bytes, clipped_line_bytes, clipped_segment_bytes;  /* window rows clipped to the
-                                                          brick's voxels and one more on each side along axis 1
-                                                          (as the march loads them) */
   double cells, cell_layers;     /* cells with samples; voxel layers loaded over all cells */
   double rays_per_cell;          /* mean pixels per cell of the chosen shape */
   double Tf, Tg;                 /* cell size on the slab plane, voxels */

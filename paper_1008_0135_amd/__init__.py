@@ -84,8 +84,7 @@ class vr_tune_result(C.Structure):
 
 class vr_cell_traffic(C.Structure):
     _fields_ = [("own_bytes", C.c_double), ("union_bytes", C.c_double), ("window_bytes", C.c_double),
-                ("line_bytes", C.c_double), ("segment_bytes", C.c_double), ("clipped_window_bytes", C.c_double),
-                ("clipped_line_bytes", C.c_double), ("clipped_segment_bytes", C.c_double), ("cells", C.c_double), ("cell_layers", C.c_double),
+                ("line_bytes", C.c_double), ("segment_bytes", C.c_double), ("cells", C.c_double), ("cell_layers", C.c_double),
                 ("rays_per_cell", C.c_double), ("Tf", C.c_double), ("Tg", C.c_double), ("axis", C.c_int32),
                 ("row_floats", C.c_int32), ("rows", C.c_int32), ("twin", C.c_int32)]
 

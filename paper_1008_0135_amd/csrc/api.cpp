@@ -378,7 +378,6 @@ int vr_create(int device, vr_ctx** out) {
   }
   if (const char* m = std::getenv("VR_FOOT_PAD")) ctx->foot_pad = std::max(0, std::min(32, std::atoi(m)));
   if (const char* m = std::getenv("VR_FOOT_KMAX")) ctx->foot_kmax = std::max(1, std::min(4, std::atoi(m)));
-  if (const char* m = std::getenv("VR_FOOT_CLIP")) ctx->foot_clip = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_PERSP_CLASSES")) ctx->persp_classes = std::max(1, std::min(4, std::atoi(m)));
   if (const char* m = std::getenv("VR_PERSP_CELLS")) ctx->persp_cells = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_PERSP_KMAX")) ctx->persp_kmax = std::max(1, std::min(4, std::atoi(m)));
@@ -1118,9 +1117,6 @@ int vr_plan_cells(const int64_t dims[3], const vr_brick_spec* spec, const vr_vie
   out->window_bytes = t.win;
   out->line_bytes = t.line;
   out->segment_bytes = t.seg;
-  out->clipped_window_bytes = t.clip_win;
-  out->clipped_line_bytes = t.clip_line;
-  out->clipped_segment_bytes = t.clip_seg;
   out->cells = t.cells;
   out->cell_layers = t.layers;
   out->rays_per_cell = fs.rays;

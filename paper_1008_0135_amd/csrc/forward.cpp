@@ -473,7 +473,6 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
       a.ring_slot = fs.slot;
       a.ring_nslots = fs.nslots;
       a.ring_reg = fs.reg;
-      a.foot_clip = ctx->foot_clip;
       ring_wpb = fs.reg && ctx->cells_wpb > 0 ? ctx->cells_wpb : fs.wpb;
       if (fs.reg && ctx->cells_waves > 0) {
         // at most cells_waves wavefronts per compute unit: reserve LDS so that
@@ -600,7 +599,6 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         ac.ring_slot = slot;
         ac.ring_nslots = 2;
         ac.ring_reg = 1;
-        ac.foot_clip = ctx->foot_clip;
         ac.foot_nf = mpitch;
         ac.foot_ng = mng;
         int32_t waves = 0;

@@ -55,6 +55,7 @@ struct CellRay {
   float px, py, pz, sx, sy, sz;
 };
 
+template <bool PERSP>
 __device__ __forceinline__ CellRay cell_ray(const MarchArgs& a, const DevBrickView& bvw, const DevBrick& br,
                                             const FootRuns& fr, int lane) {
   CellRay r;
@@ -67,8 +68,14 @@ __device__ __forceinline__ CellRay cell_ray(const MarchArgs& a, const DevBrickVi
   }
   const int lx = u - bvw.x0, ly = v - bvw.y0;
   const bool inrect = lx >= 0 && lx < bvw.w && ly >= 0 && ly < bvw.h;
-  double o[3], d[3];
-  pixel_ray(a.cam, u, v, o, d);  // parallel rays: the view direction
+  double o[3], dl[3];
+  const double* d = a.cam.e3;  // parallel rays: the view direction
+  if constexpr (PERSP) {
+    pixel_ray(a.cam, u, v, o, dl);
+    d = dl;
+  } else {
+    pixel_origin(a.cam, u, v, o);
+  }
   r.cnt = 0;
   r.px = r.py = r.pz = 0.f;
   r.dst = a.carry ? a.img + (int64_t)v * a.cam.W + u : a.img + bvw.img_off + (int64_t)ly * bvw.w + lx;
@@ -157,7 +164,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const FootRuns fr = PERSP ? foot_runs_persp(a, bvw, br, ci, cj, lane) : foot_runs(a, bvw, ci, cj, lane);
   // pixels past the 64th of a cell are marched by k_march_ring_ovf afterwards
   if (fr.n > 64 && lane == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile * 8;
-  const CellRay r = cell_ray(a, bvw, br, fr, lane);
+  const CellRay r = cell_ray<PERSP>(a, bvw, br, fr, lane);
 
   // ---- frame: b = slab axis (axis 2 if BY, else axis 3), g = the other, f = axis 1
   const float pb = BY ? r.py : r.pz, sb = BY ? r.sy : r.sz;
@@ -238,27 +245,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int nmine = rl < R ? (NG - rl + R - 1) / R : 0;
   const unsigned row_off = (unsigned)(rl * sG) * 4u;
   const unsigned step_off = (unsigned)(R * sG) * 4u;
-  // columns a sample can read: the brick's voxels along f and one more on
-  // each side (a sample's cell index is clamped only at the volume's faces)
-  const int extF = br.hi[0] - br.lo[0];
-  const bool clip = a.foot_clip != 0;
   v4f rr[kRingRegLoads];
   auto rload = [&](int V, const Window& w) {
     const char* gb = (const char*)unip(gbase + ((int64_t)V * sB + (int64_t)w.g0 * sG + w.f0));
-    // a lane whose 16 bytes lie wholly outside those columns reads the
-    // nearest chunk inside them instead (a line fetched anyway); what it
-    // leaves in its LDS place is never sampled
     if constexpr (PERSP) {
       // the window is sized for the brick's widest layer: this layer's
-      // columns and rows end earlier
-      int kc = c4l;
-      if (clip) {
-        const int k_lo = uni(max(0, (-1 - w.f0) >> 2));
-        const int k_hi = uni(max(k_lo, min(min(nf4 - 1, (extF + 1 - w.f0) >> 2), w.fb >> 2)));
-        kc = min(max(c4l, k_lo), k_hi);
-      }
-      // rows past this layer's last read that row again (lines fetched
-      // anyway); the predicate stays the cell's, so no load waits on another
+      // columns and rows end earlier.  A lane past them reads the last chunk
+      // or row the layer needs instead (lines fetched anyway; what it leaves
+      // in LDS is never sampled), so the predicate stays the cell's and no
+      // load waits on another.
+      const int kc = min(c4l, uni(min(nf4 - 1, w.fb >> 2)));
       const unsigned col_off = (unsigned)kc * 16u;
       const unsigned last_off = (unsigned)(min(NG - 1, w.gb) * sG) * 4u;
 #pragma unroll
@@ -267,13 +263,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
           rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (min(row_off + (unsigned)i * step_off, last_off) +
                                                                           col_off));
     } else {
-      int kc = c4l;
-      if (clip) {
-        const int k_lo = uni(max(0, (-1 - w.f0) >> 2));
-        const int k_hi = uni(max(k_lo, min(nf4 - 1, (extF + 1 - w.f0) >> 2)));
-        kc = min(max(c4l, k_lo), k_hi);
-      }
-      const unsigned lane_off = row_off + (unsigned)kc * 16u;
+      const unsigned lane_off = row_off + (unsigned)c4l * 16u;
 #pragma unroll
       for (int i = 0; i < kRingRegLoads; ++i)
         if (i < nmine) rr[i] = *(const v4f __attribute__((address_space(1)))*)(gb + (lane_off + (unsigned)i * step_off));
@@ -353,7 +343,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
   block_cell(a, bvw, t, wave, ci, cj);
   const FootRuns fr = foot_runs(a, bvw, ci, cj, lane);
   if (fr.n > 64 && lane == 0) a.ovf_tiles[atomicAdd(a.ovf_count, 1u)] = tile * 8 + wave;
-  const CellRay r = cell_ray(a, bvw, br, fr, lane);
+  const CellRay r = cell_ray<false>(a, bvw, br, fr, lane);
 
   const float pb = BY ? r.py : r.pz, sb = BY ? r.sy : r.sz;
   const int cloB = BY ? br.clo[1] : br.clo[2], chiB = BY ? br.chi[1] : br.chi[2];

@@ -742,10 +742,14 @@ void foot_traffic(const Camera& cam, const FootShape& fs, const Box& box, const 
   for (int i = 0; i < 3; i++) ext[i] = box.hi[i] - box.lo[i];
   t.own += 4.0 * (double)(ext[0] + (box.closed[0] ? 1 : 0)) * (double)(ext[1] + (box.closed[1] ? 1 : 0)) *
            (double)(ext[2] + (box.closed[2] ? 1 : 0));
-  // clamps of the local cell index, as on the device: global [0, n - 2] - lo
-  const int64_t cloF = -box.lo[0], chiF = n[0] - 2 - box.lo[0];
-  const int64_t cloG = -box.lo[g], chiG = n[g] - 2 - box.lo[g];
-  const int64_t cloB = -box.lo[b], chiB = n[b] - 2 - box.lo[b];
+  // clamps of the local cell index, as on the device: the brick's stored
+  // range (its box and one ghost voxel each side, inside the volume) - lo, the
+  // last cell one short of the last stored voxel
+  int64_t slo[3], shi[3];
+  stored_box(box, n, slo, shi);
+  const int64_t cloF = slo[0] - box.lo[0], chiF = shi[0] - 1 - box.lo[0];
+  const int64_t cloG = slo[g] - box.lo[g], chiG = shi[g] - 1 - box.lo[g];
+  const int64_t cloB = slo[b] - box.lo[b], chiB = shi[b] - 1 - box.lo[b];
   const int64_t pitch = (fs.nf + 3) & ~3;
   const int64_t NG = std::min<int64_t>(fs.ng, chiG + 2 - cloG);
   const int64_t sG = g == 1 ? n[0] : n[0] * n[1], sB = b == 1 ? n[0] : n[0] * n[1];
@@ -787,20 +791,11 @@ void foot_traffic(const Camera& cam, const FootShape& fs, const Box& box, const 
         const int64_t g0 = std::max(cloG, std::min(glo, chiG + 2 - NG));
         t.win += 4.0 * (double)(pitch * NG);
         const int64_t iv = V - v_lo;
-        // the columns of the window inside the brick's reach along axis 1 (its
-        // voxels and one more on each side), as the kernel clips its loads
-        const int64_t cf_lo = std::max(f0, (int64_t)-1), cf_hi = std::min(f0 + pitch, ext[0] + 2);
         for (int64_t r = 0; r < NG; r++) {
           const int64_t row = box.lo[0] + (box.lo[g] + g0 + r) * sG + (box.lo[b] + V) * sB;
           const int64_t a0 = row + f0;
           t.line += 128.0 * (double)((a0 + pitch - 1) / 32 - a0 / 32 + 1);
           t.seg += 64.0 * (double)((a0 + pitch - 1) / 16 - a0 / 16 + 1);
-          if (cf_hi > cf_lo) {
-            const int64_t c0 = row + cf_lo, c1 = row + cf_hi;
-            t.clip_win += 4.0 * (double)(c1 - c0);
-            t.clip_line += 128.0 * (double)((c1 - 1) / 32 - c0 / 32 + 1);
-            t.clip_seg += 64.0 * (double)((c1 - 1) / 16 - c0 / 16 + 1);
-          }
           const int64_t ir = g0 + r - g_base;
           if (iv < 0 || iv >= nv || ir < 0 || ir >= nrow) continue;
           const size_t k = (size_t)(iv * nrow + ir);

@@ -194,7 +194,6 @@ struct FootTraffic {
   double win = 0.0;     // sum over cells and loaded voxel layers of rows x pitch x 4
   double line = 0.0;    // the same rows counted in whole 128-byte lines
   double seg = 0.0;     // ... in 64-byte segments
-  double clip_win = 0.0, clip_line = 0.0, clip_seg = 0.0;  // rows clipped to the brick's voxels +- 1 along axis 1
   double cells = 0.0;   // cells with at least one layer
   double layers = 0.0;  // voxel layers loaded, summed over cells
 };

@@ -249,8 +249,6 @@ struct MarchArgs {
   int32_t ring_reg;      // footprint cells, two slots: 1 = the layer after next travels through
                          // registers while a layer is sampled (k_march_cells; at most
                          // kRingRegLoads loads per lane per layer)
-  int32_t foot_clip;     // k_march_cells: window columns outside the brick's voxels (and one ghost
-                         // voxel each side) are not fetched
   int32_t mask_axis;     // axis of the channel mask (2, or 1 in the permuted copy)
   const float* mask;     // channel weights along mask_axis (global indices), or null
   int32_t tile_order;    // ring march: tiles of a brick numbered along rows (0), down columns (1),

@@ -205,17 +205,13 @@ def test_cell_traffic_model_terms_ordered():
     """The window-traffic model of the footprint-cell march (host only): the
     rendered bricks' own voxels are the cube's, each term adds a cost to the
     one before (lines of all windows >= 64-byte segments >= exact window bytes
-    >= the line-granular union of the windows >= own voxels), and clipping the
-    windows to the brick's reach never adds bytes."""
+    >= the line-granular union of the windows >= own voxels)."""
     dims = (512, 512, 384)
     spec = vr.grid_spec((128, 128, 128))
     for R in synth.random_views(5, 77) + [np.eye(3)]:
         t = vr.vr_plan_cells(dims, spec, vr.make_view(R, 256, 256))
         assert t.own_bytes == 4.0 * dims[0] * dims[1] * dims[2]
         assert t.own_bytes <= t.union_bytes <= t.window_bytes <= t.segment_bytes <= t.line_bytes
-        assert t.clipped_window_bytes <= t.window_bytes
-        assert t.clipped_segment_bytes <= t.segment_bytes and t.clipped_line_bytes <= t.line_bytes
-        assert t.clipped_window_bytes <= t.clipped_segment_bytes <= t.clipped_line_bytes
         assert 0 < t.rays_per_cell <= 64 and t.axis in (2, 3) and t.row_floats % 4 == 0 and t.rows > 0
         assert t.cells > 0 and t.cell_layers > t.cells
     # a permuted view is planned on the copy, with the copy's axes
