@@ -390,6 +390,7 @@ int vr_create(int device, vr_ctx** out) {
     const double f = std::atof(m);
     if (f >= 0.3 && f <= 1.0) ctx->persp_fit = f;
   }
+  if (const char* m = std::getenv("VR_FOOT_MAXPX")) ctx->foot_maxpx = std::max(16, std::min(4096, std::atoi(m)));
   if (const char* m = std::getenv("VR_FOOT_RAYS")) {
     const double r = std::atof(m);
     if (r >= 16.0 && r <= 64.0) ctx->foot_rays = r;

@@ -33,7 +33,7 @@ constexpr int32_t kLdsPerCu = 160 * 1024;
 }  // namespace
 
 bool pick_foot(const Camera& cam, const int64_t n[3], int32_t M, bool plain, bool reg_on, int32_t nslots,
-               double rays, int32_t pad, int32_t kmax, FootShape& fs) {
+               double rays, int32_t pad, int32_t kmax, FootShape& fs, int32_t max_px) {
   // register-staged cells: a lane's offset inside a window's rows (at most
   // kRingRegLoads instructions of up to 16 rows) must stay below 4 GiB
   const int64_t row_stride = std::max(n[0], n[0] * n[1]);
@@ -41,7 +41,7 @@ bool pick_foot(const Camera& cam, const int64_t n[3], int32_t M, bool plain, boo
   const bool two = rays > 64.0;  // two pixels per lane: half the wavefronts, twice the window loads
   const int32_t rw = two ? kRingRegWaves / 2 : kRingRegWaves;
   return choose_foot(cam, kRingCap, M, kRingMaxWaves, reg ? rw : kRingWantWaves, rays, plain ? nslots : 3, fs, pad,
-                     kmax, reg ? rw : 0, two ? 2 * kRingRegLoads : kRingRegLoads);
+                     kmax, reg ? rw : 0, two ? 2 * kRingRegLoads : kRingRegLoads, max_px);
 }
 
 // Plan one view of a bricked volume: rectangles, culling (empty rectangle or
@@ -232,7 +232,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
         rc.w = b.w;
         rc.h = b.h;
         all = persp_cells(cams[v], tryax, vol->part.boxes[b.brick], rc, ctx->foot_rays, ctx->persp_kmax, kRingCap,
-                          kRingRegLoads, pcs[i]);
+                          kRingRegLoads, pcs[i], ctx->foot_maxpx);
       }
       if (all) {
         axis = tryax;
@@ -302,7 +302,7 @@ int render_forward(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t nv
     if (extras || cams[v].persp || !ctx->foot || !(mode == 0 || mode == 3) || tw != 8) continue;
     FootShape fs;
     if (!pick_foot(cams[v], vol->n, base.M, plain_ring, ctx->ring_reg > 0, ctx->ring_nslots, ctx->foot_rays,
-                   ctx->foot_pad, ctx->foot_kmax, fs))
+                   ctx->foot_pad, ctx->foot_kmax, fs, ctx->foot_maxpx))
       continue;
     Box whole;
     for (int i = 0; i < 3; i++) {

@@ -46,7 +46,7 @@ struct ForwardExtras {
 // cells of about `rays` pixels with window rows of at most kmax 128-byte
 // lines (+ pad floats).  False when the view has no suitable slab axis.
 bool pick_foot(const Camera& cam, const int64_t n[3], int32_t M, bool plain, bool reg_on, int32_t nslots,
-               double rays, int32_t pad, int32_t kmax, FootShape& fs);
+               double rays, int32_t pad, int32_t kmax, FootShape& fs, int32_t max_px = 0);
 
 void plan_bricked_view(const vr_volume* vol, const Camera& cam, const vr_params* p, int32_t tile_w, const float* tf,
                        int32_t M, double vmin, double vmax, ViewPlan& vp, bool waves = false);

@@ -457,13 +457,14 @@ int32_t window_loads(int32_t pitch, int32_t ng) {
 
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
                  int32_t nslots_rule, FootShape& out, int32_t pad, int32_t kmax, int32_t reg_waves,
-                 int32_t reg_loads) {
+                 int32_t reg_loads, int32_t max_px_in) {
   if (cam.persp) return false;
   const double p = cam.S / (double)cam.W;
   const double* e1 = cam.e1;
   const double* e2 = cam.e2;
   const double* d = cam.e3;
-  const int32_t max_px = rays > 64.0 ? 128 : 64;  // pixels a wavefront marches: one or two per lane
+  // pixels a wavefront marches: one or two per lane
+  const int32_t max_px = max_px_in > 0 ? max_px_in : (rays > 64.0 ? 128 : 64);
   double best = INFINITY;
   bool found = false;
   for (int b = 1; b <= 2; b++) {
@@ -620,7 +621,7 @@ void foot_cells(const Camera& cam, const FootShape& fs, const Box& box, int32_t&
 }
 
 bool persp_cells(const Camera& cam, int b, const Box& box, const Rect& rect, double rays, int32_t kmax,
-                 int32_t cap, int32_t reg_loads, PerspCells& out) {
+                 int32_t cap, int32_t reg_loads, PerspCells& out, int32_t max_px) {
   if (!cam.persp || rect.w <= 0 || rect.h <= 0) return false;
   const int g = 3 - b;
   double E[3], ext[3];
@@ -699,10 +700,10 @@ bool persp_cells(const Camera& cam, int b, const Box& box, const Rect& rect, dou
     int32_t most = 0;
     for (int it = 0; it < 8; it++) {
       most = foot_max_pixels(su_f / Tf, sv_f / Tf, su_g / Tg, sv_g / Tg);
-      if (most <= 64 || Tg <= 1.0) break;
-      Tg = std::max(1.0, Tg * std::min(0.98, 64.0 / most));
+      if (most <= max_px || Tg <= 1.0) break;
+      Tg = std::max(1.0, Tg * std::min(0.98, (double)max_px / most));
     }
-    if (most > 64) continue;  // too many pixels even in the thinnest cells of this width
+    if (most > max_px) continue;  // too many pixels even in the thinnest cells of this width
     // the cells of the grid's first and last columns and rows reach up to
     // two cells past the brick's box: their distance from the foot point
     const double wf = 2.0 * std::max(std::fabs(flo - 2.0 * Tf - E[0]), std::fabs(fhi + 2.0 * Tf - E[0])) /

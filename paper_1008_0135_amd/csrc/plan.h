@@ -141,10 +141,13 @@ struct FootShape {
 // three (the plain march).  reg_waves > 0: the plain march stages the layer
 // after next in registers wherever a layer's window takes at most reg_loads
 // 16-byte loads per lane; two slots then, and at most reg_waves wavefronts
-// per compute unit (the registers it takes).  False when no axis suits.
+// per compute unit (the registers it takes).  max_px: the cell sizing keeps
+// the pixels of a cell at most this (0: 64, or 128 for more than 64 rays; the
+// pixels past a wavefront's 64 are marched by gathers).  False when no axis
+// suits.
 bool choose_foot(const Camera& cam, int32_t cap, int32_t M, int32_t max_waves, int32_t want_waves, double rays,
                  int32_t nslots_rule, FootShape& out, int32_t pad = 0, int32_t kmax = 4, int32_t reg_waves = 0,
-                 int32_t reg_loads = 0);
+                 int32_t reg_loads = 0, int32_t max_px = 0);
 // Blocks of footprint cells for the chosen cell shape: blk_f x blk_g cells
 // (at most 8) marched by one workgroup with one window per voxel layer, the
 // choice with the fewest 128-byte lines per ray and layer, counting the cells
@@ -179,7 +182,7 @@ struct PerspCells {
   double rays = 0.0;          // mean pixels per cell where they are densest
 };
 bool persp_cells(const Camera& cam, int b, const Box& box, const Rect& rect, double rays, int32_t kmax,
-                 int32_t cap, int32_t reg_loads, PerspCells& out);
+                 int32_t cap, int32_t reg_loads, PerspCells& out, int32_t max_px = 64);
 
 // Bytes the window loads of the footprint-cell march request over one brick
 // (a model from the plan: every cell marches every layer its rays cross

@@ -258,6 +258,8 @@ def _ctx_with_march(mode):
         env = {"VR_MARCH": "ring", "VR_FOOT_BLOCK": mode[3:]}
     elif mode.startswith("ring:"):  # the ring march with tiles numbered in another order
         env = {"VR_MARCH": "ring", "VR_TILE_ORDER": mode[5:]}
+    elif mode == "ovf":  # cells of about 64 pixels, not shrunk: many pass their 64th pixel to the gather kernel
+        env = {"VR_MARCH": "ring", "VR_FOOT_RAYS": "64", "VR_FOOT_MAXPX": "4096"}
     else:
         env = {"VR_MARCH": mode}
     old = {k: os.environ.get(k) for k in env}
@@ -274,7 +276,9 @@ def _ctx_with_march(mode):
 
 def test_marches_identical():
     """The LDS-slab, ring (two or three LDS slots per wavefront) and gather
-    marches compute the same samples in the same order."""
+    marches compute the same samples in the same order; so do the footprint
+    cells when many of them hold more than 64 pixels (the rest marched by the
+    overflow gather kernel)."""
     _say("slab / ring / gather marches: bit-identical images")
     dims = (160, 144, 176)
     vol = synth.cube(*dims, seed=27, n_sources=15, sigma_range=(2.0, 5.0))
@@ -285,7 +289,7 @@ def test_marches_identical():
     layouts = {"grid": vr.grid_spec((48, 64, 80)), "mat": vr.grid_spec((48, 64, 80), materialize=True),
                "kd": vr.kd_spec(7), "whole": None, "wide": vr.grid_spec((128, 72, 88))}
     for mode in ("gather", "slab", "ring", "ring2", "ring2reg2", "ring2mem", "ring3", "blk0", "blk2x2", "blk8x1",
-                 "blk1x4"):
+                 "blk1x4", "ovf"):
         _say(f"  march {mode}")
         c = _ctx_with_march(mode)
         h = _upload(c, vol)
@@ -305,7 +309,8 @@ def test_marches_identical():
     for name in layouts:
         for W in (96, 333):
             a = imgs[("gather", name, W)]
-            for mode in ("slab", "ring", "ring2", "ring2reg2", "ring2mem", "ring3", "blk0", "blk2x2", "blk8x1", "blk1x4"):
+            for mode in ("slab", "ring", "ring2", "ring2reg2", "ring2mem", "ring3", "blk0", "blk2x2", "blk8x1", "blk1x4",
+                         "ovf"):
                 b = imgs[(mode, name, W)]
                 assert np.array_equal(a, b), (mode, name, W, float(np.abs(a - b).max()))
     mn, mx = float(vol.min()), float(vol.max())

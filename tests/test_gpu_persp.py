@@ -48,13 +48,17 @@ def _ctx_with_march(mode):
     cells sized per brick where every brick of the view suits them, else the
     ring march's 8 x 8 tiles) with the bricks launched in K classes of similar
     window size (K = 1: one launch per view); "tiles" / "tiles:K": the same
-    with 8 x 8 tiles for every perspective view."""
+    with 8 x 8 tiles for every perspective view; "ovf": cells of about 64
+    pixels not shrunk to 64 at most (the overflow gather kernel takes the
+    rest)."""
     import os
     env = {"VR_MARCH": mode}
     if mode.startswith("auto:"):
         env = {"VR_MARCH": "auto", "VR_PERSP_CLASSES": mode[5:]}
     elif mode.startswith("tiles"):
         env = {"VR_MARCH": "auto", "VR_PERSP_CELLS": "0", "VR_PERSP_CLASSES": mode[6:] or "3"}
+    elif mode == "ovf":  # cells of about 64 pixels, not shrunk: many pass their 64th pixel to the gather kernel
+        env = {"VR_MARCH": "auto", "VR_FOOT_RAYS": "64", "VR_FOOT_MAXPX": "4096"}
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -106,7 +110,7 @@ def test_persp_marches_identical_and_skipping_inert():
     layouts = {"whole": None, "grid": vr.grid_spec((64, 64, 64), macrocell=8), "kd": vr.kd_spec(7, macrocell=12),
                "mat": vr.grid_spec((75, 60, 85), materialize=True, macrocell=16)}
     imgs = {}
-    for march in ("gather", "auto", "auto:1", "tiles", "tiles:1"):
+    for march in ("gather", "auto", "auto:1", "tiles", "tiles:1", "ovf"):
         c = _ctx_with_march(march)
         h = vr.vr_volume_create(c, vol, dims)
         for name, spec in layouts.items():
@@ -124,7 +128,7 @@ def test_persp_marches_identical_and_skipping_inert():
         vr.vr_volume_destroy(h)
         vr.vr_destroy(c)
     for k in [k for k in imgs if k[0] == "gather"]:
-        for m in ("auto", "auto:1", "tiles", "tiles:1"):
+        for m in ("auto", "auto:1", "tiles", "tiles:1", "ovf"):
             a, b = imgs[k], imgs[(m,) + k[1:]]
             assert np.array_equal(a, b), (m, k, float(np.abs(a - b).max()))
     ref = oracle.render(vol, tables["colour"], views, 160, 136, mn, mx, tau=0.99, bricks={"grid": (64, 64, 64)},
