@@ -328,11 +328,13 @@ def bench_fwd_bwd(ctx, stream):
             "cell_layers_per_group": sorted(set(lay))}
 
 
-def bench_variants(ctx, h, dims, views_R, W, H, stream):
+def bench_variants(ctx, h, dims, views_R, W, H, stream, plan=None):
     """The same cube and views rendered with a perspective camera (eye at twice
     the half diagonal from the centre: a 53-degree field of view at the
     box-diagonal extent), as a maximum intensity projection, and with the
-    opacity test over the whole ray (bricks in front-to-back waves)."""
+    opacity test over the whole ray (bricks in front-to-back waves).  plan =
+    (brick size, brick records, table, vmin, vmax): the perspective leg then
+    also reports its march's HBM roofline fraction."""
     import torch
     n = np.array(dims, np.float64)
     eye = float(np.sqrt(((n - 1) ** 2).sum()))  # 2 x half diagonal
@@ -347,7 +349,46 @@ def bench_variants(ctx, h, dims, views_R, W, H, stream):
         log(f"{name}: {ms / len(views):.3f} ms/frame, {nominal / ms / 1e6:.1f} Gsamples/s")
         res[name] = {"ms_per_frame": round(ms / len(views), 4), "gsamples_per_s": round(nominal / ms / 1e6, 3),
                      "nominal_samples_per_frame": int(nominal // len(views))}
+        if name == "perspective" and plan is not None:
+            # the march stage of one call (all its launches), per view
+            vr.vr_set_profiling(ctx, True)
+            vr.vr_render(ctx, h, views, params, out, stream)
+            st, _ = vr.vr_stage_times(ctx)
+            vr.vr_set_profiling(ctx, False)
+            march = st[vr.VR_STAGE_MARCH] / len(views)
+            alg = float(np.mean([b + i for b, i, _ in alg_bytes_per_view(dims, plan[0], plan[1], views, *plan[2:])]))
+            ach = alg / (march * 1e-3) / 1e9
+            res[name]["march_ms_per_view"] = round(march, 4)
+            res[name]["roofline"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": int(alg),
+                                     "alg_bytes": "interior voxels of the marched bricks x 4 B + brick images x 16 B"}
     res["perspective"]["eye_dist"] = round(eye, 2)
+    return res
+
+
+def alg_bytes_per_view(dims, brick_size, bricks, views, tf, vmin, vmax):
+    """Per view (brick bytes, image bytes, bricks): the interior voxels of the
+    bricks the renderer marches (non-empty rectangle, not transparent under the
+    table) x 4 B and their brick images x 16 B, from the host plan (the same
+    rectangles and the same transparent-brick test as the renderer)."""
+    spec = vr.grid_spec(brick_size)
+    res = []
+    for v in views:
+        rects, _ = vr.vr_plan_view(dims, spec, v)
+        brick_bytes = 0
+        img_bytes = 0
+        count = 0
+        for b, (x0, y0, w, hh) in enumerate(rects):
+            d = bricks[b]
+            if w == 0 or hh == 0 or brick_transparent(d.vmin, d.vmax, tf, vmin, vmax):
+                continue
+            vox = 1
+            for i in range(3):
+                vox *= (d.hi[i] - d.lo[i] + (1 if d.closed[i] else 0))
+            brick_bytes += 4 * vox
+            img_bytes += 16 * w * hh
+            count += 1
+        res.append((brick_bytes, img_bytes, count))
     return res
 
 
@@ -502,24 +543,7 @@ def main():
     # march launches: per-view algorithmic bytes (interior voxels of the bricks
     # rendered + brick-image writes), from the host plan (the same rectangles and
     # the same transparent-brick test as the renderer; no kernel runs for it)
-    imgs_per_view = []
-    spec = vr.grid_spec(cfg["bricks"])
-    for v in views:
-        rects, _ = vr.vr_plan_view((n1, n2, n3), spec, v)
-        brick_bytes = 0
-        img_bytes = 0
-        count = 0
-        for b, (x0, y0, w, hh) in enumerate(rects):
-            d = bricks[b]
-            if w == 0 or hh == 0 or brick_transparent(d.vmin, d.vmax, tf, vmin, vmax):
-                continue
-            vox = 1
-            for i in range(3):
-                vox *= (d.hi[i] - d.lo[i] + (1 if d.closed[i] else 0))
-            brick_bytes += 4 * vox
-            img_bytes += 16 * w * hh
-            count += 1
-        imgs_per_view.append((brick_bytes, img_bytes, count))
+    imgs_per_view = alg_bytes_per_view((n1, n2, n3), cfg["bricks"], bricks, views, tf, vmin, vmax)
 
     # one view per call, before the timed region: the spread of the march time
     # over view directions (the paper reports min / average / max over orientations)
@@ -615,7 +639,7 @@ def main():
 
     legs = set() if args.no_extras else set(args.legs.split(","))
     if "variants" in legs:
-        result.update(bench_variants(ctx, h, (n1, n2, n3), views_R, W, H, stream))
+        result.update(bench_variants(ctx, h, (n1, n2, n3), views_R, W, H, stream, (cfg["bricks"], bricks, tf, vmin, vmax)))
     if "tf_suppress" in legs:
         result["tf_suppress"] = bench_tf_suppress(ctx, h, (n1, n2, n3), views_R, W, H, vmin, vmax, stream)
     if "batched" in legs:
