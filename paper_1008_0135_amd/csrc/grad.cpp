@@ -312,16 +312,28 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
   VR_TRY(upload_tables(ctx, s, host.data(), host.size(), &dtab));
   MarchArgs a0 = base;
   a0.ntiles = ntiles_of(W, H, base.tile_w, base.tile_h);
-  int nblocks_max = std::max(bwd_blocks(a0), 1);
-  for (const auto& rv : st->vs)
-    if (rv.ring) nblocks_max = std::max(nblocks_max, bwd_ring_blocks(a0, rv.bwd_wpb));
-  // per-workgroup table partials, then the reduction's slices
-  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes,
-                       sizeof(double) * 4 * (size_t)M * ((size_t)nblocks_max + (size_t)tf_reduce_slices())));
-  double* part = reinterpret_cast<double*>(ctx->d_scratch);
-  double* slices = part + 4 * (size_t)M * (size_t)nblocks_max;
+  // every view's workgroups write their table partials into a region of their
+  // own, so the views can run side by side (a view's tiles differ in ray
+  // length; alone, its launch leaves compute units idle at its tail) and one
+  // fixed-order reduction sums them all
+  std::vector<int64_t> pbase((size_t)st->nviews + 1, 0);
   for (int32_t v = 0; v < st->nviews; v++) {
     const vr_state::View& rv = st->vs[v];
+    pbase[v + 1] = pbase[v] + (rv.ring ? bwd_ring_blocks(a0, rv.bwd_wpb) : bwd_blocks(a0));
+  }
+  const bool side = ctx->bwd_side && st->nviews > 1;
+  int64_t nslots = 1;
+  for (int32_t v = 0; v < st->nviews; v++) nslots = std::max(nslots, pbase[v + 1] - pbase[v]);
+  if (side) nslots = std::max<int64_t>(pbase.back(), 1);
+  VR_TRY(ensure_device(&ctx->d_scratch, &ctx->scratch_bytes,
+                       sizeof(double) * 4 * (size_t)M * ((size_t)nslots + (size_t)tf_reduce_slices())));
+  double* part = reinterpret_cast<double*>(ctx->d_scratch);
+  double* slices = part + 4 * (size_t)M * (size_t)nslots;
+  VR_TRY(stage_begin(ctx, VR_STAGE_BACKWARD, s));
+  if (side) VR_TRY(aux_fork(ctx, s));
+  for (int32_t v = 0; v < st->nviews; v++) {
+    const vr_state::View& rv = st->vs[v];
+    const hipStream_t vs = side ? ctx->aux[v % vr_ctx::kAux] : s;
     MarchArgs a = base;
     make_camera(st->views[v], vol->n, a.cam);
     a.nbv = 1;
@@ -335,27 +347,27 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
     ba.nused = st->d_nused + (int64_t)v * npix;
     ba.gout = reinterpret_cast<const float4*>(grad_out) + (int64_t)v * npix;
     ba.gvol = grad_vol;
-    ba.tf_part = part;
+    ba.tf_part = part + (side ? 4 * (size_t)M * (size_t)pbase[v] : 0);
     ba.vmin = st->vmin;
     ba.inv_range = st->vmax > st->vmin ? 1.0 / (st->vmax - st->vmin) : 0.0;
     ba.K = rv.ring ? rv.L : st->K;
     ba.npix = (int32_t)npix;
     ba.smax = rv.smax;
     ba.flag = st->d_flag;
-    VR_TRY(stage_begin(ctx, VR_STAGE_BACKWARD, s));
-    int nblocks;
     if (rv.ring) {
       a.slab_axis = rv.axis;
       a.ring_slot = rv.slot;
-      VR_HIP(launch_bwd_ring(a, ba, rv.bwd_wpb, s));
-      nblocks = bwd_ring_blocks(a, rv.bwd_wpb);
+      VR_HIP(launch_bwd_ring(a, ba, rv.bwd_wpb, vs));
     } else {
-      VR_HIP(launch_bwd(a, ba, s));
-      nblocks = bwd_blocks(a0);
+      VR_HIP(launch_bwd(a, ba, vs));
     }
-    VR_HIP(launch_tf_reduce(part, nblocks, M * 4, grad_tf, slices, s));
-    VR_TRY(stage_end(ctx, s));
+    if (!side) VR_HIP(launch_tf_reduce(part, (int)(pbase[v + 1] - pbase[v]), M * 4, grad_tf, slices, s));
   }
+  if (side) {
+    VR_TRY(aux_join(ctx, s));
+    VR_HIP(launch_tf_reduce(part, (int)pbase.back(), M * 4, grad_tf, slices, s));
+  }
+  VR_TRY(stage_end(ctx, s));
   VR_TRY(ctx_end(ctx, s));
   // the ring adjoint's bound on the samples of one ray in one checkpoint group
   // holds by construction; a group that exceeded it is reported, not clamped

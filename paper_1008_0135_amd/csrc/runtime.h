@@ -120,6 +120,7 @@ struct vr_ctx {
   double foot_rays = 60.0;    // footprint cells: mean pixels per cell (each holds at most 64 in one pass)
   int32_t foot_pad = 0;       // footprint cells: extra floats per window row (LDS bank spread)
   int32_t foot_kmax = 2;      // footprint cells: window rows of at most this many 128-byte lines
+  int32_t bwd_side = 1;       // adjoint: views side by side on the side streams, one table reduction
   int32_t foot_maxpx = 64;    // footprint cells: pixels of a cell at most, as sized (past 64: marched by gathers)
   int32_t cells_wpb = 0;      // register-staged cells march: wavefronts per workgroup (0: the plan's)
   int32_t foot_block = 0;     // blocks of cells per workgroup: -1 = by cost, 0 = off, 1 = foot_block_f x _g
