@@ -317,7 +317,7 @@ def bench_fwd_bwd(ctx, stream):
     log(f"fwd+bwd: forward {ms_f:.3f} ms, forward+backward {ms_fb:.3f} ms for {len(views)} views of 512^2 "
         f"(backward kernels {ms_b_kernels:.3f} ms; checkpoints every {min(spg):.1f}-{max(spg):.1f} samples)")
     return {"workload": "256x256x512 f32 cube, 8 views at 512x512, colour-ramp table, L2 loss against a "
-                        "perturbed-table target, ckpt_K 32 (checkpoint groups of at most 4 cell layers on the "
+                        "perturbed-table target, ckpt_K 32 (checkpoint groups of at most 3 cell layers on the "
                         "ring layout), gradients to table and voxels",
             "ms_forward": round(ms_f, 4), "ms_forward_backward": round(ms_fb, 4),
             "ms_backward_kernels": round(ms_b_kernels, 4),

@@ -198,7 +198,13 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
   pack_whole(vol, W, H, base.tile_w, base.tile_h, nviews, host, off_bv);
   void* dtab = nullptr;
   int rc = upload_tables(ctx, s, host.data(), host.size(), &dtab);
+  // views write disjoint frames and checkpoints: side by side on the side
+  // streams, as the adjoint runs them
+  const bool side = ctx->bwd_side && nviews > 1;
+  if (rc == VR_OK && side) rc = stage_begin(ctx, VR_STAGE_MARCH, s);
+  if (rc == VR_OK && side) rc = aux_fork(ctx, s);
   for (int32_t v = 0; v < nviews && rc == VR_OK; v++) {
+    const hipStream_t vs = side ? ctx->aux[v % vr_ctx::kAux] : s;
     const vr_state::View& rv = st->vs[v];
     MarchArgs a = base;
     a.cam = cams[v];
@@ -214,20 +220,22 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
     sa.nused = st->d_nused + (int64_t)v * npix;
     sa.K = rv.ring ? rv.L : st->K;
     sa.npix = (int32_t)npix;
-    rc = stage_begin(ctx, VR_STAGE_MARCH, s);
+    if (!side) rc = stage_begin(ctx, VR_STAGE_MARCH, s);
     if (rc == VR_OK) {
       hipError_t e;
       if (rv.ring) {
         a.slab_axis = rv.axis;
         a.ring_slot = rv.slot;
-        e = launch_march_ring_save(a, sa, rv.fwd_wpb, s);
+        e = launch_march_ring_save(a, sa, rv.fwd_wpb, vs);
       } else {
-        e = launch_fwd_save(a, sa, s);
+        e = launch_fwd_save(a, sa, vs);
       }
       if (e != hipSuccess) rc = fail(VR_EHIP, "forward launch: %s", hipGetErrorString(e));
     }
-    if (rc == VR_OK) rc = stage_end(ctx, s);
+    if (rc == VR_OK && !side) rc = stage_end(ctx, s);
   }
+  if (rc == VR_OK && side) rc = aux_join(ctx, s);
+  if (rc == VR_OK && side) rc = stage_end(ctx, s);
   if (rc == VR_OK) rc = ctx_end(ctx, s);
   if (rc != VR_OK) {
     vr_state_destroy(st);

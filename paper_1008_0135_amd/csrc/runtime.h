@@ -109,7 +109,7 @@ struct vr_ctx {
   // 2 = LDS-staged slabs (else gather); 3 = same as 0
   int32_t march_mode = 0;
   int32_t lds_budget = 4096;  // floats of LDS for one slab's voxel box
-  int32_t bwd_layer_cap = 4;  // adjoint on the ring layout: cell layers per checkpoint group, at most
+  int32_t bwd_layer_cap = 3;  // adjoint on the ring layout: cell layers per checkpoint group, at most
   // ring march: tiles of a brick numbered along rows (0), down columns (1) or in
   // blocks of tile_bw x tile_bh tiles (2)
   int32_t tile_order = 2, tile_bw = 2, tile_bh = 4;
@@ -120,7 +120,7 @@ struct vr_ctx {
   double foot_rays = 60.0;    // footprint cells: mean pixels per cell (each holds at most 64 in one pass)
   int32_t foot_pad = 0;       // footprint cells: extra floats per window row (LDS bank spread)
   int32_t foot_kmax = 2;      // footprint cells: window rows of at most this many 128-byte lines
-  int32_t bwd_side = 1;       // adjoint: views side by side on the side streams, one table reduction
+  int32_t bwd_side = 1;       // differentiable pair: views side by side on the side streams (one table reduction)
   int32_t foot_maxpx = 64;    // footprint cells: pixels of a cell at most, as sized (past 64: marched by gathers)
   int32_t cells_wpb = 0;      // register-staged cells march: wavefronts per workgroup (0: the plan's)
   int32_t foot_block = 0;     // blocks of cells per workgroup: -1 = by cost, 0 = off, 1 = foot_block_f x _g

@@ -219,7 +219,7 @@ def test_c5_full_size_two_views(ctx):
 
 def test_checkpoint_interval_follows_ckpt_K(ctx):
     """The planned checkpoint group follows ckpt_K: L = round(K step |d_b|) cell layers,
-    capped at 4, so the interval is min(K, about 4 / (step |d_b|)) samples; gradients
+    capped at 3, so the interval is min(K, about 3 / (step |d_b|)) samples; gradients
     agree across intervals (the exact derivative does not depend on where the
     recomputation restarts)."""
     vol, tf, vmin, vmax = _case(seed=51)
@@ -240,7 +240,7 @@ def test_checkpoint_interval_follows_ckpt_K(ctx):
         d = np.abs(np.asarray(R, np.float64)[2])
         db = L / (0.5 * spg)  # |d_b| of the slab axis the plan took: axis 2 or 3
         assert min(abs(db - d[1]), abs(db - d[2])) <= 1e-9, (db, d)
-        want = max(1, min(4, int(np.floor(K * 0.5 * db + 0.5))))
+        want = max(1, min(3, int(np.floor(K * 0.5 * db + 0.5))))
         assert L == want, (K, L, want)
         assert spg <= K + 1.0 / db + 1e-9, (K, L, spg)
         _say(f"ckpt_K {K}: {L} cell layers per group, {spg:.2f} samples per checkpoint")
