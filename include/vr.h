@@ -336,11 +336,13 @@ int vr_composite(vr_ctx *ctx, const vr_brick_image *imgs, int32_t n, const int32
  * forward from its saved transmittance checkpoint.  ckpt_K bounds a stretch:
  * on the ring-window layout (the default where its windows fit) a stretch is
  * a group of L cell layers of the ray's 8 x 8 tile, L = round(ckpt_K step
- * |d_b|) capped at 4 layers (the environment variable VR_BWD_LAYERS sets the
+ * |d_b|) capped at 3 layers (the environment variable VR_BWD_LAYERS sets the
  * cap, 1 to 16: longer groups need more LDS per wavefront), so a checkpoint
- * falls every min(ckpt_K, about 4 / (step |d_b|)) samples (vr_state_info
+ * falls every min(ckpt_K, about 3 / (step |d_b|)) samples (vr_state_info
  * reports it per view); otherwise a stretch is a segment of exactly ckpt_K
- * samples.  Synchronises with `stream` at the end (it checks the adjoint's
+ * samples.  Views run side by side on the library's side streams (forked from
+ * and joined back to `stream`; VR_BWD_SIDE=0 runs them one after another).
+ * Synchronises with `stream` at the end (it checks the adjoint's
  * per-group sample bound).
  * Errors: VR_EINVAL, VR_ESTATE (state from another volume, or the transfer
  * function changed since the forward), VR_EHIP (also a group beyond its
