@@ -399,6 +399,7 @@ int vr_create(int device, vr_ctx** out) {
     const int k = std::atoi(m);
     if (k >= 1 && k <= 16) ctx->bwd_layer_cap = k;
   }
+  if (const char* m = std::getenv("VR_BWD_BANDS")) ctx->bwd_bands = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_BWD_SIDE")) ctx->bwd_side = std::atoi(m) != 0 ? 1 : 0;
   if (const char* m = std::getenv("VR_MARCH"))
     ctx->march_mode = std::strcmp(m, "gather") == 0 ? 1 : std::strcmp(m, "slab") == 0 ? 2 : std::strcmp(m, "ring") == 0 ? 3 : 0;

@@ -27,6 +27,7 @@ struct vr_state {
     bool ring = false;
     int32_t axis = 0, slot = 0, fwd_wpb = 4, bwd_wpb = 1, L = 0, smax = 0, ngrp = 0;
     int64_t off = 0;  // offset of this view's checkpoints (floats / ints) in d_ckpt / d_ckpt_j
+    int32_t band[9] = {};  // ring adjoint: tile groups per XCD (all zero: equal counts)
   };
   std::vector<View> vs;
   float* d_ckpt = nullptr;     // checkpoints, all views
@@ -67,6 +68,42 @@ void pack_whole(const vr_volume* vol, int32_t W, int32_t H, int32_t tw, int32_t 
 }
 
 int ntiles_of(int32_t W, int32_t H, int32_t tw, int32_t th) { return ((W + tw - 1) / tw) * ((H + th - 1) / th); }
+
+// The ring adjoint's tile groups (wpb consecutive 8 x 8 tiles) in 8 contiguous
+// bands of about equal work, one per XCD: a tile costs a fixed set-up plus the
+// samples of its longest ray, taken as the longest of its four corner rays
+// through the volume (the walk runs in lockstep over the tile's rays).  Equal
+// counts of groups leave the XCDs holding the image's border idle while those
+// holding its middle, where rays are longest, still work.
+void xcd_bands(const Camera& cam, const double hi[3], double step, int32_t W, int32_t H, int wpb, int32_t band[9]) {
+  const int tx_n = (W + 7) / 8, ty_n = (H + 7) / 8, nt = tx_n * ty_n;
+  const int ng = (nt + wpb - 1) / wpb;
+  // samples of the rays through the tile corners, on the (tx_n + 1) x (ty_n + 1) grid
+  std::vector<int64_t> cn((size_t)(tx_n + 1) * (ty_n + 1), 0);
+  for (int cy = 0; cy <= ty_n; cy++)
+    for (int cx = 0; cx <= tx_n; cx++) {
+      double o[3], tin;
+      int64_t n = 0;
+      pixel_origin(cam, std::min(cx * 8, W - 1), std::min(cy * 8, H - 1), o);
+      if (ray_lattice(o, cam.e3, hi, step, tin, n)) cn[(size_t)cy * (tx_n + 1) + cx] = n;
+    }
+  std::vector<double> pre((size_t)ng + 1, 0.0);
+  for (int g = 0; g < ng; g++) {
+    double c = 0.0;
+    for (int t = g * wpb; t < std::min(nt, (g + 1) * wpb); t++) {
+      const size_t i = (size_t)(t / tx_n) * (tx_n + 1) + (size_t)(t % tx_n);
+      c += 32.0 + (double)std::max(std::max(cn[i], cn[i + 1]), std::max(cn[i + tx_n + 1], cn[i + tx_n + 2]));
+    }
+    pre[g + 1] = pre[g] + c;
+  }
+  band[0] = 0;
+  for (int x = 1; x < 8; x++) {
+    const double target = pre[ng] * (double)x / 8.0;
+    const int b = (int)(std::lower_bound(pre.begin(), pre.end(), target) - pre.begin());
+    band[x] = std::max(band[x - 1], std::min(b, ng));
+  }
+  band[8] = ng;
+}
 
 // Ring layout for the differentiable pair of one view: slab axis, window slot,
 // forward launch shape, cell layers per checkpoint group (about K samples),
@@ -236,6 +273,10 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
   }
   if (rc == VR_OK && side) rc = aux_join(ctx, s);
   if (rc == VR_OK && side) rc = stage_end(ctx, s);
+  // the adjoint's XCD bands, planned on the host while the forward runs
+  if (rc == VR_OK && ctx->bwd_bands)
+    for (int32_t v = 0; v < nviews; v++)
+      if (st->vs[v].ring) xcd_bands(cams[v], base.hi, p->step, W, H, st->vs[v].bwd_wpb, st->vs[v].band);
   if (rc == VR_OK) rc = ctx_end(ctx, s);
   if (rc != VR_OK) {
     vr_state_destroy(st);
@@ -327,7 +368,10 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
   std::vector<int64_t> pbase((size_t)st->nviews + 1, 0);
   for (int32_t v = 0; v < st->nviews; v++) {
     const vr_state::View& rv = st->vs[v];
-    pbase[v + 1] = pbase[v] + (rv.ring ? bwd_ring_blocks(a0, rv.bwd_wpb) : bwd_blocks(a0));
+    BwdArgs bb;
+    std::memset(&bb, 0, sizeof bb);
+    std::memcpy(bb.band, rv.band, sizeof bb.band);
+    pbase[v + 1] = pbase[v] + (rv.ring ? bwd_ring_blocks(a0, bb, rv.bwd_wpb) : bwd_blocks(a0));
   }
   const bool side = ctx->bwd_side && st->nviews > 1;
   int64_t nslots = 1;
@@ -361,6 +405,7 @@ int vr_render_backward(vr_ctx* ctx, const vr_volume* vol, const vr_state* st, co
     ba.K = rv.ring ? rv.L : st->K;
     ba.npix = (int32_t)npix;
     ba.smax = rv.smax;
+    std::memcpy(ba.band, rv.band, sizeof ba.band);
     ba.flag = st->d_flag;
     if (rv.ring) {
       a.slab_axis = rv.axis;

@@ -25,6 +25,8 @@
 // recursion and the gradient algebra in double precision.  A tile whose window would not
 // fit reads its corners from global memory and adds its voxel gradients with
 // global atomics directly (same groups, same arithmetic).
+#include <algorithm>
+
 #include "ring_common.h"
 #include "sample.h"
 #include "vr_internal.h"
@@ -116,8 +118,14 @@ __global__ __launch_bounds__(256) void k_bwd_ring(MarchArgs a, BwdArgs ba) {
 
   // same tile order as the forward
   const int ngroups_b = (a.ntiles + wpb - 1) / wpb;
-  const int per = (ngroups_b + 7) >> 3;
-  const int tile = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * wpb + wave;
+  int grp;
+  if (ba.band[8] > 0) {
+    const int x = (int)(blockIdx.x & 7), g = ba.band[x] + (int)(blockIdx.x >> 3);
+    grp = g < ba.band[x + 1] ? g : ngroups_b;
+  } else {
+    grp = (int)(blockIdx.x & 7) * ((ngroups_b + 7) >> 3) + (int)(blockIdx.x >> 3);
+  }
+  const int tile = grp < ngroups_b ? grp * wpb + wave : a.ntiles;
   const bool tile_on = tile < a.ntiles;
   // every wavefront reaches the workgroup barrier at the end, so the work
   // sits inside `if (tile_on)` rather than behind an early return
@@ -446,8 +454,13 @@ size_t bwd_ring_lds_bytes(const MarchArgs& a, const BwdArgs& ba, int wpb) {
   return sizeof(double) * 4 * (size_t)a.M + sizeof(float4) * (size_t)a.M + sizeof(float) * wpb * per_wave;
 }
 
-int bwd_ring_blocks(const MarchArgs& a, int wpb) {
+int bwd_ring_blocks(const MarchArgs& a, const BwdArgs& ba, int wpb) {
   if (a.ntiles <= 0) return 0;
+  if (ba.band[8] > 0) {
+    int widest = 0;
+    for (int x = 0; x < 8; x++) widest = std::max(widest, ba.band[x + 1] - ba.band[x]);
+    return 8 * widest;
+  }
   const int groups = (a.ntiles + wpb - 1) / wpb;
   return ((groups + 7) / 8) * 8;
 }
@@ -466,7 +479,7 @@ hipError_t launch_bwd_ring(const MarchArgs& a, const BwdArgs& ba, int wpb, hipSt
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_bwd_ring, dim3(bwd_ring_blocks(a, wpb)), dim3(64 * wpb), lds, s, a, ba);
+  hipLaunchKernelGGL(k_bwd_ring, dim3(bwd_ring_blocks(a, ba, wpb)), dim3(64 * wpb), lds, s, a, ba);
   return hipGetLastError();
 }
 

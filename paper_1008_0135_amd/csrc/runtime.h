@@ -120,6 +120,7 @@ struct vr_ctx {
   double foot_rays = 60.0;    // footprint cells: mean pixels per cell (each holds at most 64 in one pass)
   int32_t foot_pad = 0;       // footprint cells: extra floats per window row (LDS bank spread)
   int32_t foot_kmax = 2;      // footprint cells: window rows of at most this many 128-byte lines
+  int32_t bwd_bands = 1;      // ring adjoint: tile groups in XCD bands of equal estimated work (0: equal counts)
   int32_t bwd_side = 1;       // differentiable pair: views side by side on the side streams (one table reduction)
   int32_t foot_maxpx = 64;    // footprint cells: pixels of a cell at most, as sized (past 64: marched by gathers)
   int32_t cells_wpb = 0;      // register-staged cells march: wavefronts per workgroup (0: the plan's)

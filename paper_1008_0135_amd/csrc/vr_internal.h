@@ -309,7 +309,10 @@ struct BwdArgs {
   int32_t K;          // samples per segment, or cell layers per group
   int32_t npix;
   int32_t smax;       // layer groups: samples of one ray in one group, at most
-  int32_t pad;
+  // ring adjoint: tile groups of XCD x (workgroup b runs on XCD b % 8 and takes
+  // group band[x] + b / 8 while below band[x + 1]); contiguous bands of equal
+  // estimated work.  band[8] == 0: equal counts of groups
+  int32_t band[9];
   int32_t* flag;      // set to 1 when a ray's group held more than smax samples
 };
 
@@ -367,7 +370,7 @@ hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wp
 // Adjoint on the ring layout (grad_ring.hip): layer groups of ba.K cell layers.
 hipError_t launch_bwd_ring(const MarchArgs& a, const BwdArgs& ba, int wpb, hipStream_t s);
 size_t bwd_ring_lds_bytes(const MarchArgs& a, const BwdArgs& ba, int wpb);
-int bwd_ring_blocks(const MarchArgs& a, int wpb);
+int bwd_ring_blocks(const MarchArgs& a, const BwdArgs& ba, int wpb);
 hipError_t launch_march_lds(const MarchArgs& a, hipStream_t s);
 hipError_t launch_composite(const CompArgs& a, hipStream_t s);
 hipError_t launch_minmax(const float* x, int64_t n, float* partial, int32_t nblocks, hipStream_t s);
