@@ -69,17 +69,13 @@ void pack_whole(const vr_volume* vol, int32_t W, int32_t H, int32_t tw, int32_t 
 
 int ntiles_of(int32_t W, int32_t H, int32_t tw, int32_t th) { return ((W + tw - 1) / tw) * ((H + th - 1) / th); }
 
-// The ring adjoint's tile groups (wpb consecutive 8 x 8 tiles) in 8 contiguous
-// bands of about equal work, one per XCD: a tile costs a fixed set-up plus the
-// samples of its longest ray, taken as the longest of its four corner rays
-// through the volume (the walk runs in lockstep over the tile's rays).  Equal
-// counts of groups leave the XCDs holding the image's border idle while those
-// holding its middle, where rays are longest, still work.
-void xcd_bands(const Camera& cam, const double hi[3], double step, int32_t W, int32_t H, int wpb, int32_t band[9]) {
-  const int tx_n = (W + 7) / 8, ty_n = (H + 7) / 8, nt = tx_n * ty_n;
-  const int ng = (nt + wpb - 1) / wpb;
-  // samples of the rays through the tile corners, on the (tx_n + 1) x (ty_n + 1) grid
-  std::vector<int64_t> cn((size_t)(tx_n + 1) * (ty_n + 1), 0);
+// Estimated work of each 8 x 8 tile of a whole-volume view, for splitting a
+// ring march's tile groups into XCD bands: a fixed set-up plus the samples of
+// the tile's longest ray, taken as the longest of its four corner rays through
+// the volume (a wavefront walks its tile's rays in lockstep).
+std::vector<double> tile_costs(const Camera& cam, const double hi[3], double step, int32_t W, int32_t H) {
+  const int tx_n = (W + 7) / 8, ty_n = (H + 7) / 8;
+  std::vector<int64_t> cn((size_t)(tx_n + 1) * (ty_n + 1), 0);  // samples of the corner rays
   for (int cy = 0; cy <= ty_n; cy++)
     for (int cx = 0; cx <= tx_n; cx++) {
       double o[3], tin;
@@ -87,13 +83,24 @@ void xcd_bands(const Camera& cam, const double hi[3], double step, int32_t W, in
       pixel_origin(cam, std::min(cx * 8, W - 1), std::min(cy * 8, H - 1), o);
       if (ray_lattice(o, cam.e3, hi, step, tin, n)) cn[(size_t)cy * (tx_n + 1) + cx] = n;
     }
+  std::vector<double> c((size_t)tx_n * ty_n);
+  for (int t = 0; t < tx_n * ty_n; t++) {
+    const size_t i = (size_t)(t / tx_n) * (tx_n + 1) + (size_t)(t % tx_n);
+    c[(size_t)t] = 32.0 + (double)std::max(std::max(cn[i], cn[i + 1]), std::max(cn[i + tx_n + 1], cn[i + tx_n + 2]));
+  }
+  return c;
+}
+
+// Tile groups (wpb consecutive tiles) in 8 contiguous bands of about equal
+// work, one per XCD.  Equal counts of groups leave the XCDs holding the
+// image's border idle while those holding its middle, where rays are
+// longest, still work.
+void xcd_bands(const std::vector<double>& cost, int wpb, int32_t band[9]) {
+  const int nt = (int)cost.size(), ng = (nt + wpb - 1) / wpb;
   std::vector<double> pre((size_t)ng + 1, 0.0);
   for (int g = 0; g < ng; g++) {
     double c = 0.0;
-    for (int t = g * wpb; t < std::min(nt, (g + 1) * wpb); t++) {
-      const size_t i = (size_t)(t / tx_n) * (tx_n + 1) + (size_t)(t % tx_n);
-      c += 32.0 + (double)std::max(std::max(cn[i], cn[i + 1]), std::max(cn[i + tx_n + 1], cn[i + tx_n + 2]));
-    }
+    for (int t = g * wpb; t < std::min(nt, (g + 1) * wpb); t++) c += cost[(size_t)t];
     pre[g + 1] = pre[g] + c;
   }
   band[0] = 0;
@@ -257,6 +264,13 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
     sa.nused = st->d_nused + (int64_t)v * npix;
     sa.K = rv.ring ? rv.L : st->K;
     sa.npix = (int32_t)npix;
+    if (rv.ring && ctx->bwd_bands) {
+      // XCD bands of this view's forward and adjoint (the host plans view v
+      // while the GPU marches view v - 1)
+      const std::vector<double> cost = tile_costs(cams[v], base.hi, p->step, W, H);
+      xcd_bands(cost, rv.fwd_wpb, sa.band);
+      xcd_bands(cost, rv.bwd_wpb, st->vs[v].band);
+    }
     if (!side) rc = stage_begin(ctx, VR_STAGE_MARCH, s);
     if (rc == VR_OK) {
       hipError_t e;
@@ -273,10 +287,6 @@ int render_with_state(vr_ctx* ctx, vr_volume* vol, const vr_view* views, int32_t
   }
   if (rc == VR_OK && side) rc = aux_join(ctx, s);
   if (rc == VR_OK && side) rc = stage_end(ctx, s);
-  // the adjoint's XCD bands, planned on the host while the forward runs
-  if (rc == VR_OK && ctx->bwd_bands)
-    for (int32_t v = 0; v < nviews; v++)
-      if (st->vs[v].ring) xcd_bands(cams[v], base.hi, p->step, W, H, st->vs[v].bwd_wpb, st->vs[v].band);
   if (rc == VR_OK) rc = ctx_end(ctx, s);
   if (rc != VR_OK) {
     vr_state_destroy(st);

@@ -83,7 +83,13 @@ __global__ __launch_bounds__(256) void k_march_ring(MarchArgs a, SaveArgs sa) {
   // contiguous range of tiles so that neighbouring tiles share its L2
   const int ngroups = (a.ntiles + wpb - 1) / wpb;
   const int per = (ngroups + 7) >> 3;
-  const int tile = ((int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3)) * wpb + wave;
+  int grp = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (SAVE && sa.band[8] > 0) {
+    // the checkpointing forward: bands of equal estimated work per XCD
+    const int x = (int)(blockIdx.x & 7), g = sa.band[x] + (int)(blockIdx.x >> 3);
+    grp = g < sa.band[x + 1] ? g : ngroups;
+  }
+  const int tile = grp * wpb + wave;
   if (tile >= a.ntiles) return;
 
   int lo = 0, hi = a.nbv - 1;
@@ -882,7 +888,12 @@ hipError_t launch_march_ring_save(const MarchArgs& a, const SaveArgs& sa, int wp
       a.mc != 0 || a.mip != 0 || a.cam.persp != 0 || a.ring_nslots == 2 || sa.K < 1 || !sa.ckpt_j)
     return hipErrorInvalidValue;
   const int groups = (a.ntiles + wpb - 1) / wpb;
-  const int grid = ((groups + 7) / 8) * 8;
+  int grid = ((groups + 7) / 8) * 8;
+  if (sa.band[8] > 0) {
+    int widest = 0;
+    for (int x = 0; x < 8; x++) widest = std::max(widest, sa.band[x + 1] - sa.band[x]);
+    grid = 8 * widest;
+  }
   hipLaunchKernelGGL((k_march_ring<false, true, false, false>), dim3(grid), dim3(64 * wpb), ring_lds_bytes(a, wpb), s, a, sa);
   return hipGetLastError();
 }

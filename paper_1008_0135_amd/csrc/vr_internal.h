@@ -296,6 +296,7 @@ struct SaveArgs {
   int32_t* nused;     // samples applied per ray (early termination included)
   int32_t K;          // samples per segment, or cell layers per group
   int32_t npix;       // W * H
+  int32_t band[9];    // ring march: tile groups per XCD, as BwdArgs::band (band[8] == 0: equal counts)
 };
 
 struct BwdArgs {
