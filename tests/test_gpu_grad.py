@@ -254,3 +254,50 @@ def test_checkpoint_interval_follows_ckpt_K(ctx):
         assert _rel(grads[K][0], grads[32][0]).max() <= 1e-4
         assert _rel(grads[K][1], grads[32][1]).max() <= 1e-4
     vr.vr_volume_destroy(h)
+
+
+def _ctx_with_env(env):
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return vr.vr_create(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
+def test_adjoint_schedules_agree():
+    """The differentiable pair's schedules (views side by side or one after
+    another; tile groups in XCD bands of equal estimated work or equal counts)
+    march the same tiles with the same arithmetic: the checkpointing forward's
+    images are bit-identical and the gradients differ only by the order of
+    their atomic and partial sums."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = synth.CONFIGS["C5"]
+    vol = synth.config_cube("C5")
+    tf = synth.tf_colour(256)
+    vmin, vmax = float(vol.min()) - 0.5, float(vol.max()) + 0.5
+    views = synth.random_views(c["nviews"], c["view_seed"])[:5]
+    W, H = c["image"]
+    gout = np.random.Generator(np.random.PCG64(71)).normal(0, 1, (len(views), H, W, 4)).astype(np.float32)
+    res = {}
+    for name, env in (("default", {}), ("in turn", {"VR_BWD_SIDE": "0"}), ("equal counts", {"VR_BWD_BANDS": "0"}),
+                      ("both off", {"VR_BWD_SIDE": "0", "VR_BWD_BANDS": "0"})):
+        _say(f"C5 volume, {len(views)} views at 512^2, schedule: {name}")
+        cx = _ctx_with_env(env)
+        try:
+            res[name] = _gpu_grad(cx, vol, tf, views, W, H, vmin, vmax, gout)
+        finally:
+            vr.vr_destroy(cx)
+    img0, plain0, gtf0, gvol0 = res["default"]
+    for name, (img, plain, gtf, gvol) in res.items():
+        assert np.array_equal(img, img0), name
+        assert np.array_equal(plain, plain0), name
+        r_tf, r_vol = _rel(gtf, gtf0), _rel(gvol, gvol0)
+        _say(f"{name}: max rel difference tf {r_tf.max():.3g}, voxels {r_vol.max():.3g}")
+        assert r_tf.max() <= 1e-5 and r_vol.max() <= 3e-4, name
